@@ -1,0 +1,115 @@
+"""Benchmark of the shift-and-stack search on one MI355X.
+
+One step = one sst_detect call over the full synthetic field (64 frames of
+1024x1024 float32, an 81x81 grid of trial velocities at 1 px/h, S/N 5 cut,
+top-64 candidates per velocity): frame statistics, padded background-
+subtracted copy, coverage intervals, the stacking kernel with S/N and peak
+extraction, and the per-velocity merge.  Frames are resident in HBM before the
+timed region.  The metric is frame*pixel*velocity updates per second
+(N*H*W*N_vel per step / step time).
+
+The JSON line also carries the roofline position of the dominant kernel
+(the stacking kernel, timed with HIP events on its launch stream inside the
+library) and the float64 CPU oracle timed on a bounded sample of the same
+workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X FP32 vector issue rate for adds: 256 CUs x 4 SIMDs x 16 lanes x 2
+# (packed) x 2.4 GHz = 78.6 T adds/s (the 157.3 TFLOP/s FP32 figure counts an
+# FMA as two flops).
+PEAK_FP32_ADD_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(f, n_vel: int, seed: int = 0):
+    import oracle
+    rng = np.random.default_rng(seed)
+    nk = len(f.vx) * len(f.vy)
+    ks = sorted(rng.choice(nk, size=n_vel, replace=False).tolist())
+    t0 = time.perf_counter()
+    oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, velocities=ks)
+    dt = time.perf_counter() - t0
+    ups = n_vel * f.n * f.h * f.w / dt
+    return {"value": ups, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_vel} of {nk} velocities of the same field (all {f.n} frames of {f.w}x{f.h}), "
+                      f"numpy float64 oracle incl. frame statistics, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["full", "tiny"], default="full")
+    ap.add_argument("--cpu-velocities", type=int, default=32, help="oracle sample size (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the search shards by field or velocity block with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2303_07293_amd as sst
+
+    f = synth.config2() if args.workload == "full" else synth.config1()
+    dev = torch.device("cuda:0")
+    frames = torch.from_numpy(f.frames).to(dev)
+    n, h, w = f.frames.shape
+    nk = len(f.vx) * len(f.vy)
+    nb = sst.sst_workspace_bytes(sst.SST_OP_DETECT, n, h, w, f.t, f.t_ref, f.vx, f.vy, f.k_max)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    cand = torch.empty((nk, f.k_max, 8), dtype=torch.int32, device=dev)
+    count = torch.empty((nk,), dtype=torch.int32, device=dev)
+
+    def step():
+        sst.sst_detect(frames, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max,
+                       ws=ws, cand=cand, count=count)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sst.sst_profile_begin()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = sst.sst_profile_end()
+
+    updates = f.updates
+    ms_step = dt * 1e3 / args.steps
+    value = updates / (dt / args.steps)
+    kern_ms_step = kern_ms / args.steps
+    achieved = updates / (kern_ms_step * 1e-3) / 1e12  # TFLOP/s at one FP32 add per update
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_ADD_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_ADD_TFLOPS, 4), "traffic": None,
+            "kernel": "k_stack<detect>", "kernel_ms_per_step": round(kern_ms_step, 4),
+            "launches_per_step": launches / args.steps}
+    out = {
+        "metric": "frame*pixel*velocity updates/s", "value": value, "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f.name, "frames": n, "height": h, "width": w, "velocities": nk,
+                   "threshold": f.threshold, "k_max": f.k_max, "candidates_last_step": int(count.sum().item())},
+        "roofline": roof,
+    }
+    if args.cpu_velocities > 0:
+        out["cpu_baseline"] = cpu_baseline(f, args.cpu_velocities)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,153 @@
+/*
+ * sst.h -- C ABI of the shift-and-stack search for moving sources
+ * ("synthetic tracking", Burdanov, Hasler & de Wit, MNRAS 2023,
+ * arXiv:2303.07293), implemented with HIP kernels for AMD gfx950.
+ *
+ * The search (paper Sec. 1 and Sec. 2.1): stationary sources are removed
+ * (here: each frame's mean is subtracted), linear motion is assumed with no
+ * prior on position angle, each frame is shifted along a trial motion and the
+ * frames are summed; tracks come back with their velocity, pixel coordinates
+ * and S/N (Sec. 2.1).  Concretely, for a trial velocity v = (vx[a], vy[b]) in
+ * px per time unit, frame i is sampled at integer offset
+ *     d_i = llround(v * (t[i] - t_ref))      (round half away from zero)
+ * and, for every pixel p of the w x h grid at t_ref,
+ *     S'(p) = sum over in-frame samples, in ascending i, of F_i(p + d_i) - b_i
+ *     c(p)  = number of in-frame samples     V(p) = sum of s2_i over them
+ *     SN(p) = S'(p) / sqrt(V(p))   (-inf where c = 0, 0 where V = 0)
+ * with b_i, s2_i the mean and population variance of frame i.  A candidate is
+ * a pixel with c >= min_coverage, SN > threshold, whose key (SN, -raster
+ * index) beats all in-grid 8-neighbours.  Where the paper is silent these
+ * are readings: t_ref is an argument, shifts round half away from zero,
+ * out-of-frame samples add nothing, the background is the frame mean and the
+ * S/N is per pixel with no matched filter.
+ *
+ * Conventions for every entry point:
+ *  - Memory: "dev" pointers are device memory of the current HIP device,
+ *    "host" pointers are host memory.  The caller owns every buffer; the
+ *    library keeps no per-call state and allocates no device memory (all
+ *    scratch space is the caller's workspace `ws`).
+ *  - Layout: frames are C-contiguous [n][h][w]; velocity index k = b*nvx + a
+ *    (vy major); stacks are [nvy][nvx][h][w].
+ *  - Streams: work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *    stream) and the call returns after enqueueing, except where noted.
+ *  - Errors: a negative SST_E_* code is returned and sst_last_error() gives
+ *    a message.  All argument checks happen on the host before any device
+ *    work is enqueued; a failed check enqueues nothing.
+ *  - Time and velocity units are the caller's (hours and px/h in the
+ *    examples); t must be strictly increasing and finite.
+ */
+#ifndef SST_H
+#define SST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SST_OK 0
+#define SST_E_ARG (-1)         /* null pointer, bad size, bad enum, NaN */
+#define SST_E_UNSORTED (-2)    /* timestamps not strictly increasing */
+#define SST_E_RANGE (-3)       /* a shift or size beyond the supported range */
+#define SST_E_WORKSPACE (-4)   /* workspace missing or too small */
+#define SST_E_DEVICE (-5)      /* a HIP runtime call failed */
+#define SST_E_UNSUPPORTED (-6) /* valid request this build does not handle */
+
+/* frame storage types */
+#define SST_F32 0
+#define SST_BF16 1
+#define SST_F16 2
+
+/* operations (for sst_workspace_bytes) */
+#define SST_OP_STACK 0
+#define SST_OP_DETECT 1
+#define SST_OP_STATS 2
+
+/* plain-stack modes */
+#define SST_SUM 0
+#define SST_MEAN 1
+
+/* One detection (paper Sec. 2.1: a track with its motion, pixel coordinates
+ * and S/N).  32 bytes. */
+typedef struct sst_candidate {
+    int32_t ivx, ivy; /* indices into vx[], vy[] */
+    int32_t x, y;     /* pixel on the frame grid at t_ref */
+    float snr;        /* S'/sqrt(V) */
+    float flux;       /* S': background-subtracted stacked flux */
+    int32_t coverage; /* number of frames whose sample fell inside the frame */
+    int32_t rank;     /* 0-based position in this velocity's list; -1 = unused slot */
+} sst_candidate;
+
+/* Integer shift table (host only, no device work).
+ * out[i*nv + a] = llround(v[a] * (t[i] - t_ref)), one double product, no FMA.
+ * t: host [n] strictly increasing; v: host [nv]; out: host [n][nv].
+ * Errors: SST_E_ARG, SST_E_UNSORTED, SST_E_RANGE (|shift| >= 2^30). */
+int sst_shift_table(const double* t, int n, double t_ref, const double* v, int nv, int32_t* out);
+
+/* Bytes of device workspace an operation needs for this problem (0 on error,
+ * with sst_last_error set).  op = SST_OP_STACK, SST_OP_DETECT or SST_OP_STATS;
+ * the shift tables enter because the zero-padded frame copy is sized by the
+ * largest shift.  k_max is used by SST_OP_DETECT only. */
+size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double t_ref,
+                           const double* vx, int nvx, const double* vy, int nvy, int k_max);
+
+/* Per-frame statistics (the S/N normaliser's inputs): stats[2i] = mean of
+ * frame i, stats[2i+1] = population variance, both float64, dev [n][2].
+ * frames: dev [n][h][w] of `dtype`; scale: dev [n] per-frame multiplier for
+ * SST_BF16/SST_F16 storage (frame value = scale[i] * stored value), NULL for
+ * SST_F32.  ws: dev, >= sst_workspace_bytes(SST_OP_STATS, ...). */
+int sst_frame_stats(const void* frames, int dtype, const float* scale, int n, int h, int w,
+                    double* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* Plain shift-and-stack of every trial velocity (paper Sec. 2.1).
+ * out: dev float32 [nvy][nvx][h][w]:
+ *   SST_SUM : sum over in-frame samples of (F_i(p + d_i) - bg[i])
+ *   SST_MEAN: that sum / c(p), 0 where c(p) = 0
+ * bg: host [n] per-frame values to subtract, or NULL for none.
+ * cov: dev int32 [nvy][nvx][h][w] receiving c(p), or NULL.
+ * t, vx, vy: host.  Asynchronous on `stream`. */
+int sst_stack(const void* frames, int dtype, const float* scale, int n, int h, int w,
+              const double* t, double t_ref, const double* vx, int nvx, const double* vy, int nvy,
+              const double* bg, int mode, float* out, int32_t* cov,
+              void* ws, size_t ws_bytes, void* stream);
+
+/* Shift-and-stack + S/N + peak extraction with per-velocity candidate lists.
+ * cand: dev [nvy*nvx][k_max]; list k holds min(count[k], k_max) candidates
+ *   sorted by (SN descending, raster index ascending); unused slots have
+ *   rank = -1.
+ * count: dev int32 [nvy*nvx], number of candidates before truncation.
+ * threshold: S/N cut (strict >); min_coverage <= 0 means ceil(n/2) (the
+ *   paper's pipeline only finds a mover seen in half or more of a group's
+ *   frames, Sec. 2.1).
+ * k_max in [1, 1024].  frame_stats: host [n][2] receiving each frame's mean
+ *   and variance, or NULL; when non-NULL the call waits for the stream.
+ * Asynchronous on `stream` otherwise. */
+int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, int w,
+               const double* t, double t_ref, const double* vx, int nvx, const double* vy, int nvy,
+               float threshold, int min_coverage, int k_max,
+               sst_candidate* cand, int32_t* count, double* frame_stats,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel timing for measurements.  Between sst_profile_begin() and
+ * sst_profile_end(), every launch of the stacking kernel (the dominant cost
+ * of sst_stack and sst_detect) is bracketed by HIP events recorded on the
+ * launch stream.  sst_profile_end waits for those events and returns the
+ * summed kernel time in milliseconds and the number of launches (either
+ * pointer may be NULL).  Process-wide state: do not overlap profiled calls
+ * from several host threads.  Errors: SST_E_DEVICE, SST_E_RANGE (more than
+ * 4096 launches in one profiled interval). */
+int sst_profile_begin(void);
+int sst_profile_end(double* stack_ms, int* stack_launches);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* sst_last_error(void);
+
+/* Library version string. */
+const char* sst_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SST_H */

@@ -10,9 +10,9 @@ values), written from the paper's statement of the method:
 * Sec. 1 and Sec. 2.1: stationary sources removed, linear motion assumed with
   no constraint on position angle, each frame shifted according to the trial
   motion and the frames summed ("shift and stack" / synthetic tracking);
-* Sec. 2.1: a track is reported with its speed, position angle, pixel
-  coordinates and S/N; the minimum useful shift is half a pixel; a mover must
-  be above threshold for at least half of the frames of a group.
+* Sec. 2.1: each track comes back with its motion, pixel position and S/N;
+  trial motions are spaced by about half a pixel of shift; the pipeline only
+  finds movers that show in half or more of a group's frames.
 
 The readings taken where the paper is silent are listed in `sst_oracle.py`.
 """

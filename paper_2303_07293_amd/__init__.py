@@ -1,0 +1,30 @@
+"""Shift-and-stack search for moving sources ("synthetic tracking",
+arXiv:2303.07293) on AMD MI355X: HIP kernels for gfx950 behind a small C ABI
+(include/sst.h), bound here with ctypes.
+
+    from paper_2303_07293_amd import sst_detect, sst_stack, candidates_to_numpy
+"""
+
+from .binding import (  # noqa: F401
+    CANDIDATE_DTYPE,
+    EXPORTS,
+    SST_BF16,
+    SST_F16,
+    SST_F32,
+    SST_MEAN,
+    SST_OP_DETECT,
+    SST_OP_STACK,
+    SST_OP_STATS,
+    SST_SUM,
+    SstError,
+    candidates_to_numpy,
+    load,
+    sst_detect,
+    sst_frame_stats,
+    sst_last_error,
+    sst_profile_begin,
+    sst_profile_end,
+    sst_shift_table,
+    sst_stack,
+    sst_workspace_bytes,
+)

@@ -1,0 +1,238 @@
+"""ctypes binding of libsst.so, the C ABI of the shift-and-stack search.
+
+Argument marshalling only: every step of the search runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream; NumPy arrays
+carry the host-side inputs (timestamps, velocity grids).  If the compiled
+library is missing or cannot be loaded every call raises: there is no other
+implementation behind these functions.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+from ._build import LIB
+
+SST_OK = 0
+SST_E_ARG = -1
+SST_E_UNSORTED = -2
+SST_E_RANGE = -3
+SST_E_WORKSPACE = -4
+SST_E_DEVICE = -5
+SST_E_UNSUPPORTED = -6
+
+SST_F32, SST_BF16, SST_F16 = 0, 1, 2
+SST_OP_STACK, SST_OP_DETECT, SST_OP_STATS = 0, 1, 2
+SST_SUM, SST_MEAN = 0, 1
+
+# the 32-byte sst_candidate record
+CANDIDATE_DTYPE = np.dtype([
+    ("ivx", np.int32), ("ivy", np.int32), ("x", np.int32), ("y", np.int32),
+    ("snr", np.float32), ("flux", np.float32), ("coverage", np.int32), ("rank", np.int32),
+])
+
+EXPORTS = ("sst_shift_table", "sst_workspace_bytes", "sst_frame_stats", "sst_stack", "sst_detect",
+           "sst_profile_begin", "sst_profile_end", "sst_last_error", "sst_version")
+
+
+class SstError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sst error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_p = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_f = ctypes.c_float
+_sz = ctypes.c_size_t
+
+
+def load(path: Optional[str] = None) -> ctypes.CDLL:
+    """Load libsst.so (built by `_build.build`) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    lib.sst_shift_table.argtypes = [_p, _i, _d, _p, _i, _p]
+    lib.sst_shift_table.restype = _i
+    lib.sst_workspace_bytes.argtypes = [_i, _i, _i, _i, _p, _d, _p, _i, _p, _i, _i]
+    lib.sst_workspace_bytes.restype = _sz
+    lib.sst_frame_stats.argtypes = [_p, _i, _p, _i, _i, _i, _p, _p, _sz, _p]
+    lib.sst_frame_stats.restype = _i
+    lib.sst_stack.argtypes = [_p, _i, _p, _i, _i, _i, _p, _d, _p, _i, _p, _i, _p, _i, _p, _p, _p, _sz, _p]
+    lib.sst_stack.restype = _i
+    lib.sst_detect.argtypes = [_p, _i, _p, _i, _i, _i, _p, _d, _p, _i, _p, _i, _f, _i, _i, _p, _p, _p, _p, _sz,
+                               _p]
+    lib.sst_detect.restype = _i
+    lib.sst_profile_begin.argtypes = []
+    lib.sst_profile_begin.restype = _i
+    lib.sst_profile_end.argtypes = [_p, _p]
+    lib.sst_profile_end.restype = _i
+    lib.sst_last_error.argtypes = []
+    lib.sst_last_error.restype = ctypes.c_char_p
+    lib.sst_version.argtypes = []
+    lib.sst_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def sst_last_error() -> str:
+    return load().sst_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise SstError(rc, sst_last_error())
+    return rc
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _frames_dtype(frames) -> int:
+    import torch
+    if frames.dtype == torch.float32:
+        return SST_F32
+    if frames.dtype == torch.bfloat16:
+        return SST_BF16
+    if frames.dtype == torch.float16:
+        return SST_F16
+    raise TypeError(f"frames dtype {frames.dtype} is not float32/bfloat16/float16")
+
+
+def _check_frames(frames):
+    if frames.dim() != 3 or not frames.is_contiguous() or not frames.is_cuda:
+        raise ValueError("frames must be a contiguous [n][h][w] tensor on a HIP device")
+
+
+# ------------------------------------------------------------- entry points
+def sst_shift_table(t, t_ref: float, v) -> np.ndarray:
+    """int32 [n][nv] table llround(v[a] * (t[i] - t_ref)), computed by the library."""
+    t, v = _f64(t), _f64(v)
+    out = np.empty((len(t), len(v)), dtype=np.int32)
+    _check(load().sst_shift_table(_ptr(t), len(t), float(t_ref), _ptr(v), len(v), _ptr(out)))
+    return out
+
+
+def sst_workspace_bytes(op: int, n: int, h: int, w: int, t=None, t_ref: float = 0.0, vx=None, vy=None,
+                        k_max: int = 0) -> int:
+    t = None if t is None else _f64(t)
+    vx = None if vx is None else _f64(vx)
+    vy = None if vy is None else _f64(vy)
+    nb = load().sst_workspace_bytes(op, n, h, w, _ptr(t), float(t_ref), _ptr(vx), 0 if vx is None else len(vx),
+                                    _ptr(vy), 0 if vy is None else len(vy), k_max)
+    if nb == 0:
+        raise SstError(SST_E_ARG, sst_last_error())
+    return int(nb)
+
+
+def _workspace(nbytes: int, device, ws=None):
+    import torch
+    if ws is not None:
+        if ws.numel() * ws.element_size() < nbytes:
+            raise ValueError(f"workspace too small: {ws.numel() * ws.element_size()} < {nbytes}")
+        return ws
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def sst_frame_stats(frames, scale=None, ws=None):
+    """Per-frame (mean, population variance), float64 [n][2] on the device."""
+    import torch
+    _check_frames(frames)
+    n, h, w = frames.shape
+    nb = sst_workspace_bytes(SST_OP_STATS, n, h, w)
+    ws = _workspace(nb, frames.device, ws)
+    stats = torch.empty((n, 2), dtype=torch.float64, device=frames.device)
+    _check(load().sst_frame_stats(_dev(frames), _frames_dtype(frames), _dev(scale), n, h, w, _dev(stats),
+                                  _dev(ws), ws.numel(), _stream(frames.device)))
+    return stats
+
+
+def sst_stack(frames, t, t_ref: float, vx, vy, bg=None, mode: int = SST_SUM, with_coverage: bool = False,
+              out=None, cov=None, scale=None, ws=None):
+    """Plain stacks float32 [nvy][nvx][h][w] (and coverage int32 if asked)."""
+    import torch
+    _check_frames(frames)
+    n, h, w = frames.shape
+    t, vx, vy = _f64(t), _f64(vx), _f64(vy)
+    bgv = None if bg is None else _f64(bg)
+    if bgv is not None and len(bgv) != n:
+        raise ValueError("bg must have one value per frame")
+    nb = sst_workspace_bytes(SST_OP_STACK, n, h, w, t, t_ref, vx, vy)
+    ws = _workspace(nb, frames.device, ws)
+    if out is None:
+        out = torch.empty((len(vy), len(vx), h, w), dtype=torch.float32, device=frames.device)
+    if with_coverage and cov is None:
+        cov = torch.empty((len(vy), len(vx), h, w), dtype=torch.int32, device=frames.device)
+    _check(load().sst_stack(_dev(frames), _frames_dtype(frames), _dev(scale), n, h, w, _ptr(t), float(t_ref),
+                            _ptr(vx), len(vx), _ptr(vy), len(vy), _ptr(bgv), mode, _dev(out), _dev(cov), _dev(ws),
+                            ws.numel(), _stream(frames.device)))
+    return (out, cov) if with_coverage else out
+
+
+def sst_detect(frames, t, t_ref: float, vx, vy, threshold: float, min_coverage: int = 0, k_max: int = 64,
+               want_stats: bool = False, scale=None, ws=None, cand=None, count=None):
+    """Per-velocity candidate lists.
+
+    Returns (cand, count[, stats]): cand is an int32 device tensor
+    [nvy*nvx][k_max][8] holding sst_candidate records (see `candidates_to_numpy`),
+    count an int32 device tensor [nvy*nvx]; stats (host float64 [n][2]) if asked.
+    """
+    import torch
+    _check_frames(frames)
+    n, h, w = frames.shape
+    t, vx, vy = _f64(t), _f64(vx), _f64(vy)
+    nk = len(vx) * len(vy)
+    nb = sst_workspace_bytes(SST_OP_DETECT, n, h, w, t, t_ref, vx, vy, k_max)
+    ws = _workspace(nb, frames.device, ws)
+    if cand is None:
+        cand = torch.empty((nk, k_max, 8), dtype=torch.int32, device=frames.device)
+    if count is None:
+        count = torch.empty((nk,), dtype=torch.int32, device=frames.device)
+    stats = np.empty((n, 2), dtype=np.float64) if want_stats else None
+    _check(load().sst_detect(_dev(frames), _frames_dtype(frames), _dev(scale), n, h, w, _ptr(t), float(t_ref),
+                             _ptr(vx), len(vx), _ptr(vy), len(vy), float(threshold), int(min_coverage), int(k_max),
+                             _dev(cand), _dev(count), _ptr(stats), _dev(ws), ws.numel(), _stream(frames.device)))
+    return (cand, count, stats) if want_stats else (cand, count)
+
+
+def sst_profile_begin() -> None:
+    _check(load().sst_profile_begin())
+
+
+def sst_profile_end() -> Tuple[float, int]:
+    """(summed stacking-kernel milliseconds, launches) since sst_profile_begin."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int(0)
+    _check(load().sst_profile_end(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def candidates_to_numpy(cand) -> np.ndarray:
+    """Copy a candidate tensor to the host as a structured [nk][k_max] array."""
+    a = cand.detach().cpu().numpy()
+    return np.ascontiguousarray(a).view(CANDIDATE_DTYPE).reshape(a.shape[0], a.shape[1])

@@ -1,0 +1,496 @@
+// C ABI of the shift-and-stack library: argument checks, integer shift
+// tables, work planning, workspace layout and kernel launches.  Every check
+// runs on the host before any HIP call, so a rejected call enqueues nothing.
+#include "../../include/sst.h"
+#include "sst_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace {
+
+using namespace sst;
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(SST_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+constexpr int kMaxFrames = 65535;
+constexpr int kMaxSide = 16384;
+constexpr int kMaxGrid = 65535;
+constexpr double kMaxShift = 1073741824.0;  // 2^30
+constexpr size_t kEntryBudget = size_t(1) << 30;
+
+int check_dims(int n, int h, int w) {
+    if (n < 1 || n > kMaxFrames) return fail(SST_E_ARG, "n = %d frames: need 1..%d", n, kMaxFrames);
+    if (h < 1 || w < 1 || h > kMaxSide || w > kMaxSide)
+        return fail(SST_E_ARG, "frame size %dx%d: need 1..%d per side", w, h, kMaxSide);
+    return SST_OK;
+}
+
+int check_times(const double* t, int n, double t_ref) {
+    if (!t) return fail(SST_E_ARG, "t is NULL");
+    if (!std::isfinite(t_ref)) return fail(SST_E_ARG, "t_ref is not finite");
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(t[i])) return fail(SST_E_ARG, "t[%d] is not finite", i);
+        if (i > 0 && !(t[i] > t[i - 1]))
+            return fail(SST_E_UNSORTED, "timestamps must be strictly increasing (t[%d] <= t[%d])", i, i - 1);
+    }
+    return SST_OK;
+}
+
+int check_grid(const double* v, int nv, const char* name) {
+    if (!v) return fail(SST_E_ARG, "%s is NULL", name);
+    if (nv < 1 || nv > kMaxGrid) return fail(SST_E_ARG, "%s has %d entries: need 1..%d", name, nv, kMaxGrid);
+    for (int a = 0; a < nv; ++a)
+        if (!std::isfinite(v[a])) return fail(SST_E_ARG, "%s[%d] is not finite", name, a);
+    return SST_OK;
+}
+
+// d = llround(v * (t - t_ref)): one float64 subtraction and one product
+// (separate statements, no contraction), rounded half away from zero.
+int shift_of(double t, double t_ref, double v, long long& d) {
+    const double tau = t - t_ref;
+    const double p = v * tau;
+    if (!(std::fabs(p) < kMaxShift)) return SST_E_RANGE;
+    d = std::llround(p);
+    return SST_OK;
+}
+
+// Shift table for the kernels: [n][ld], ld = nv rounded up to a whole
+// velocity block; shifts clamped to [-clamp, clamp] (beyond the frame size a
+// sample is outside for every output pixel either way); padding columns
+// repeat the last real velocity.
+int build_table(const double* t, int n, double t_ref, const double* v, int nv, int ld, int clamp,
+                std::vector<int32_t>& out, const char* name) {
+    out.assign((size_t)n * ld, 0);
+    for (int i = 0; i < n; ++i) {
+        for (int a = 0; a < ld; ++a) {
+            const int aa = std::min(a, nv - 1);
+            long long d;
+            if (shift_of(t[i], t_ref, v[aa], d) != SST_OK)
+                return fail(SST_E_RANGE, "|%s[%d] * (t[%d] - t_ref)| >= 2^30 px", name, aa, i);
+            d = std::max<long long>(-clamp, std::min<long long>(clamp, d));
+            out[(size_t)i * ld + a] = (int32_t)d;
+        }
+    }
+    return SST_OK;
+}
+
+struct Plan {
+    int op = 0;
+    int n = 0, h = 0, w = 0;
+    int nvx = 0, nvy = 0, ldx = 0, ldy = 0, nvbx = 0, nvby = 0;
+    int halo = 0, step_x = 0, step_y = 0, tiles_x = 0, tiles_y = 0, ntiles = 0;
+    int padL = 0, padT = 0, Wp = 0, Hp = 0;
+    bool staged = true;
+    int kt = 0, rows_per_chunk = 0, nchunk = 0;
+    std::vector<int32_t> DX, DY;
+    // workspace offsets (bytes)
+    size_t o_tab = 0, o_part = 0, o_b = 0, o_s2 = 0, o_P = 0, o_b32 = 0, o_sdev = 0;
+    size_t o_ix = 0, o_iy = 0, o_pad = 0, o_tcount = 0, o_ent = 0, total = 0;
+};
+
+size_t take(size_t& cur, size_t bytes) {
+    const size_t o = cur;
+    cur = align_up(cur + bytes, 256);
+    return o;
+}
+
+int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
+              const double* vy, int nvy, int k_max, Plan& p) {
+    int rc = check_dims(n, h, w);
+    if (rc) return rc;
+    p.op = op;
+    p.n = n;
+    p.h = h;
+    p.w = w;
+    p.nchunk = (int)(((long long)h * w + kStatChunk - 1) / kStatChunk);
+    size_t cur = 0;
+    if (op == SST_OP_STATS) {
+        p.o_part = take(cur, (size_t)n * p.nchunk * 3 * sizeof(double));
+        p.o_b = take(cur, (size_t)n * sizeof(double));
+        p.o_s2 = take(cur, (size_t)n * sizeof(double));
+        p.o_P = take(cur, (size_t)(n + 1) * sizeof(double));
+        p.o_b32 = take(cur, (size_t)n * sizeof(float));
+        p.total = cur;
+        return SST_OK;
+    }
+    if (op != SST_OP_STACK && op != SST_OP_DETECT) return fail(SST_E_ARG, "unknown op %d", op);
+    if ((rc = check_times(t, n, t_ref))) return rc;
+    if ((rc = check_grid(vx, nvx, "vx"))) return rc;
+    if ((rc = check_grid(vy, nvy, "vy"))) return rc;
+    if (op == SST_OP_DETECT && (k_max < 1 || k_max > kMaxK))
+        return fail(SST_E_ARG, "k_max = %d: need 1..%d", k_max, kMaxK);
+    const bool detect = op == SST_OP_DETECT;
+    p.nvx = nvx;
+    p.nvy = nvy;
+    p.nvbx = ceil_div(nvx, kVBX);
+    p.nvby = ceil_div(nvy, kVBY);
+    p.ldx = p.nvbx * kVBX;
+    p.ldy = p.nvby * kVBY;
+    if ((rc = build_table(t, n, t_ref, vx, nvx, p.ldx, w, p.DX, "vx"))) return rc;
+    if ((rc = build_table(t, n, t_ref, vy, nvy, p.ldy, h, p.DY, "vy"))) return rc;
+
+    p.halo = detect ? 1 : 0;
+    p.step_x = kTileW - 2 * p.halo;
+    p.step_y = kRows - 2 * p.halo;
+    p.tiles_x = ceil_div(w, p.step_x);
+    p.tiles_y = ceil_div(h, p.step_y);
+    p.ntiles = p.tiles_x * p.tiles_y;
+
+    int dxmin = 0, dxmax = 0, dymin = 0, dymax = 0, sx = 0, sy = 0;
+    for (int i = 0; i < n; ++i) {
+        const int32_t* rx = &p.DX[(size_t)i * p.ldx];
+        for (int a0 = 0; a0 < p.ldx; a0 += kVBX) {
+            const auto mm = std::minmax_element(rx + a0, rx + a0 + kVBX);
+            dxmin = std::min(dxmin, *mm.first);
+            dxmax = std::max(dxmax, *mm.second);
+            sx = std::max(sx, *mm.second - *mm.first);
+        }
+        const int32_t* ry = &p.DY[(size_t)i * p.ldy];
+        for (int b0 = 0; b0 < p.ldy; b0 += kVBY) {
+            const auto mm = std::minmax_element(ry + b0, ry + b0 + kVBY);
+            dymin = std::min(dymin, *mm.first);
+            dymax = std::max(dymax, *mm.second);
+            sy = std::max(sy, *mm.second - *mm.first);
+        }
+    }
+    p.staged = sx <= kSMaxX && sy <= kSMaxY;
+    // zero padding so that every staged or direct read stays inside the copy
+    const int X0max = (p.tiles_x - 1) * p.step_x - p.halo;
+    const int Y0max = (p.tiles_y - 1) * p.step_y - p.halo;
+    p.padL = (int)align_up((size_t)std::max(0, p.halo - dxmin), 4);
+    p.padT = std::max(0, p.halo - dymin);
+    // the staged window is kLdsPitch x kLdsRows from the block's smallest
+    // shift (aligned down by up to 3 columns), the direct path reads up to the
+    // largest shift plus the tile
+    const int need_w = std::max(X0max + dxmax + kTileW, X0max + dxmax + kStageW) + p.padL + 4;
+    const int need_h = std::max(Y0max + dymax + kRows, Y0max + dymax + kLdsRows) + p.padT;
+    p.Wp = (int)align_up((size_t)std::max(4, need_w), 16);
+    p.Hp = std::max(1, need_h);
+
+    p.o_tab = take(cur, ((size_t)n * p.ldx + (size_t)n * p.ldy) * sizeof(int32_t));
+    p.o_b32 = take(cur, (size_t)n * sizeof(float));
+    p.o_ix = take(cur, (size_t)nvx * w * 2 * sizeof(int32_t));
+    p.o_iy = take(cur, (size_t)nvy * h * 2 * sizeof(int32_t));
+    p.o_pad = take(cur, (size_t)n * p.Hp * p.Wp * sizeof(float));
+    if (detect) {
+        p.o_part = take(cur, (size_t)n * p.nchunk * 3 * sizeof(double));
+        p.o_b = take(cur, (size_t)n * sizeof(double));
+        p.o_s2 = take(cur, (size_t)n * sizeof(double));
+        p.o_P = take(cur, (size_t)(n + 1) * sizeof(double));
+        p.o_sdev = take(cur, (size_t)n * 2 * sizeof(double));
+        p.kt = k_max;
+        const size_t per_row = (size_t)kVBY * nvx * p.ntiles * ((size_t)p.kt * sizeof(Entry) + sizeof(int32_t));
+        p.rows_per_chunk = (int)std::max<size_t>(1, std::min<size_t>(p.nvby, kEntryBudget / per_row));
+        const size_t nk = (size_t)p.rows_per_chunk * kVBY * nvx;
+        p.o_tcount = take(cur, nk * p.ntiles * sizeof(int32_t));
+        p.o_ent = take(cur, nk * p.ntiles * p.kt * sizeof(Entry));
+    }
+    p.total = cur;
+    return SST_OK;
+}
+
+int check_frames(const void* frames, int dtype, const float* scale) {
+    if (!frames) return fail(SST_E_ARG, "frames is NULL");
+    if (dtype == SST_BF16 || dtype == SST_F16) {
+        if (!scale) return fail(SST_E_ARG, "16-bit frames need a per-frame scale array");
+        return fail(SST_E_UNSUPPORTED, "16-bit frame storage is not implemented in this build");
+    }
+    if (dtype != SST_F32) return fail(SST_E_ARG, "unknown frame dtype %d", dtype);
+    return SST_OK;
+}
+
+int check_ws(const Plan& p, void* ws, size_t ws_bytes) {
+    if (!ws) return fail(SST_E_WORKSPACE, "workspace is NULL (need %zu bytes)", p.total);
+    if (ws_bytes < p.total) return fail(SST_E_WORKSPACE, "workspace has %zu bytes, need %zu", ws_bytes, p.total);
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(SST_E_WORKSPACE, "workspace must be 256-byte aligned");
+    return SST_OK;
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// Upload the shift tables (and optional per-frame floats) in one copy.
+int upload_tables(const Plan& p, const double* bg, void* ws, hipStream_t s) {
+    const size_t nx = (size_t)p.n * p.ldx, ny = (size_t)p.n * p.ldy;
+    std::vector<char> host(p.o_b32 - p.o_tab + (size_t)p.n * sizeof(float), 0);
+    std::memcpy(host.data(), p.DX.data(), nx * sizeof(int32_t));
+    std::memcpy(host.data() + nx * sizeof(int32_t), p.DY.data(), ny * sizeof(int32_t));
+    size_t bytes = (nx + ny) * sizeof(int32_t);
+    if (bg) {
+        float* f = reinterpret_cast<float*>(host.data() + (p.o_b32 - p.o_tab));
+        for (int i = 0; i < p.n; ++i) f[i] = (float)bg[i];
+        bytes = host.size();
+    }
+    hipError_t e = hipMemcpyAsync(at<char>(ws, p.o_tab), host.data(), bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(shift tables)");
+    // the copy is from pageable memory; make sure it has been consumed before
+    // `host` goes out of scope
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(shift tables)");
+    return SST_OK;
+}
+
+StackArgs stack_args(const Plan& p, void* ws) {
+    StackArgs a{};
+    a.pad = at<float>(ws, p.o_pad);
+    a.fstride = (long long)p.Hp * p.Wp;
+    a.n = p.n;
+    a.h = p.h;
+    a.w = p.w;
+    a.Wp = p.Wp;
+    a.padL = p.padL;
+    a.padT = p.padT;
+    a.DX = at<int>(ws, p.o_tab);
+    a.DY = at<int>(ws, p.o_tab + (size_t)p.n * p.ldx * sizeof(int32_t));
+    a.ldx = p.ldx;
+    a.ldy = p.ldy;
+    a.nvx = p.nvx;
+    a.nvy = p.nvy;
+    a.IX = at<int>(ws, p.o_ix);
+    a.IY = at<int>(ws, p.o_iy);
+    a.P = p.o_P ? at<double>(ws, p.o_P) : nullptr;
+    a.tiles_x = p.tiles_x;
+    a.tiles_y = p.tiles_y;
+    a.step_x = p.step_x;
+    a.step_y = p.step_y;
+    a.halo = p.halo;
+    a.nvbx = p.nvbx;
+    a.vby0 = 0;
+    a.nvby = p.nvby;
+    a.ntiles = p.ntiles;
+    return a;
+}
+
+int prep_and_cov(const Plan& p, const void* frames, const float* b32, void* ws, hipStream_t s) {
+    PrepArgs pa{};
+    pa.frames = static_cast<const float*>(frames);
+    pa.b32 = b32;
+    pa.pad = at<float>(ws, p.o_pad);
+    pa.n = p.n;
+    pa.h = p.h;
+    pa.w = p.w;
+    pa.Hp = p.Hp;
+    pa.Wp = p.Wp;
+    pa.padL = p.padL;
+    pa.padT = p.padT;
+    hipError_t e = launch_prep(pa, s);
+    if (e != hipSuccess) return hip_fail(e, "prep kernel");
+    const int* DX = at<int>(ws, p.o_tab);
+    const int* DY = at<int>(ws, p.o_tab + (size_t)p.n * p.ldx * sizeof(int32_t));
+    if ((e = launch_cov(DX, p.ldx, p.n, p.nvx, p.w, at<int>(ws, p.o_ix), s)) != hipSuccess)
+        return hip_fail(e, "coverage kernel (x)");
+    if ((e = launch_cov(DY, p.ldy, p.n, p.nvy, p.h, at<int>(ws, p.o_iy), s)) != hipSuccess)
+        return hip_fail(e, "coverage kernel (y)");
+    return SST_OK;
+}
+
+// Event pairs around stacking-kernel launches while profiling is on.
+constexpr int kProfMax = 4096;
+struct Profiler {
+    bool on = false;
+    int used = 0;
+    std::vector<hipEvent_t> ev;  // 2 per launch
+    std::mutex mu;
+};
+Profiler g_prof;
+
+hipError_t launch_stack_profiled(const StackArgs& a, bool detect, bool staged, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (!g_prof.on) return launch_stack(a, detect, staged, s);
+    if (g_prof.used >= kProfMax) {
+        g_prof.on = false;
+        return hipErrorLaunchOutOfResources;
+    }
+    hipEvent_t e0 = g_prof.ev[2 * g_prof.used], e1 = g_prof.ev[2 * g_prof.used + 1];
+    hipError_t e = hipEventRecord(e0, s);
+    if (e != hipSuccess) return e;
+    e = launch_stack(a, detect, staged, s);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(e1, s);
+    if (e == hipSuccess) ++g_prof.used;
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sst_profile_begin(void) {
+    g_err.clear();
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    while ((int)g_prof.ev.size() < 2 * kProfMax) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
+        g_prof.ev.push_back(e);
+    }
+    g_prof.used = 0;
+    g_prof.on = true;
+    return SST_OK;
+}
+
+int sst_profile_end(double* stack_ms, int* stack_launches) {
+    g_err.clear();
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    const bool overflow = g_prof.on == false && g_prof.used >= kProfMax;
+    g_prof.on = false;
+    double total = 0.0;
+    for (int k = 0; k < g_prof.used; ++k) {
+        hipError_t r = hipEventSynchronize(g_prof.ev[2 * k + 1]);
+        if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
+        float ms = 0.f;
+        r = hipEventElapsedTime(&ms, g_prof.ev[2 * k], g_prof.ev[2 * k + 1]);
+        if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
+        total += ms;
+    }
+    if (stack_ms) *stack_ms = total;
+    if (stack_launches) *stack_launches = g_prof.used;
+    if (overflow) return fail(SST_E_RANGE, "more than %d profiled launches", kProfMax);
+    return SST_OK;
+}
+
+
+const char* sst_last_error(void) { return g_err.c_str(); }
+
+const char* sst_version(void) { return "sst 0.1 (gfx950)"; }
+
+int sst_shift_table(const double* t, int n, double t_ref, const double* v, int nv, int32_t* out) {
+    g_err.clear();
+    if (n < 1 || n > kMaxFrames) return fail(SST_E_ARG, "n = %d: need 1..%d", n, kMaxFrames);
+    int rc = check_times(t, n, t_ref);
+    if (rc) return rc;
+    if ((rc = check_grid(v, nv, "v"))) return rc;
+    if (!out) return fail(SST_E_ARG, "out is NULL");
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < nv; ++a) {
+            long long d;
+            if (shift_of(t[i], t_ref, v[a], d) != SST_OK)
+                return fail(SST_E_RANGE, "|v[%d] * (t[%d] - t_ref)| >= 2^30 px", a, i);
+            out[(size_t)i * nv + a] = (int32_t)d;
+        }
+    return SST_OK;
+}
+
+size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
+                           const double* vy, int nvy, int k_max) {
+    g_err.clear();
+    Plan p;
+    if (make_plan(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p) != SST_OK) return 0;
+    return p.total;
+}
+
+int sst_frame_stats(const void* frames, int dtype, const float* scale, int n, int h, int w, double* stats, void* ws,
+                    size_t ws_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_frames(frames, dtype, scale);
+    if (rc) return rc;
+    if (!stats) return fail(SST_E_ARG, "stats is NULL");
+    Plan p;
+    if ((rc = make_plan(SST_OP_STATS, n, h, w, nullptr, 0, nullptr, 0, nullptr, 0, 0, p))) return rc;
+    if ((rc = check_ws(p, ws, ws_bytes))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_stats(static_cast<const float*>(frames), n, h, w, at<double>(ws, p.o_part), p.nchunk,
+                                at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
+                                at<double>(ws, p.o_P), stats, s);
+    if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
+    return SST_OK;
+}
+
+int sst_stack(const void* frames, int dtype, const float* scale, int n, int h, int w, const double* t, double t_ref,
+              const double* vx, int nvx, const double* vy, int nvy, const double* bg, int mode, float* out,
+              int32_t* cov, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_frames(frames, dtype, scale);
+    if (rc) return rc;
+    if (!out) return fail(SST_E_ARG, "out is NULL");
+    if (mode != SST_SUM && mode != SST_MEAN) return fail(SST_E_ARG, "unknown stack mode %d", mode);
+    if (bg)
+        for (int i = 0; i < n && i < kMaxFrames; ++i)
+            if (!std::isfinite(bg[i])) return fail(SST_E_ARG, "bg[%d] is not finite", i);
+    Plan p;
+    if ((rc = make_plan(SST_OP_STACK, n, h, w, t, t_ref, vx, nvx, vy, nvy, 0, p))) return rc;
+    if ((rc = check_ws(p, ws, ws_bytes))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = upload_tables(p, bg, ws, s))) return rc;
+    if ((rc = prep_and_cov(p, frames, bg ? at<float>(ws, p.o_b32) : nullptr, ws, s))) return rc;
+    StackArgs a = stack_args(p, ws);
+    a.out = out;
+    a.cov = cov;
+    a.mean = mode == SST_MEAN;
+    hipError_t e = launch_stack_profiled(a, false, p.staged, s);
+    if (e != hipSuccess) return hip_fail(e, "stack kernel");
+    return SST_OK;
+}
+
+int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, int w, const double* t, double t_ref,
+               const double* vx, int nvx, const double* vy, int nvy, float threshold, int min_coverage, int k_max,
+               sst_candidate* cand, int32_t* count, double* frame_stats, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_frames(frames, dtype, scale);
+    if (rc) return rc;
+    if (!cand || !count) return fail(SST_E_ARG, "cand/count is NULL");
+    if (std::isnan(threshold)) return fail(SST_E_ARG, "threshold is NaN");
+    Plan p;
+    if ((rc = make_plan(SST_OP_DETECT, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p))) return rc;
+    if ((rc = check_ws(p, ws, ws_bytes))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = upload_tables(p, nullptr, ws, s))) return rc;
+    hipError_t e = launch_stats(static_cast<const float*>(frames), n, h, w, at<double>(ws, p.o_part), p.nchunk,
+                                at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
+                                at<double>(ws, p.o_P), at<double>(ws, p.o_sdev), s);
+    if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
+    if ((rc = prep_and_cov(p, frames, at<float>(ws, p.o_b32), ws, s))) return rc;
+    StackArgs a = stack_args(p, ws);
+    a.thr = threshold;
+    a.cmin = min_coverage > 0 ? min_coverage : (n + 1) / 2;
+    a.kt = p.kt;
+    a.tcount = at<int32_t>(ws, p.o_tcount);
+    a.ent = at<Entry>(ws, p.o_ent);
+    for (int r0 = 0; r0 < p.nvby; r0 += p.rows_per_chunk) {
+        const int rows = std::min(p.rows_per_chunk, p.nvby - r0);
+        a.vby0 = r0;
+        a.nvby = rows;
+        if ((e = launch_stack_profiled(a, true, p.staged, s)) != hipSuccess) return hip_fail(e, "detect kernel");
+        const int b_first = r0 * kVBY;
+        const int b_last = std::min(nvy, (r0 + rows) * kVBY);
+        const int nk = (b_last - b_first) * nvx;
+        if ((e = launch_merge(a.tcount, a.ent, p.ntiles, p.kt, k_max, nvx, w, b_first * nvx, nk, cand, count, s)) !=
+            hipSuccess)
+            return hip_fail(e, "merge kernel");
+    }
+    if (frame_stats) {
+        e = hipMemcpyAsync(frame_stats, at<double>(ws, p.o_sdev), (size_t)n * 2 * sizeof(double),
+                           hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(frame stats)");
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    }
+    return SST_OK;
+}
+
+}  // extern "C"

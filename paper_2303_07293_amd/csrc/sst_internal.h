@@ -1,0 +1,105 @@
+// Internal declarations shared by the host API (sst_api.cpp) and the HIP
+// kernels (sst_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace sst {
+
+// clang vector types (HIP's int4/float4 wrappers are structs that keep
+// register arrays of them from being promoted out of scratch)
+typedef int i4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Work decomposition of the stack kernels.  A workgroup is kWaves wave64s;
+// it owns a tile of 64 columns (one per lane) by kRows rows and a block of
+// kVBX x kVBY trial velocities.  Wave w handles the kVPW velocities
+// a0 + kVPW*(w / kVBY) + q (q < kVPW) of velocity row b0 + w % kVBY, so each
+// lane keeps kVPW * kRows float accumulators and every staged frame tile is
+// reused by all kVBX * kVBY velocities of the block.
+constexpr int kWave = 64;
+constexpr int kWaves = 8;
+constexpr int kThreads = kWave * kWaves;
+constexpr int kTileW = 64;
+constexpr int kRows = 32;
+constexpr int kVBX = 6;
+constexpr int kVBY = 4;
+constexpr int kVPW = 3;  // velocities per wave
+static_assert(kVBX * kVBY == kVPW * kWaves, "every velocity of a block has one wave");
+// LDS staging: the frame region a velocity block needs is the tile widened by
+// the spread of the block's shifts (at most kSMaxX / kSMaxY px) plus 3
+// columns of alignment slack for 16-byte staging.  A fixed window of
+// kStageW x kLdsRows floats is staged per frame; LDS rows are kLdsPitch = 128
+// floats apart so that every row of a column is reachable from one base
+// address (row offsets are multiples of 64 dwords).
+constexpr int kSMaxX = 32;
+constexpr int kSMaxY = 16;
+constexpr int kStageW = kTileW + kSMaxX + 4;
+constexpr int kLdsPitch = 128;
+constexpr int kLdsRows = kRows + kSMaxY;
+constexpr int kLdsBuf = kLdsPitch * kLdsRows;  // floats per staging buffer
+static_assert(kStageW % 4 == 0 && kStageW <= kLdsPitch, "16-byte staging chunks fit an LDS row");
+
+constexpr int kStatThreads = 256;
+constexpr int kStatChunk = 8192;  // pixels per frame-statistics workgroup
+constexpr int kMaxK = 1024;       // largest k_max accepted
+constexpr int kMergeLds = 2048;   // entries ranked in LDS by the merge kernel
+
+// One candidate kept by a (tile, velocity) before the per-velocity merge.
+struct Entry {
+    float sn;
+    float flux;
+    int32_t raster;
+    int32_t cov;
+};
+
+struct StackArgs {
+    const float* pad;   // zero-padded, background-subtracted frames [n][Hp][Wp]
+    long long fstride;  // Hp * Wp
+    int n, h, w;
+    int Wp, padL, padT;
+    const int* DX;  // [n][ldx] clamped x shifts, columns >= nvx repeat column nvx-1
+    const int* DY;  // [n][ldy]
+    int ldx, ldy;
+    int nvx, nvy;
+    const int* IX;    // [nvx][w][2]: first and last frame whose x sample is in the frame
+    const int* IY;    // [nvy][h][2]
+    const double* P;  // [n+1] prefix sums of the frame variances
+    int tiles_x, tiles_y, step_x, step_y, halo;
+    int nvbx;        // velocity blocks along x
+    int vby0, nvby;  // velocity-block rows handled by this launch
+    // plain stack
+    float* out;
+    int32_t* cov;
+    int mean;
+    // detect
+    float thr;
+    int cmin;
+    int kt;      // entries kept per (tile, velocity)
+    int ntiles;  // tiles_x * tiles_y
+    int32_t* tcount;  // [velocities of this launch][ntiles]
+    Entry* ent;       // [velocities of this launch][ntiles][kt]
+};
+
+struct PrepArgs {
+    const float* frames;
+    const float* b32;  // [n] subtracted per frame, or nullptr
+    float* pad;
+    int n, h, w, Hp, Wp, padL, padT;
+};
+
+// launch wrappers (sst_kernels.hip); each returns a hipError_t
+hipError_t launch_stats(const float* frames, int n, int h, int w, double* part, int nchunk,
+                        double* b, double* s2, float* b32, double* P, double* stats_dev,
+                        hipStream_t s);
+hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
+hipError_t launch_cov(const int* D, int ld, int n, int nv, int size, int* I, hipStream_t s);
+hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, hipStream_t s);
+hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int ntiles, int kt, int k_max,
+                        int nvx, int w, int k_first, int nk, void* cand, int32_t* count,
+                        hipStream_t s);
+
+}  // namespace sst

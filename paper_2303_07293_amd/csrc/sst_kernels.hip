@@ -1,0 +1,750 @@
+// HIP kernels of the shift-and-stack search, written for gfx950 (CDNA4):
+// wave64, LDS-staged frame tiles, FP32 accumulation, FP64 only for the
+// per-frame variance sums of the S/N normaliser.
+//
+// Data flow of one detect call (paper Sec. 2.1: remove the static sky, shift
+// each frame along a trial linear motion, sum, keep significant peaks):
+//   k_stats_partial/k_stats_final  per-frame mean b_i, variance s2_i, prefix P
+//   k_prep                         zero-padded copy of F_i - b_i (float32)
+//   k_cov                          per (velocity component, coordinate) the
+//                                  first/last frame whose sample is in frame
+//   k_stack<detect>                accumulate, S/N, 8-neighbour peaks, keep the
+//                                  best kt per (tile, velocity)
+//   k_merge                        per-velocity top-k_max, deterministic order
+#include "sst_internal.h"
+#include "../../include/sst.h"
+
+#include <climits>
+#include <cmath>
+
+namespace sst {
+
+constexpr int kAux = kStatThreads;  // threads of the auxiliary kernels (4 waves)
+
+// ------------------------------------------------------------------ helpers
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber them so that each XCD runs a contiguous range of logical
+// work items: neighbouring velocity blocks of one tile then share that XCD's
+// L2 copy of the frame region.
+__device__ __forceinline__ int xcd_remap(int g, int G) {
+    const int per = G / 8, rem = G % 8;
+    const int xcd = g % 8, idx = g / 8;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+__device__ __forceinline__ double block_sum_f64(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);  // fixed order: deterministic
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ long long block_sum_i64(long long v, long long* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const long long t = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int lane) {
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    return inc - v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(v, o);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+// Total order of candidates of one velocity: larger S/N first, then lower
+// raster index.  The float is mapped to an unsigned integer with the same
+// order; raster indices are distinct, so keys are distinct.
+__device__ __forceinline__ unsigned long long cand_key(float sn, int raster) {
+    unsigned u = __float_as_uint(sn);
+    u ^= (u & 0x80000000u) ? 0xFFFFFFFFu : 0x80000000u;
+    return ((unsigned long long)u << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)raster);
+}
+
+__device__ __forceinline__ i4 load_i4(const int* p) { return *reinterpret_cast<const i4*>(p); }
+
+__device__ __forceinline__ int pick4(const i4 v, int q) {
+    return q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+}
+
+// (first, last) frame pair of a coverage interval
+__device__ __forceinline__ void load_iv(const int* I, long long e, int& lo, int& hi) {
+    const long long v = *reinterpret_cast<const long long*>(I + 2 * e);
+    lo = (int)(unsigned)(v & 0xFFFFFFFFll);
+    hi = (int)(v >> 32);
+}
+
+// ------------------------------------------------------- frame statistics
+// One workgroup per (chunk of kStatChunk pixels, frame): the chunk's sum and
+// sum of squared deviations from the chunk mean, both float64.
+__global__ __launch_bounds__(kAux) void k_stats_partial(const float* __restrict__ frames, long long npx,
+                                                           int nchunk, double* __restrict__ part) {
+    const int i = blockIdx.y, c = blockIdx.x;
+    const float* f = frames + (long long)i * npx;
+    const long long base = (long long)c * kStatChunk;
+    const int cnt = (int)min((long long)kStatChunk, npx - base);
+    constexpr int PER = kStatChunk / kAux;
+    __shared__ double sh[4];
+    float v[PER];
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int e = j * kAux + threadIdx.x;
+        v[j] = e < cnt ? f[base + e] : 0.f;
+        s += (double)v[j];
+    }
+    const double sum = block_sum_f64(s, sh);
+    const double mean = sum / (double)cnt;
+    double m2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int e = j * kAux + threadIdx.x;
+        if (e < cnt) {
+            const double d = (double)v[j] - mean;
+            m2 += d * d;
+        }
+    }
+    const double M2 = block_sum_f64(m2, sh);
+    if (threadIdx.x == 0) {
+        double* o = part + ((long long)i * nchunk + c) * 3;
+        o[0] = (double)cnt;
+        o[1] = sum;
+        o[2] = M2;
+    }
+}
+
+// Combine the chunks of each frame (pairwise-update formula for the sum of
+// squared deviations: M2 = sum_c [M2_c + n_c (mean_c - mean)^2]) and build the
+// prefix P[j] = sum_{i<j} s2_i used to normalise any contiguous frame range.
+__global__ __launch_bounds__(kAux) void k_stats_final(const double* __restrict__ part, int nchunk, int n,
+                                                         long long npx, double* __restrict__ b,
+                                                         double* __restrict__ s2, float* __restrict__ b32,
+                                                         double* __restrict__ P, double* __restrict__ stats_dev) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double* p = part + (long long)i * nchunk * 3;
+        double sum = 0.0;
+        for (int c = 0; c < nchunk; ++c) sum += p[c * 3 + 1];
+        const double mean = sum / (double)npx;
+        double M2 = 0.0;
+        for (int c = 0; c < nchunk; ++c) {
+            const double cnt = p[c * 3 + 0];
+            const double d = p[c * 3 + 1] / cnt - mean;
+            M2 += p[c * 3 + 2] + cnt * d * d;
+        }
+        const double var = M2 / (double)npx;
+        b[i] = mean;
+        s2[i] = var;
+        b32[i] = (float)mean;
+        if (stats_dev) {
+            stats_dev[2 * i] = mean;
+            stats_dev[2 * i + 1] = var;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        P[0] = 0.0;
+        for (int i = 0; i < n; ++i) {
+            acc += s2[i];
+            P[i + 1] = acc;
+        }
+    }
+}
+
+// ------------------------------------------------------------ padded copy
+// pad[i][yp][xp] = F_i(xp - padL, yp - padT) - b32[i] inside the frame, 0
+// outside: out-of-frame samples then add nothing, and every staging read of
+// the stack kernel is an unconditional aligned 16-byte load.
+__global__ __launch_bounds__(kAux) void k_prep(const PrepArgs a) {
+    const int i = blockIdx.z, yp = blockIdx.y;
+    const int xp = (blockIdx.x * kAux + threadIdx.x) * 4;
+    if (xp >= a.Wp) return;
+    const int y = yp - a.padT;
+    float o[4] = {0.f, 0.f, 0.f, 0.f};
+    if (y >= 0 && y < a.h) {
+        const float bb = a.b32 ? a.b32[i] : 0.f;
+        const float* row = a.frames + ((long long)i * a.h + y) * a.w;
+        const int x0 = xp - a.padL;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int x = x0 + k;
+            o[k] = (x >= 0 && x < a.w) ? row[x] - bb : 0.f;
+        }
+    }
+    f4* dst = reinterpret_cast<f4*>(a.pad + (long long)i * a.Hp * a.Wp + (long long)yp * a.Wp + xp);
+    *dst = f4{o[0], o[1], o[2], o[3]};
+}
+
+// ------------------------------------------------------ coverage intervals
+// I[a][x] = (first, last) frame i with 0 <= x + D[i][a] < size.  D is
+// monotone in i (the timestamps are sorted), so the in-frame frames form one
+// interval and the 2-D coverage of a pixel is the intersection of its x and
+// y intervals.  Empty: (n, -1).
+__global__ __launch_bounds__(kAux) void k_cov(const int* __restrict__ D, int ld, int n, int size,
+                                                 int* __restrict__ I) {
+    const int x = blockIdx.x * kAux + threadIdx.x;
+    const int a = blockIdx.y;
+    if (x >= size) return;
+    int lo = n, hi = -1;
+    for (int i = 0; i < n; ++i) {
+        const int p = x + D[(long long)i * ld + a];
+        if (p >= 0 && p < size) {
+            lo = min(lo, i);
+            hi = i;
+        }
+    }
+    I[2 * ((long long)a * size + x)] = lo;
+    I[2 * ((long long)a * size + x) + 1] = hi;
+}
+
+__device__ __forceinline__ int coverage(int xlo, int xhi, int ylo, int yhi, int& lo, int& hi) {
+    lo = max(xlo, ylo);
+    hi = min(xhi, yhi);
+    return hi - lo + 1;
+}
+
+// -------------------------------------------------------------- stacking
+// Frame geometry of one velocity block for one frame.  The staged region is
+// always kLdsRows x kLdsPitch floats starting at the 16-byte aligned column
+// at or left of the block's smallest shift; the padded copy is sized so that
+// this fixed window never leaves it.
+struct FrameGeom {
+    int dxw[kVPW];  // x shifts of this wave's velocities
+    int dyw;        // y shift of this wave's velocity row
+    int dxmin;      // smallest x shift of the block
+    int dymin;
+    int c0;         // LDS column of the region's first needed column
+    long long src;  // element offset of the staged window's origin
+};
+
+__device__ __forceinline__ FrameGeom frame_geom(const StackArgs& A, int i, int a0, int b0, int wave, int X0,
+                                                int Y0) {
+    FrameGeom g;
+    const int* rx = A.DX + (long long)i * A.ldx + a0;
+    const int* ry = A.DY + (long long)i * A.ldy + b0;
+    const int xg = wave / kVBY;  // which kVPW-group of the block's x velocities
+    int dxmin = rx[0], dymin = ry[0];
+#pragma unroll
+    for (int j = 1; j < kVBX; ++j) dxmin = min(dxmin, rx[j]);
+#pragma unroll
+    for (int j = 1; j < kVBY; ++j) dymin = min(dymin, ry[j]);
+#pragma unroll
+    for (int q = 0; q < kVPW; ++q) g.dxw[q] = rx[xg * kVPW + q];
+    g.dyw = ry[wave % kVBY];
+    g.dxmin = dxmin;
+    g.dymin = dymin;
+    const int gx0 = X0 + g.dxmin + A.padL;
+    const int xa = gx0 & ~3;
+    g.c0 = gx0 - xa;
+    const int gy0 = Y0 + g.dymin + A.padT;
+    g.src = (long long)i * A.fstride + (long long)gy0 * A.Wp + xa;
+    return g;
+}
+
+constexpr int kC4 = kStageW / 4;                                    // float4 chunks per staged row
+constexpr int kChunks = kC4 * kLdsRows;                              // chunks per staged window
+constexpr int kStage = (kChunks + kThreads - 1) / kThreads;          // chunks per thread
+constexpr bool kStageRagged = kChunks % kThreads != 0;
+
+// Per-thread constant part of the staging addresses: chunk e = tid + j*kThreads
+// is row e / kC4, column 4*(e % kC4) of the window (divisions by constants).
+struct StageMap {
+    unsigned goff[kStage];  // element offset in the padded copy, from the window origin
+    int loff[kStage];       // element offset in an LDS buffer
+    bool last;              // whether this thread has a chunk in the last (ragged) round
+};
+
+__device__ __forceinline__ StageMap stage_map(int Wp) {
+    StageMap m;
+#pragma unroll
+    for (int j = 0; j < kStage; ++j) {
+        const int e = (int)threadIdx.x + j * kThreads;
+        const int row = e / kC4, c = e % kC4;
+        m.goff[j] = (unsigned)(row * Wp + 4 * c);
+        m.loff[j] = row * kLdsPitch + 4 * c;
+    }
+    m.last = (int)threadIdx.x + (kStage - 1) * kThreads < kChunks;
+    return m;
+}
+
+__device__ __forceinline__ void stage_load(const StackArgs& A, const FrameGeom& g, const StageMap& m,
+                                           f4 (&st)[kStage]) {
+    const float* src = A.pad + g.src;
+#pragma unroll
+    for (int j = 0; j < kStage; ++j) {
+        if (j < kStage - 1 || !kStageRagged || m.last) st[j] = *reinterpret_cast<const f4*>(src + m.goff[j]);
+    }
+}
+
+__device__ __forceinline__ void stage_store(float* buf, const StageMap& m, const f4 (&st)[kStage]) {
+#pragma unroll
+    for (int j = 0; j < kStage; ++j) {
+        if (j < kStage - 1 || !kStageRagged || m.last) *reinterpret_cast<f4*>(buf + m.loff[j]) = st[j];
+    }
+}
+
+// S/N, peak test and candidate output of one (tile, velocity) for one wave.
+// Each lane holds one column of kRows accumulated sums.  Rows 0 and kRows-1
+// and lanes 0 and 63 are the 1-pixel halo: their S/N is only compared with.
+// The S/N of a row is recomputed where it is needed rather than stored, to
+// keep the register footprint of this epilogue below the main loop's.
+struct SnCtx {
+    const StackArgs* A;
+    int b, Y0, xlo, xhi;
+    bool full;
+    float rs;  // 1/sqrt(V) of a fully covered pixel
+};
+
+__device__ __forceinline__ float sn_row(const SnCtx& c, float acc, int r, int& cov) {
+    if (c.full) {
+        cov = c.A->n;
+        return acc * c.rs;
+    }
+    const StackArgs& A = *c.A;
+    const int y = c.Y0 + r;
+    int ylo = A.n, yhi = -1;
+    if (y >= 0 && y < A.h) load_iv(A.IY, (long long)c.b * A.h + y, ylo, yhi);
+    int lo, hi;
+    cov = coverage(c.xlo, c.xhi, ylo, yhi, lo, hi);
+    if (cov <= 0) return -INFINITY;
+    const double V = A.P[hi + 1] - A.P[lo];
+    return V > 0.0 ? acc * rsqrtf((float)V) : 0.f;
+}
+
+// Peak test and candidate output for one (tile, velocity) whose column sums
+// are parked in LDS: col[r * 64 + lane] = S' of row r of this lane's column.
+__device__ __noinline__ void candidates_from_column(const SnCtx c, const float* col, unsigned fl, int lane, int x,
+                                                    int Y0, int tile, long long kc) {
+    const StackArgs& A = *c.A;
+    const int kt = A.kt;
+    // 8-neighbour test with the raster tie rule: neighbours earlier in raster
+    // order must be strictly smaller, later ones may tie.
+    unsigned cm = 0;
+    int cv;
+    float Sm = sn_row(c, col[lane], 0, cv), S0 = sn_row(c, col[kWave + lane], 1, cv);
+    float Lm = __shfl_up(Sm, 1), Rm = __shfl_down(Sm, 1);
+    float L0 = __shfl_up(S0, 1), R0 = __shfl_down(S0, 1);
+#pragma unroll 1
+    for (int r = 1; r <= kRows - 2; ++r) {
+        const float Sp = sn_row(c, col[(r + 1) * kWave + lane], r + 1, cv);
+        const float Lp = __shfl_up(Sp, 1), Rp = __shfl_down(Sp, 1);
+        if ((fl >> r) & 1u) {
+            const float s = S0;
+            const bool ok = s > Lm && s > Sm && s > Rm && s > L0 && s >= R0 && s >= Lp && s >= Sp && s >= Rp;
+            if (ok) cm |= 1u << r;
+        }
+        Sm = S0;
+        S0 = Sp;
+        Lm = L0;
+        Rm = R0;
+        L0 = Lp;
+        R0 = Rp;
+    }
+    const int total = wave_sum_i32(__popc(cm));
+    if (lane == 0) A.tcount[kc * A.ntiles + tile] = total;
+    if (total == 0) return;
+    Entry* E = A.ent + (kc * A.ntiles + tile) * (long long)kt;
+    if (total <= kt) {
+        int slot = wave_excl_scan(__popc(cm), lane);
+#pragma unroll 1
+        for (int r = 1; r <= kRows - 2; ++r) {
+            if ((cm >> r) & 1u) {
+                int cov;
+                const float v = col[r * kWave + lane];
+                const float s = sn_row(c, v, r, cov);
+                E[slot++] = Entry{s, v, (Y0 + r) * A.w + x, cov};
+            }
+        }
+        return;
+    }
+    // more candidates than kept entries: keep the kt best keys
+    unsigned left = cm;
+#pragma unroll 1
+    for (int k = 0; k < kt; ++k) {
+        unsigned long long best = 0;
+        int bestr = -1;
+#pragma unroll 1
+        for (int r = 1; r <= kRows - 2; ++r) {
+            if ((left >> r) & 1u) {
+                int cov;
+                const unsigned long long key = cand_key(sn_row(c, col[r * kWave + lane], r, cov), (Y0 + r) * A.w + x);
+                if (key > best) {
+                    best = key;
+                    bestr = r;
+                }
+            }
+        }
+        const unsigned long long wb = wave_max_u64(best);
+        if (bestr >= 0 && best == wb) {
+            int cov;
+            const float v = col[bestr * kWave + lane];
+            E[k] = Entry{sn_row(c, v, bestr, cov), v, (Y0 + bestr) * A.w + x, cov};
+            left &= ~(1u << bestr);
+        }
+    }
+}
+
+__device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float (&acc)[kRows], int a, int b, int x,
+                                                bool xin, int lane, int Y0, int tile, float* col) {
+    const bool lane_emit = lane >= 1 && lane <= kWave - 2 && xin;
+    const long long kc = (long long)(b - A.vby0 * kVBY) * A.nvx + a;
+    SnCtx c;
+    c.A = &A;
+    c.b = b;
+    c.Y0 = Y0;
+    c.xlo = A.n;
+    c.xhi = -1;
+    if (xin) load_iv(A.IX, (long long)a * A.w + x, c.xlo, c.xhi);
+    // Fast path: every pixel of the tile sees all n frames (the fully
+    // covered rows form one interval of y, so the two end rows decide), and
+    // V = P[n] - P[0] is the same for the whole tile.
+    int y0lo = A.n, y0hi = -1, y1lo = A.n, y1hi = -1;
+    if (Y0 >= 0 && Y0 < A.h) load_iv(A.IY, (long long)b * A.h + Y0, y0lo, y0hi);
+    if (Y0 + kRows - 1 < A.h) load_iv(A.IY, (long long)b * A.h + Y0 + kRows - 1, y1lo, y1hi);
+    const bool full_y = y0lo == 0 && y0hi == A.n - 1 && y1lo == 0 && y1hi == A.n - 1;
+    c.full = full_y && __all(c.xlo == 0 && c.xhi == A.n - 1);
+    {
+        const double V = A.P[A.n] - A.P[0];
+        c.rs = V > 0.0 ? rsqrtf((float)V) : 0.f;
+    }
+    unsigned fl = 0;
+    if (c.full) {
+        if (A.n >= A.cmin) {
+#pragma unroll
+            for (int r = 1; r <= kRows - 2; ++r)
+                if (lane_emit && Y0 + r < A.h && acc[r] * c.rs > A.thr) fl |= 1u << r;
+        }
+    } else {
+#pragma unroll
+        for (int r = 1; r <= kRows - 2; ++r) {
+            int cov;
+            const float s = sn_row(c, acc[r], r, cov);
+            if (lane_emit && Y0 + r < A.h && cov >= A.cmin && s > A.thr) fl |= 1u << r;
+            // bound the number of prefix-sum loads in flight
+            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (__ballot(fl != 0) == 0) {
+        if (lane == 0) A.tcount[kc * A.ntiles + tile] = 0;
+        return;
+    }
+    // Rare path (some pixel of this wave's column block clears the
+    // threshold): park the sums in this wave's LDS slot and work from there
+    // with runtime row loops, which keeps this code's register use small.
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) col[r * kWave + lane] = acc[r];
+    candidates_from_column(c, col, fl, lane, x, Y0, tile, kc);
+}
+
+template <bool DETECT, bool STAGED>
+__global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
+    // staging buffers during the frame loop; afterwards each wave's slot of
+    // kRows x 64 floats for the candidate search
+    constexpr int kLdsFloats = (2 * kLdsBuf > kWaves * kRows * kWave) ? 2 * kLdsBuf : kWaves * kRows * kWave;
+    __shared__ __attribute__((aligned(16))) float lds[kLdsFloats];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nvb = A.nvbx * A.nvby;
+    const int logical = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = logical / nvb;
+    const int vb = logical - tile * nvb;
+    const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
+    const int a0 = (vb % A.nvbx) * kVBX;
+    const int b0 = (A.vby0 + vb / A.nvbx) * kVBY;
+    const int aw = a0 + kVPW * (wave / kVBY);  // this wave's first x velocity
+    const int b = b0 + wave % kVBY;            // this wave's velocity row
+    const int X0 = tx * A.step_x - A.halo;
+    const int Y0 = ty * A.step_y - A.halo;
+
+    float acc[kVPW][kRows];
+#pragma unroll
+    for (int q = 0; q < kVPW; ++q)
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) acc[q][r] = 0.f;
+
+    if constexpr (STAGED) {
+        const StageMap sm = stage_map(A.Wp);
+        f4 st[kStage];
+        FrameGeom g = frame_geom(A, 0, a0, b0, wave, X0, Y0);
+        stage_load(A, g, sm, st);
+        stage_store(lds, sm, st);
+        __syncthreads();
+        for (int i = 0; i < A.n; ++i) {
+            const float* buf = lds + (i & 1) * kLdsBuf;
+            FrameGeom gn;
+            const bool more = i + 1 < A.n;
+            if (more) {
+                gn = frame_geom(A, i + 1, a0, b0, wave, X0, Y0);
+                stage_load(A, gn, sm, st);
+            }
+            const int rowb = (g.dyw - g.dymin) * kLdsPitch + g.c0 - g.dxmin;
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q) {
+                const float* p = buf + (rowb + g.dxw[q]) + lane;
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) acc[q][r] += p[r * kLdsPitch];
+                // keep at most one velocity's row loads in flight
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (more) {
+                stage_store(lds + ((i + 1) & 1) * kLdsBuf, sm, st);
+                g = gn;
+            }
+            __syncthreads();
+        }
+    } else {
+        // Direct path for velocity blocks whose shift spread does not fit the
+        // LDS region: every sample is read from the padded copy through L2.
+        for (int i = 0; i < A.n; ++i) {
+            const int* rx = A.DX + (long long)i * A.ldx + aw;
+            const int dyw = A.DY[(long long)i * A.ldy + b];
+            const float* base = A.pad + (long long)i * A.fstride + (long long)(Y0 + dyw + A.padT) * A.Wp +
+                                (X0 + lane + A.padL);
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q) {
+                const float* p = base + rx[q];
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) acc[q][r] += p[(long long)r * A.Wp];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+
+    const int x = X0 + lane;
+    const bool xin = x >= 0 && x < A.w;
+
+    if constexpr (!DETECT) {
+        // plain stack: SUM or MEAN, optional coverage
+        if (b >= A.nvy || !xin) return;
+        const bool need_c = A.mean || A.cov != nullptr;
+#pragma unroll
+        for (int q = 0; q < kVPW; ++q) {
+            const int a = aw + q;
+            if (a < A.nvx) {
+                const long long kk = (long long)b * A.nvx + a;
+                int xlo = 0, xhi = -1;
+                if (need_c) load_iv(A.IX, (long long)a * A.w + x, xlo, xhi);
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) {
+                    const int y = Y0 + r;
+                    if (y < A.h) {
+                        float v = acc[q][r];
+                        int c = 0;
+                        if (need_c) {
+                            int lo, hi;
+                            int ylo, yhi;
+                            load_iv(A.IY, (long long)b * A.h + y, ylo, yhi);
+                            c = max(0, coverage(xlo, xhi, ylo, yhi, lo, hi));
+                        }
+                        if (A.mean) v = c > 0 ? v / (float)c : 0.f;
+                        const long long o = (kk * A.h + y) * A.w + x;
+                        A.out[o] = v;
+                        if (A.cov) A.cov[o] = c;
+                    }
+                    if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return;
+    } else {
+        if (b >= A.nvy) return;
+        // written out (not a loop) so that acc stays in registers: the
+        // epilogue is too large for the unroller to replicate
+        static_assert(kVPW == 3, "one call per velocity of the wave");
+        float* col = lds + wave * (kRows * kWave);
+        if (aw + 0 < A.nvx) detect_epilogue(A, acc[0], aw + 0, b, x, xin, lane, Y0, tile, col);
+        __builtin_amdgcn_sched_barrier(0);
+        if (aw + 1 < A.nvx) detect_epilogue(A, acc[1], aw + 1, b, x, xin, lane, Y0, tile, col);
+        __builtin_amdgcn_sched_barrier(0);
+        if (aw + 2 < A.nvx) detect_epilogue(A, acc[2], aw + 2, b, x, xin, lane, Y0, tile, col);
+    }
+}
+
+// ------------------------------------------------------------------ merge
+// One workgroup per velocity: gather the entries kept by every tile, rank
+// them by key and write the first k_max in order; count = all candidates.
+__global__ __launch_bounds__(kAux) void k_merge(const int32_t* __restrict__ tcount, const Entry* __restrict__ ent,
+                                                   int ntiles, int kt, int k_max, int nvx, int w, int k_first,
+                                                   sst_candidate* __restrict__ cand, int32_t* __restrict__ count) {
+    const int kc = blockIdx.x;
+    const int k = k_first + kc;
+    __shared__ unsigned long long keys[kMergeLds];
+    __shared__ int idx[kMergeLds];
+    __shared__ int nst;
+    __shared__ long long shl[4];
+    __shared__ unsigned long long bk[4];
+    __shared__ long long bi[4];
+    if (threadIdx.x == 0) nst = 0;
+    __syncthreads();
+    const int32_t* tc = tcount + (long long)kc * ntiles;
+    const Entry* E = ent + (long long)kc * ntiles * kt;
+    long long tot = 0;
+    for (int t = threadIdx.x; t < ntiles; t += kAux) {
+        const int c = tc[t];
+        tot += c;
+        const int s = min(c, kt);
+        for (int e = 0; e < s; ++e) {
+            const int slot = atomicAdd(&nst, 1);
+            if (slot < kMergeLds) {
+                const Entry en = E[(long long)t * kt + e];
+                keys[slot] = cand_key(en.sn, en.raster);
+                idx[slot] = t * kt + e;
+            }
+        }
+    }
+    tot = block_sum_i64(tot, shl);  // contains barriers: LDS gathers are complete
+    const int m = nst;
+    const int nout = min(k_max, m);
+    sst_candidate* out = cand + (long long)k * k_max;
+    const int ivx = k % nvx, ivy = k / nvx;
+    auto emit = [&](const Entry& en, int r) {
+        sst_candidate o;
+        o.ivx = ivx;
+        o.ivy = ivy;
+        o.x = en.raster % w;
+        o.y = en.raster / w;
+        o.snr = en.sn;
+        o.flux = en.flux;
+        o.coverage = en.cov;
+        o.rank = r;
+        out[r] = o;
+    };
+    if (m <= kMergeLds) {
+        for (int e = threadIdx.x; e < m; e += kAux) {
+            const unsigned long long ke = keys[e];
+            int r = 0;
+            for (int f = 0; f < m; ++f) r += keys[f] > ke ? 1 : 0;
+            if (r < k_max) emit(E[idx[e]], r);
+        }
+    } else {
+        unsigned long long prev = ~0ull;
+        for (int r = 0; r < nout; ++r) {
+            unsigned long long best = 0;
+            long long bidx = -1;
+            for (int t = threadIdx.x; t < ntiles; t += kAux) {
+                const int s = min(tc[t], kt);
+                for (int e = 0; e < s; ++e) {
+                    const Entry en = E[(long long)t * kt + e];
+                    const unsigned long long key = cand_key(en.sn, en.raster);
+                    if (key < prev && key > best) {
+                        best = key;
+                        bidx = (long long)t * kt + e;
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned long long tk = __shfl_xor(best, o);
+                const long long ti = __shfl_xor(bidx, o);
+                if (tk > best) {
+                    best = tk;
+                    bidx = ti;
+                }
+            }
+            if ((threadIdx.x & 63) == 0) {
+                bk[threadIdx.x >> 6] = best;
+                bi[threadIdx.x >> 6] = bidx;
+            }
+            __syncthreads();
+            unsigned long long gb = bk[0];
+            long long gi = bi[0];
+            for (int wv = 1; wv < 4; ++wv)
+                if (bk[wv] > gb) {
+                    gb = bk[wv];
+                    gi = bi[wv];
+                }
+            if (threadIdx.x == 0) emit(E[gi], r);
+            prev = gb;
+            __syncthreads();
+        }
+    }
+    for (int r = nout + threadIdx.x; r < k_max; r += kAux) {
+        sst_candidate o;
+        o.ivx = ivx;
+        o.ivy = ivy;
+        o.x = -1;
+        o.y = -1;
+        o.snr = -INFINITY;
+        o.flux = 0.f;
+        o.coverage = 0;
+        o.rank = -1;
+        out[r] = o;
+    }
+    if (threadIdx.x == 0) count[k] = (int32_t)min(tot, (long long)INT_MAX);
+}
+
+// ------------------------------------------------------------- launchers
+hipError_t launch_stats(const float* frames, int n, int h, int w, double* part, int nchunk, double* b, double* s2,
+                        float* b32, double* P, double* stats_dev, hipStream_t s) {
+    const long long npx = (long long)h * w;
+    hipLaunchKernelGGL(k_stats_partial, dim3(nchunk, n), dim3(kAux), 0, s, frames, npx, nchunk, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kAux), 0, s, part, nchunk, n, npx, b, s2, b32, P,
+                       stats_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
+    const int c4 = a.Wp / 4;
+    hipLaunchKernelGGL(k_prep, dim3((c4 + kAux - 1) / kAux, a.Hp, a.n), dim3(kAux), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cov(const int* D, int ld, int n, int nv, int size, int* I, hipStream_t s) {
+    hipLaunchKernelGGL(k_cov, dim3((size + kAux - 1) / kAux, nv), dim3(kAux), 0, s, D, ld, n, size, I);
+    return hipGetLastError();
+}
+
+hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, hipStream_t s) {
+    const long long groups = (long long)a.tiles_x * a.tiles_y * a.nvbx * a.nvby;
+    const dim3 grid((unsigned)groups), block(kThreads);
+    if (detect) {
+        if (staged)
+            hipLaunchKernelGGL((k_stack<true, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_stack<true, false>), grid, block, 0, s, a);
+    } else {
+        if (staged)
+            hipLaunchKernelGGL((k_stack<false, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((k_stack<false, false>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int ntiles, int kt, int k_max, int nvx, int w,
+                        int k_first, int nk, void* cand, int32_t* count, hipStream_t s) {
+    hipLaunchKernelGGL(k_merge, dim3(nk), dim3(kAux), 0, s, tcount, ent, ntiles, kt, k_max, nvx, w, k_first,
+                       static_cast<sst_candidate*>(cand), count);
+    return hipGetLastError();
+}
+
+}  // namespace sst

@@ -1,0 +1,201 @@
+"""Host-side tests of the C-ABI library (no GPU needed).
+
+The library must load and export every function the public header declares.
+Its host logic is tested without device work: the shift table against the
+oracle (bit-exact), workspace sizing, and every argument check, which the
+library performs before it touches the device (so fake device pointers are
+never dereferenced).
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2303_07293_amd as sst
+from paper_2303_07293_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sst.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB):
+        pytest.skip("libsst.so not built (run __graft_entry__.build())")
+    return sst.load()
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sst_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for name in ("sst_stack", "sst_detect", "sst_shift_table", "sst_workspace_bytes", "sst_frame_stats",
+                 "sst_last_error"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    for name in B.EXPORTS:
+        assert name in header_functions()
+
+
+def test_candidate_record_layout():
+    assert B.CANDIDATE_DTYPE.itemsize == 32
+    src = open(HEADER).read()
+    assert "typedef struct sst_candidate" in src
+
+
+# ------------------------------------------------------------ shift tables
+SHIFT_CASES = [
+    (np.array([0.0, 0.5, 1.0, 1.5, 2.0, 2.5]), 0.0, np.array([1.0, -1.0, 0.5, -0.5, 3.0, -3.0, 0.0])),
+    (np.array([0.0, 0.25, 0.75, 1.0]), 0.5, np.array([2.0, -2.0, 1.0, -6.0])),
+    (np.array([-3.0, -1.0, 1e-9, 2.0]), -1.0, np.array([0.49999999999999994, 1.5, -2.5, 1e6])),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SHIFT_CASES)))
+def test_shift_table_bit_exact_vs_oracle(lib, case):
+    t, t_ref, v = SHIFT_CASES[case]
+    got = sst.sst_shift_table(t, t_ref, v)
+    want = oracle.shift_table(t, t_ref, v)
+    assert np.array_equal(got, want.astype(np.int32))
+
+
+def test_shift_table_bit_exact_on_configs(lib):
+    f1 = synth.config1(noise=False)
+    assert np.array_equal(sst.sst_shift_table(f1.t, f1.t_ref, f1.vx), oracle.shift_table(f1.t, f1.t_ref, f1.vx))
+    rng = np.random.default_rng(synth.SEED_BASE + 2)
+    t2 = synth.fields.config2_times(rng)
+    v2 = np.arange(-40, 41, dtype=np.float64)
+    assert np.array_equal(sst.sst_shift_table(t2, t2[0], v2), oracle.shift_table(t2, t2[0], v2))
+
+
+def test_shift_table_random_irregular(lib):
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        n = int(rng.integers(1, 50))
+        t = np.cumsum(rng.uniform(1e-3, 2.0, size=n))
+        t_ref = float(rng.uniform(t[0] - 1, t[-1] + 1))
+        v = rng.normal(0, 30, size=int(rng.integers(1, 40)))
+        # half-integer products: exact ties
+        v[:3] = [0.5, -0.5, 2.5]
+        assert np.array_equal(sst.sst_shift_table(t, t_ref, v), oracle.shift_table(t, t_ref, v))
+
+
+# ------------------------------------------------------------ error paths
+def test_shift_table_errors(lib):
+    with pytest.raises(sst.SstError) as e:
+        sst.sst_shift_table([0.0, 1.0, 1.0], 0.0, [1.0])
+    assert e.value.code == B.SST_E_UNSORTED
+    with pytest.raises(sst.SstError) as e:
+        sst.sst_shift_table([0.0, np.nan], 0.0, [1.0])
+    assert e.value.code == B.SST_E_ARG
+    with pytest.raises(sst.SstError) as e:
+        sst.sst_shift_table([0.0, 1.0], 0.0, [np.inf])
+    assert e.value.code == B.SST_E_ARG
+    with pytest.raises(sst.SstError) as e:
+        sst.sst_shift_table([0.0, 1e10], 0.0, [1.0])
+    assert e.value.code == B.SST_E_RANGE
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+FAKE = ctypes.c_void_p(4096)  # never dereferenced: every failing check runs first
+
+
+def _detect(lib, n=4, h=8, w=8, t=None, vx=None, vy=None, thr=5.0, kmax=4, ws=FAKE, wsb=1 << 40, frames=FAKE,
+            dtype=0, cand=FAKE, count=FAKE, cmin=0):
+    t = np.arange(n, dtype=np.float64) if t is None else np.asarray(t, np.float64)
+    vx = np.array([0.0, 1.0]) if vx is None else np.asarray(vx, np.float64)
+    vy = np.array([0.0]) if vy is None else np.asarray(vy, np.float64)
+    return lib.sst_detect(frames, dtype, None, n, h, w, _p(t), 0.0, _p(vx), len(vx), _p(vy), len(vy), thr, cmin, kmax,
+                          cand, count, None, ws, wsb, None)
+
+
+def test_detect_argument_errors(lib):
+    assert _detect(lib, frames=None) == B.SST_E_ARG
+    assert _detect(lib, cand=None) == B.SST_E_ARG
+    assert _detect(lib, n=0) == B.SST_E_ARG
+    assert _detect(lib, h=0) == B.SST_E_ARG
+    assert _detect(lib, w=20000) == B.SST_E_ARG
+    assert _detect(lib, t=[0.0, 2.0, 1.0, 3.0]) == B.SST_E_UNSORTED
+    assert _detect(lib, t=[0.0, 1.0, 2.0, np.inf]) == B.SST_E_ARG
+    assert _detect(lib, vx=[np.nan]) == B.SST_E_ARG
+    assert _detect(lib, vx=[1e12]) == B.SST_E_RANGE
+    assert _detect(lib, thr=float("nan")) == B.SST_E_ARG
+    assert _detect(lib, kmax=0) == B.SST_E_ARG
+    assert _detect(lib, kmax=5000) == B.SST_E_ARG
+    assert _detect(lib, dtype=7) == B.SST_E_ARG
+    assert _detect(lib, ws=None) == B.SST_E_WORKSPACE
+    assert _detect(lib, wsb=100) == B.SST_E_WORKSPACE
+    assert "workspace" in sst.sst_last_error()
+    assert _detect(lib, ws=ctypes.c_void_p(4096 + 4)) == B.SST_E_WORKSPACE
+
+
+def test_stack_argument_errors(lib):
+    t = np.arange(3, dtype=np.float64)
+    v = np.array([0.0, 1.0])
+    bg = np.array([1.0, np.nan, 2.0])
+
+    def call(frames=FAKE, out=FAKE, mode=0, bgv=None, wsb=1 << 40):
+        return lib.sst_stack(frames, 0, None, 3, 5, 5, _p(t), 0.0, _p(v), 2, _p(v), 2,
+                             None if bgv is None else _p(bgv), mode, out, None, FAKE, wsb, None)
+    assert call(frames=None) == B.SST_E_ARG
+    assert call(out=None) == B.SST_E_ARG
+    assert call(mode=3) == B.SST_E_ARG
+    assert call(bgv=bg) == B.SST_E_ARG
+    assert call(wsb=10) == B.SST_E_WORKSPACE
+
+
+def test_frame_stats_argument_errors(lib):
+    assert lib.sst_frame_stats(None, 0, None, 2, 4, 4, FAKE, FAKE, 1 << 30, None) == B.SST_E_ARG
+    assert lib.sst_frame_stats(FAKE, 0, None, 2, 4, 4, None, FAKE, 1 << 30, None) == B.SST_E_ARG
+    assert lib.sst_frame_stats(FAKE, 0, None, 2, 4, 4, FAKE, FAKE, 8, None) == B.SST_E_WORKSPACE
+
+
+def test_workspace_bytes(lib):
+    t = np.arange(8, dtype=np.float64) / 7
+    v = np.arange(-3, 4, dtype=np.float64)
+    a = sst.sst_workspace_bytes(sst.SST_OP_DETECT, 8, 100, 120, t, 0.0, v, v, 16)
+    b = sst.sst_workspace_bytes(sst.SST_OP_DETECT, 8, 100, 120, t, 0.0, v, v, 32)
+    s = sst.sst_workspace_bytes(sst.SST_OP_STACK, 8, 100, 120, t, 0.0, v, v)
+    st = sst.sst_workspace_bytes(sst.SST_OP_STATS, 8, 100, 120)
+    assert a > s > 0 and b > a and st > 0
+    # the padded frame copy grows with the largest shift
+    big = sst.sst_workspace_bytes(sst.SST_OP_STACK, 8, 100, 120, t, 0.0, v * 10, v)
+    assert big > s
+    # full-field config fits comfortably in one MI355X's HBM
+    rng = np.random.default_rng(synth.SEED_BASE + 2)
+    t2 = synth.fields.config2_times(rng)
+    g = np.arange(-40, 41, dtype=np.float64)
+    nb = sst.sst_workspace_bytes(sst.SST_OP_DETECT, 64, 1024, 1024, t2, t2[0], g, g, 64)
+    assert nb < 4 << 30
+    with pytest.raises(sst.SstError):
+        sst.sst_workspace_bytes(sst.SST_OP_DETECT, 8, 100, 120, t[::-1], 0.0, v, v, 16)
+    with pytest.raises(sst.SstError):
+        sst.sst_workspace_bytes(9, 8, 100, 120, t, 0.0, v, v, 16)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    import importlib
+    saved = B._lib
+    try:
+        B._lib = None
+        with pytest.raises(RuntimeError):
+            B.load(str(tmp_path / "missing.so"))
+    finally:
+        B._lib = saved
+    importlib.reload  # keep linters quiet

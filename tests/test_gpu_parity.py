@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 oracle.
+
+Tolerances and the marginal-decision rule are derived in tests/parity.py.
+Integer outputs (coverage, pixel positions, ranks, counts, velocity indices)
+must match exactly except for decisions the derivation marks as marginal;
+the tests also bound how many such decisions may occur.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sst_oracle as so
+import synth
+from parity import compare_velocity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def sst():
+    _need_gpu()
+    import paper_2303_07293_amd as m
+    m.load()
+    return m
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(frames):
+    return torch.from_numpy(np.ascontiguousarray(frames)).to("cuda:0")
+
+
+# ------------------------------------------------------------ frame stats
+def test_frame_stats_match_oracle(sst):
+    f = synth.small_case(1, 9, 77, 131, 1, 1, sky=100.0, sigma=10.0)
+    _say(f"case {f.name}")
+    st = sst.sst_frame_stats(_dev(f.frames)).cpu().numpy()
+    b, s2 = oracle.frame_stats(f.frames)
+    assert np.allclose(st[:, 0], b, rtol=1e-13, atol=0)
+    assert np.allclose(st[:, 1], s2, rtol=1e-11, atol=0)
+
+
+# --------------------------------------------------------------- stacking
+def _check_stack(sst, f, bg=None, mode="sum", velocities=None):
+    fr = _dev(f.frames)
+    m = sst.SST_MEAN if mode == "mean" else sst.SST_SUM
+    out, cov = sst.sst_stack(fr, f.t, f.t_ref, f.vx, f.vy, bg=bg, mode=m, with_coverage=True)
+    torch.cuda.synchronize()
+    dx = oracle.shift_table(f.t, f.t_ref, f.vx)
+    dy = oracle.shift_table(f.t, f.t_ref, f.vy)
+    nvx = len(f.vx)
+    ks = range(nvx * len(f.vy)) if velocities is None else velocities
+    worst = 0.0
+    for k in ks:
+        a, b = k % nvx, k // nvx
+        S, c, _, A = so.stack_velocity(f.frames, dx[:, a], dy[:, b], offsets=bg, absolute=True)
+        g = out[b, a].cpu().numpy().astype(np.float64)
+        gc = cov[b, a].cpu().numpy()
+        assert np.array_equal(gc, c), (k, np.argwhere(gc != c)[:5])
+        if mode == "mean":
+            ref = np.where(c > 0, S / np.maximum(c, 1), 0.0)
+            tol = 1e-5 * np.where(c > 0, A / np.maximum(c, 1), 0.0) + 1e-30
+        else:
+            ref = S
+            tol = 1e-5 * A + 1e-30
+        err = np.abs(g - ref)
+        assert np.all(err <= tol), (k, float((err / tol).max()))
+        worst = max(worst, float((err / np.maximum(A, 1e-30)).max()))
+    return worst
+
+
+def test_stack_tiny_config_sum_and_mean(sst):
+    f = synth.config1()
+    _say(f"case {f.name} sum")
+    w1 = _check_stack(sst, f)
+    _say(f"case {f.name} mean")
+    _check_stack(sst, f, mode="mean")
+    _say(f"max |dS|/A = {w1:.3g}")
+
+
+@pytest.mark.parametrize("seed,n,h,w,nvx,nvy,vmax", [
+    (10, 1, 33, 65, 3, 2, 2.0),     # one frame
+    (11, 7, 70, 130, 7, 5, 3.0),    # ragged tiles and velocity blocks
+    (12, 5, 3, 5, 4, 3, 2.0),       # frame smaller than a tile
+    (13, 9, 64, 64, 6, 4, 1.5),     # exact tile multiple
+    (14, 6, 40, 200, 5, 9, 40.0),   # large shifts: most samples outside
+])
+def test_stack_small_cases(sst, seed, n, h, w, nvx, nvy, vmax):
+    f = synth.small_case(seed, n, h, w, nvx, nvy, vmax=vmax, sky=20.0, sigma=3.0)
+    _say(f"case {f.name}")
+    _check_stack(sst, f)
+    rng = np.random.default_rng(seed)
+    _check_stack(sst, f, bg=rng.normal(20.0, 2.0, size=n), mode="mean")
+
+
+def test_stack_direct_path(sst):
+    """Velocity steps of 25 px/h over 2 h spread a block's shifts beyond the
+    LDS window, which sends the whole call down the direct (L2) path."""
+    rng = np.random.default_rng(5)
+    n, h, w = 6, 50, 90
+    t = np.linspace(0, 2.0, n)
+    frames = rng.normal(5, 1, size=(n, h, w)).astype(np.float32)
+    f = synth.Field("direct", frames, t, 0.7, np.arange(-3, 4) * 25.0, np.arange(-2, 2) * 13.0)
+    _say("case direct path")
+    _check_stack(sst, f)
+
+
+# -------------------------------------------------------------- detection
+def _check_detect(sst, f, thr, cmin, kmax, velocities=None, max_marginal=0):
+    fr = _dev(f.frames)
+    cand, count, stats = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax, want_stats=True)
+    torch.cuda.synchronize()
+    got = sst.candidates_to_numpy(cand)
+    cnt = count.cpu().numpy()
+    b, s2 = oracle.frame_stats(f.frames)
+    assert np.allclose(stats[:, 0], b, rtol=1e-13) and np.allclose(stats[:, 1], s2, rtol=1e-11)
+    nvx = len(f.vx)
+    ks = list(range(nvx * len(f.vy))) if velocities is None else list(velocities)
+    ref = oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax, velocities=ks, keep_maps=True)
+    c_min = ref["c_min"]
+    bmax = float(np.abs(b).max())
+    marg = 0
+    for k in ks:
+        g = got[k]
+        assert np.all(g["ivx"] == k % nvx) and np.all(g["ivy"] == k // nvx)
+        marg += compare_velocity(g, int(cnt[k]), ref[k], f.n, bmax, thr, c_min, kmax, f.w)
+    _say(f"  {len(ks)} velocities, {int(cnt[ks].sum())} candidates, {marg} marginal decisions")
+    assert marg <= max_marginal
+    return got, cnt
+
+
+def test_detect_tiny_config(sst):
+    f = synth.config1()
+    _say(f"case {f.name}")
+    got, cnt = _check_detect(sst, f, f.threshold, f.min_coverage, f.k_max)
+    # every injected mover is detected at its true velocity bin, within 1 px
+    for mv in f.movers:
+        k = (int(mv.vy) + 10) * 21 + int(mv.vx) + 10
+        g = got[k][: min(cnt[k], 64)]
+        d = np.hypot(g["x"] - mv.x0, g["y"] - mv.y0)
+        assert len(d) and d.min() <= 1.5, (mv, g[:3])
+
+
+@pytest.mark.parametrize("seed,n,h,w,nvx,nvy,vmax,sky", [
+    (20, 1, 40, 70, 2, 3, 2.0, 0.0),
+    (21, 8, 70, 130, 7, 5, 3.0, 50.0),
+    (22, 5, 3, 5, 3, 3, 2.0, 1.0),
+    (23, 12, 97, 61, 6, 4, 4.0, 100.0),
+    (24, 6, 40, 200, 5, 9, 40.0, 10.0),
+])
+def test_detect_small_cases(sst, seed, n, h, w, nvx, nvy, vmax, sky):
+    f = synth.small_case(seed, n, h, w, nvx, nvy, vmax=vmax, sky=sky, sigma=2.0, ties=(seed % 2 == 0))
+    _say(f"case {f.name}")
+    _check_detect(sst, f, 2.5, 0, 6)
+
+
+def test_detect_many_candidates_truncation_and_merge(sst):
+    """A threshold far below the noise makes almost every local maximum a
+    candidate: tiles hold more candidates than they keep (kt), and each
+    velocity has more kept entries than the merge ranks in LDS."""
+    f = synth.pure_noise(3, 6, 300, 420, sigma=1.0, sky=3.0)
+    f.vx = np.array([0.0, 1.0])
+    f.vy = np.array([-1.0, 0.0])
+    _say("case many candidates")
+    _check_detect(sst, f, -100.0, 0, 40, max_marginal=50)
+    _check_detect(sst, f, -100.0, 0, 1, max_marginal=50)
+
+
+def test_detect_constant_frames(sst):
+    """Zero-variance frames: V = 0 gives S/N 0 everywhere; with threshold -1
+    the only candidate is the raster-first pixel of the flat plateau."""
+    n, h, w = 4, 20, 30
+    frames = np.full((n, h, w), 7.0, np.float32)
+    f = synth.Field("flat", frames, np.arange(n, dtype=np.float64), 0.0, np.array([0.0]), np.array([0.0]))
+    cand, count = sst.sst_detect(_dev(frames), f.t, 0.0, f.vx, f.vy, -1.0, 0, 4)
+    g = sst.candidates_to_numpy(cand)[0]
+    assert int(count.cpu()[0]) == 1 and (g["x"][0], g["y"][0]) == (0, 0) and g["snr"][0] == 0.0
+
+
+def test_detect_repeatable_bitwise(sst):
+    f = synth.small_case(30, 10, 90, 150, 6, 4, vmax=3.0, sky=10.0)
+    fr = _dev(f.frames)
+    c1, n1 = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, 2.0, 0, 16)
+    c2, n2 = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, 2.0, 0, 16)
+    assert torch.equal(c1, c2) and torch.equal(n1, n2)
+    o1 = sst.sst_stack(fr, f.t, f.t_ref, f.vx, f.vy)
+    o2 = sst.sst_stack(fr, f.t, f.t_ref, f.vx, f.vy)
+    assert torch.equal(o1, o2)
+
+
+@pytest.mark.slow
+def test_detect_full_field_sampled(sst):
+    """The full field (64 x 1024^2, 81^2 velocities) in the benchmark's launch
+    configuration; sampled velocities checked against the oracle, including
+    the bins nearest the brightest movers."""
+    f = synth.config2()
+    _say(f"case {f.name}")
+    ks = [0, 80, 3280, 6480, 6560, 41 * 81 + 7]
+    movers = sorted(f.movers, key=lambda m: -m.amp)[:6]
+    for m in movers:
+        ks.append((int(round(m.vy)) + 40) * 81 + int(round(m.vx)) + 40)
+    ks = sorted(set(ks))
+    _check_detect(sst, f, f.threshold, f.min_coverage, f.k_max, velocities=ks, max_marginal=2)
+
+
+@pytest.mark.slow
+def test_stack_full_field_sampled(sst):
+    f = synth.config2()
+    _say(f"case {f.name} stack")
+    _check_stack(sst, f, velocities=[0, 3280, 6560, 100])
