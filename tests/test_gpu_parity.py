@@ -70,12 +70,15 @@ def _check_stack(sst, f, bg=None, mode="sum", velocities=None):
         g = out[b, a].cpu().numpy().astype(np.float64)
         gc = cov[b, a].cpu().numpy()
         assert np.array_equal(gc, c), (k, np.argwhere(gc != c)[:5])
+        # 1e-5 of the sum of |terms| (the float32 target), plus the rounding of
+        # a float64 background to float32 once per term (c u |bg|)
+        bgt = 0.0 if bg is None else 2.0 * 2.0 ** -24 * float(np.abs(bg).max())
         if mode == "mean":
             ref = np.where(c > 0, S / np.maximum(c, 1), 0.0)
-            tol = 1e-5 * np.where(c > 0, A / np.maximum(c, 1), 0.0) + 1e-30
+            tol = 1e-5 * np.where(c > 0, A / np.maximum(c, 1), 0.0) + bgt + 1e-30
         else:
             ref = S
-            tol = 1e-5 * A + 1e-30
+            tol = 1e-5 * A + c * bgt + 1e-30
         err = np.abs(g - ref)
         assert np.all(err <= tol), (k, float((err / tol).max()))
         worst = max(worst, float((err / np.maximum(A, 1e-30)).max()))
@@ -164,7 +167,7 @@ def test_detect_tiny_config(sst):
 def test_detect_small_cases(sst, seed, n, h, w, nvx, nvy, vmax, sky):
     f = synth.small_case(seed, n, h, w, nvx, nvy, vmax=vmax, sky=sky, sigma=2.0, ties=(seed % 2 == 0))
     _say(f"case {f.name}")
-    _check_detect(sst, f, 2.5, 0, 6)
+    _check_detect(sst, f, 2.5, 0, 6, max_marginal=4)
 
 
 def test_detect_many_candidates_truncation_and_merge(sst):
