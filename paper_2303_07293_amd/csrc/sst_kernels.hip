@@ -229,82 +229,67 @@ __device__ __forceinline__ int coverage(int xlo, int xhi, int ylo, int yhi, int&
 }
 
 // -------------------------------------------------------------- stacking
-// Frame geometry of one velocity block for one frame.  The staged region is
-// always kLdsRows x kLdsPitch floats starting at the 16-byte aligned column
-// at or left of the block's smallest shift; the padded copy is sized so that
-// this fixed window never leaves it.
-struct FrameGeom {
-    int dxw[kVPW];  // x shifts of this wave's velocities
-    int dyw;        // y shift of this wave's velocity row
-    int dxmin;      // smallest x shift of the block
-    int dymin;
-    int c0;         // LDS column of the region's first needed column
-    long long src;  // element offset of the staged window's origin
-};
+// Per-frame geometry of a workgroup's velocity block, kept in LDS for a
+// chunk of kGeomChunk frames.  For frame i the staged window is the
+// kStageW x kLdsRows region of the padded copy whose origin is the
+// 16-byte aligned column at or left of X0 + (smallest x shift of the block)
+// and the row Y0 + (smallest y shift).  All offsets are in elements.
+constexpr int kGeomChunk = 256;
+constexpr int kGeomInts = 12;  // soff, col[2][3], row[4], 1 spare
+static_assert(kVBX == 2 * kVPW && kVBY == 4 && kWaves == 8, "geometry layout assumed below");
 
-__device__ __forceinline__ FrameGeom frame_geom(const StackArgs& A, int i, int a0, int b0, int wave, int X0,
-                                                int Y0) {
-    FrameGeom g;
-    const int* rx = A.DX + (long long)i * A.ldx + a0;
-    const int* ry = A.DY + (long long)i * A.ldy + b0;
-    const int xg = wave / kVBY;  // which kVPW-group of the block's x velocities
-    int dxmin = rx[0], dymin = ry[0];
+// Fill the geometry of frames [f0, f0 + cnt) (one thread per frame).
+__device__ __forceinline__ void fill_geometry(const StackArgs& A, int* geo, int f0, int cnt, int a0, int b0, int X0,
+                                              int Y0) {
+    const int t = threadIdx.x;
+    if (t < cnt) {
+        const int i = f0 + t;
+        const int* rx = A.DX + (long long)i * A.ldx + a0;
+        const int* ry = A.DY + (long long)i * A.ldy + b0;
+        int dx[kVBX], dy[kVBY];
 #pragma unroll
-    for (int j = 1; j < kVBX; ++j) dxmin = min(dxmin, rx[j]);
+        for (int j = 0; j < kVBX; ++j) dx[j] = rx[j];
 #pragma unroll
-    for (int j = 1; j < kVBY; ++j) dymin = min(dymin, ry[j]);
+        for (int j = 0; j < kVBY; ++j) dy[j] = ry[j];
+        int dxmin = dx[0], dymin = dy[0];
 #pragma unroll
-    for (int q = 0; q < kVPW; ++q) g.dxw[q] = rx[xg * kVPW + q];
-    g.dyw = ry[wave % kVBY];
-    g.dxmin = dxmin;
-    g.dymin = dymin;
-    const int gx0 = X0 + g.dxmin + A.padL;
-    const int xa = gx0 & ~3;
-    g.c0 = gx0 - xa;
-    const int gy0 = Y0 + g.dymin + A.padT;
-    g.src = (long long)i * A.fstride + (long long)gy0 * A.Wp + xa;
-    return g;
-}
-
-constexpr int kC4 = kStageW / 4;                                    // float4 chunks per staged row
-constexpr int kChunks = kC4 * kLdsRows;                              // chunks per staged window
-constexpr int kStage = (kChunks + kThreads - 1) / kThreads;          // chunks per thread
-constexpr bool kStageRagged = kChunks % kThreads != 0;
-
-// Per-thread constant part of the staging addresses: chunk e = tid + j*kThreads
-// is row e / kC4, column 4*(e % kC4) of the window (divisions by constants).
-struct StageMap {
-    unsigned goff[kStage];  // element offset in the padded copy, from the window origin
-    int loff[kStage];       // element offset in an LDS buffer
-    bool last;              // whether this thread has a chunk in the last (ragged) round
-};
-
-__device__ __forceinline__ StageMap stage_map(int Wp) {
-    StageMap m;
+        for (int j = 1; j < kVBX; ++j) dxmin = min(dxmin, dx[j]);
 #pragma unroll
-    for (int j = 0; j < kStage; ++j) {
-        const int e = (int)threadIdx.x + j * kThreads;
-        const int row = e / kC4, c = e % kC4;
-        m.goff[j] = (unsigned)(row * Wp + 4 * c);
-        m.loff[j] = row * kLdsPitch + 4 * c;
+        for (int j = 1; j < kVBY; ++j) dymin = min(dymin, dy[j]);
+        const int gx0 = X0 + dxmin + A.padL;
+        const int xa = gx0 & ~3;
+        const int c0 = gx0 - xa;
+        const int gy0 = Y0 + dymin + A.padT;
+        int* g = geo + t * kGeomInts;
+        g[0] = gy0 * A.Wp + xa;  // window origin within frame i of the padded copy
+#pragma unroll
+        for (int j = 0; j < kVBX; ++j) g[1 + j] = c0 + dx[j] - dxmin;  // LDS column of velocity j
+#pragma unroll
+        for (int j = 0; j < kVBY; ++j) g[1 + kVBX + j] = (dy[j] - dymin) * kLdsPitch;  // LDS row offset
     }
-    m.last = (int)threadIdx.x + (kStage - 1) * kThreads < kChunks;
-    return m;
 }
 
-__device__ __forceinline__ void stage_load(const StackArgs& A, const FrameGeom& g, const StageMap& m,
+constexpr int kC4 = kStageW / 4;  // float4 chunks per staged row
+static_assert(kC4 <= 32 && kLdsRows % (2 * kWaves) == 0, "two staged rows per wave instruction");
+constexpr int kStage = kLdsRows / (2 * kWaves);  // staging loads per thread and frame
+
+// Staging: wave w, load j covers staged row 2*(w + kWaves*j) + (lane >> 5),
+// float4 column lane & 31 (lanes with column >= kC4 idle).  The per-lane part
+// of the address is constant; the frame and j parts are scalar.
+__device__ __forceinline__ void stage_load(__amdgpu_buffer_rsrc_t rsrc, int voff, int soff, int Wp, bool act,
                                            f4 (&st)[kStage]) {
-    const float* src = A.pad + g.src;
 #pragma unroll
     for (int j = 0; j < kStage; ++j) {
-        if (j < kStage - 1 || !kStageRagged || m.last) st[j] = *reinterpret_cast<const f4*>(src + m.goff[j]);
+        if (act)
+            st[j] = __builtin_bit_cast(
+                f4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, (soff + j * 2 * kWaves * Wp) * 4, 0));
     }
 }
 
-__device__ __forceinline__ void stage_store(float* buf, const StageMap& m, const f4 (&st)[kStage]) {
+__device__ __forceinline__ void stage_store(float* buf, int loff, bool act, const f4 (&st)[kStage]) {
 #pragma unroll
     for (int j = 0; j < kStage; ++j) {
-        if (j < kStage - 1 || !kStageRagged || m.last) *reinterpret_cast<f4*>(buf + m.loff[j]) = st[j];
+        if (act) *reinterpret_cast<f4*>(buf + loff + j * 2 * kWaves * kLdsPitch) = st[j];
     }
 }
 
@@ -314,34 +299,41 @@ __device__ __forceinline__ void stage_store(float* buf, const StageMap& m, const
 // The S/N of a row is recomputed where it is needed rather than stored, to
 // keep the register footprint of this epilogue below the main loop's.
 struct SnCtx {
-    const StackArgs* A;
-    int b, Y0, xlo, xhi;
+    const int* IY;    // coverage intervals of y
+    const double* P;  // prefix sums of the frame variances
+    int n, h, b, Y0, xlo, xhi;
     bool full;
     float rs;  // 1/sqrt(V) of a fully covered pixel
 };
 
 __device__ __forceinline__ float sn_row(const SnCtx& c, float acc, int r, int& cov) {
     if (c.full) {
-        cov = c.A->n;
+        cov = c.n;
         return acc * c.rs;
     }
-    const StackArgs& A = *c.A;
     const int y = c.Y0 + r;
-    int ylo = A.n, yhi = -1;
-    if (y >= 0 && y < A.h) load_iv(A.IY, (long long)c.b * A.h + y, ylo, yhi);
+    int ylo = c.n, yhi = -1;
+    if (y >= 0 && y < c.h) load_iv(c.IY, (long long)c.b * c.h + y, ylo, yhi);
     int lo, hi;
     cov = coverage(c.xlo, c.xhi, ylo, yhi, lo, hi);
     if (cov <= 0) return -INFINITY;
-    const double V = A.P[hi + 1] - A.P[lo];
+    const double V = c.P[hi + 1] - c.P[lo];
     return V > 0.0 ? acc * rsqrtf((float)V) : 0.f;
 }
 
+// Where a (tile, velocity) writes its kept candidates.
+struct CandOut {
+    int32_t* tcount;
+    Entry* ent;
+    long long slot;  // (velocity of this launch) * ntiles + tile
+    int kt, w;
+};
+
 // Peak test and candidate output for one (tile, velocity) whose column sums
 // are parked in LDS: col[r * 64 + lane] = S' of row r of this lane's column.
-__device__ __noinline__ void candidates_from_column(const SnCtx c, const float* col, unsigned fl, int lane, int x,
-                                                    int Y0, int tile, long long kc) {
-    const StackArgs& A = *c.A;
-    const int kt = A.kt;
+__device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut o, const float* col, unsigned fl,
+                                                    int lane, int x, int Y0) {
+    const int kt = o.kt;
     // 8-neighbour test with the raster tie rule: neighbours earlier in raster
     // order must be strictly smaller, later ones may tie.
     unsigned cm = 0;
@@ -366,9 +358,9 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const float* 
         R0 = Rp;
     }
     const int total = wave_sum_i32(__popc(cm));
-    if (lane == 0) A.tcount[kc * A.ntiles + tile] = total;
+    if (lane == 0) o.tcount[o.slot] = total;
     if (total == 0) return;
-    Entry* E = A.ent + (kc * A.ntiles + tile) * (long long)kt;
+    Entry* E = o.ent + o.slot * (long long)kt;
     if (total <= kt) {
         int slot = wave_excl_scan(__popc(cm), lane);
 #pragma unroll 1
@@ -377,7 +369,7 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const float* 
                 int cov;
                 const float v = col[r * kWave + lane];
                 const float s = sn_row(c, v, r, cov);
-                E[slot++] = Entry{s, v, (Y0 + r) * A.w + x, cov};
+                E[slot++] = Entry{s, v, (Y0 + r) * o.w + x, cov};
             }
         }
         return;
@@ -392,7 +384,7 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const float* 
         for (int r = 1; r <= kRows - 2; ++r) {
             if ((left >> r) & 1u) {
                 int cov;
-                const unsigned long long key = cand_key(sn_row(c, col[r * kWave + lane], r, cov), (Y0 + r) * A.w + x);
+                const unsigned long long key = cand_key(sn_row(c, col[r * kWave + lane], r, cov), (Y0 + r) * o.w + x);
                 if (key > best) {
                     best = key;
                     bestr = r;
@@ -403,7 +395,7 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const float* 
         if (bestr >= 0 && best == wb) {
             int cov;
             const float v = col[bestr * kWave + lane];
-            E[k] = Entry{sn_row(c, v, bestr, cov), v, (Y0 + bestr) * A.w + x, cov};
+            E[k] = Entry{sn_row(c, v, bestr, cov), v, (Y0 + bestr) * o.w + x, cov};
             left &= ~(1u << bestr);
         }
     }
@@ -414,7 +406,10 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
     const bool lane_emit = lane >= 1 && lane <= kWave - 2 && xin;
     const long long kc = (long long)(b - A.vby0 * kVBY) * A.nvx + a;
     SnCtx c;
-    c.A = &A;
+    c.IY = A.IY;
+    c.P = A.P;
+    c.n = A.n;
+    c.h = A.h;
     c.b = b;
     c.Y0 = Y0;
     c.xlo = A.n;
@@ -449,8 +444,14 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
             if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
     }
+    CandOut o;
+    o.tcount = A.tcount;
+    o.ent = A.ent;
+    o.slot = kc * A.ntiles + tile;
+    o.kt = A.kt;
+    o.w = A.w;
     if (__ballot(fl != 0) == 0) {
-        if (lane == 0) A.tcount[kc * A.ntiles + tile] = 0;
+        if (lane == 0) o.tcount[o.slot] = 0;
         return;
     }
     // Rare path (some pixel of this wave's column block clears the
@@ -458,15 +459,16 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
     // with runtime row loops, which keeps this code's register use small.
 #pragma unroll
     for (int r = 0; r < kRows; ++r) col[r * kWave + lane] = acc[r];
-    candidates_from_column(c, col, fl, lane, x, Y0, tile, kc);
+    candidates_from_column(c, o, col, fl, lane, x, Y0);
 }
 
 template <bool DETECT, bool STAGED>
 __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
-    // staging buffers during the frame loop; afterwards each wave's slot of
-    // kRows x 64 floats for the candidate search
+    // LDS: two staging buffers during the frame loop (afterwards each wave's
+    // slot of kRows x 64 floats for the candidate search) + frame geometry
     constexpr int kLdsFloats = (2 * kLdsBuf > kWaves * kRows * kWave) ? 2 * kLdsBuf : kWaves * kRows * kWave;
     __shared__ __attribute__((aligned(16))) float lds[kLdsFloats];
+    __shared__ int geo[STAGED ? kGeomChunk * kGeomInts : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -477,7 +479,8 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
     const int a0 = (vb % A.nvbx) * kVBX;
     const int b0 = (A.vby0 + vb / A.nvbx) * kVBY;
-    const int aw = a0 + kVPW * (wave / kVBY);  // this wave's first x velocity
+    const int xg = wave / kVBY;                // which kVPW-group of the block's x velocities
+    const int aw = a0 + kVPW * xg;             // this wave's first x velocity
     const int b = b0 + wave % kVBY;            // this wave's velocity row
     const int X0 = tx * A.step_x - A.halo;
     const int Y0 = ty * A.step_y - A.halo;
@@ -489,34 +492,50 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
         for (int r = 0; r < kRows; ++r) acc[q][r] = 0.f;
 
     if constexpr (STAGED) {
-        const StageMap sm = stage_map(A.Wp);
+        const int srow = 2 * wave + (lane >> 5);  // staged row of this lane's first load
+        const int scol = lane & 31;               // float4 column
+        const bool act = scol < kC4;
+        const int voff = (srow * A.Wp + 4 * scol) * 4;  // bytes, per lane
+        const int loff = srow * kLdsPitch + 4 * scol;   // floats, per lane
+        const unsigned fbytes = (unsigned)min((long long)A.fstride * 4, 0x7FFFFFFFll);
+        int f0 = 0;
+        fill_geometry(A, geo, 0, min(A.n, kGeomChunk), a0, b0, X0, Y0);
+        __syncthreads();
         f4 st[kStage];
-        FrameGeom g = frame_geom(A, 0, a0, b0, wave, X0, Y0);
-        stage_load(A, g, sm, st);
-        stage_store(lds, sm, st);
+        {
+            const __amdgpu_buffer_rsrc_t r0 = __builtin_amdgcn_make_buffer_rsrc((void*)A.pad, 0, fbytes, 0x00020000);
+            stage_load(r0, voff, __builtin_amdgcn_readfirstlane(geo[0]), A.Wp, act, st);
+            stage_store(lds, loff, act, st);
+        }
         __syncthreads();
         for (int i = 0; i < A.n; ++i) {
             const float* buf = lds + (i & 1) * kLdsBuf;
-            FrameGeom gn;
             const bool more = i + 1 < A.n;
             if (more) {
-                gn = frame_geom(A, i + 1, a0, b0, wave, X0, Y0);
-                stage_load(A, gn, sm, st);
+                const int gi = (i + 1 - f0) * kGeomInts;
+                const __amdgpu_buffer_rsrc_t rn = __builtin_amdgcn_make_buffer_rsrc(
+                    (void*)(A.pad + (long long)(i + 1) * A.fstride), 0, fbytes, 0x00020000);
+                stage_load(rn, voff, __builtin_amdgcn_readfirstlane(geo[gi]), A.Wp, act, st);
             }
-            const int rowb = (g.dyw - g.dymin) * kLdsPitch + g.c0 - g.dxmin;
+            const int* g = geo + (i - f0) * kGeomInts;
+            const int rowb = __builtin_amdgcn_readfirstlane(g[1 + kVBX + wave % kVBY]);
 #pragma unroll
             for (int q = 0; q < kVPW; ++q) {
-                const float* p = buf + (rowb + g.dxw[q]) + lane;
+                const int colq = __builtin_amdgcn_readfirstlane(g[1 + kVPW * xg + q]);
+                const float* p = buf + (rowb + colq) + lane;
 #pragma unroll
                 for (int r = 0; r < kRows; ++r) acc[q][r] += p[r * kLdsPitch];
                 // keep at most one velocity's row loads in flight
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (more) {
-                stage_store(lds + ((i + 1) & 1) * kLdsBuf, sm, st);
-                g = gn;
-            }
+            if (more) stage_store(lds + ((i + 1) & 1) * kLdsBuf, loff, act, st);
             __syncthreads();
+            // next geometry chunk: must hold frames i + 1 and i + 2
+            if (i + 2 < A.n && i + 2 == f0 + kGeomChunk) {
+                f0 = i + 1;
+                fill_geometry(A, geo, f0, min(A.n - f0, kGeomChunk), a0, b0, X0, Y0);
+                __syncthreads();
+            }
         }
     } else {
         // Direct path for velocity blocks whose shift spread does not fit the
