@@ -498,41 +498,74 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
         const int voff = (srow * A.Wp + 4 * scol) * 4;  // bytes, per lane
         const int loff = srow * kLdsPitch + 4 * scol;   // floats, per lane
         const unsigned fbytes = (unsigned)min((long long)A.fstride * 4, 0x7FFFFFFFll);
+        const int last = A.n - 1;
         int f0 = 0;
         fill_geometry(A, geo, 0, min(A.n, kGeomChunk), a0, b0, X0, Y0);
         __syncthreads();
+        // this wave's geometry of frame i: LDS row offset and the kVPW column
+        // offsets, plus the staging window origin of frame i + 1
+        const int gw_row = 1 + kVBX + wave % kVBY, gw_col = 1 + kVPW * xg;
+        auto geom = [&](int i, int& rowb, int (&col)[kVPW]) {
+            const int* g = geo + (i - f0) * kGeomInts;
+            rowb = __builtin_amdgcn_readfirstlane(g[gw_row]);
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(g[gw_col + q]);
+        };
+        auto frame_rsrc = [&](int i) {
+            return __builtin_amdgcn_make_buffer_rsrc((void*)(A.pad + (long long)i * A.fstride), 0, fbytes, 0x00020000);
+        };
         f4 st[kStage];
-        {
-            const __amdgpu_buffer_rsrc_t r0 = __builtin_amdgcn_make_buffer_rsrc((void*)A.pad, 0, fbytes, 0x00020000);
-            stage_load(r0, voff, __builtin_amdgcn_readfirstlane(geo[0]), A.Wp, act, st);
-            stage_store(lds, loff, act, st);
-        }
+        stage_load(frame_rsrc(0), voff, __builtin_amdgcn_readfirstlane(geo[0]), A.Wp, act, st);
+        stage_store(lds, loff, act, st);
+        int rowb, col[kVPW];
+        geom(0, rowb, col);
+        int soff_next = __builtin_amdgcn_readfirstlane(geo[min(1, last) * kGeomInts]);
         __syncthreads();
         for (int i = 0; i < A.n; ++i) {
             const float* buf = lds + (i & 1) * kLdsBuf;
-            const bool more = i + 1 < A.n;
-            if (more) {
-                const int gi = (i + 1 - f0) * kGeomInts;
-                const __amdgpu_buffer_rsrc_t rn = __builtin_amdgcn_make_buffer_rsrc(
-                    (void*)(A.pad + (long long)(i + 1) * A.fstride), 0, fbytes, 0x00020000);
-                stage_load(rn, voff, __builtin_amdgcn_readfirstlane(geo[gi]), A.Wp, act, st);
-            }
-            const int* g = geo + (i - f0) * kGeomInts;
-            const int rowb = __builtin_amdgcn_readfirstlane(g[1 + kVBX + wave % kVBY]);
+            // staging of frame i + 1 (the last iteration reloads frame n - 1
+            // into the idle buffer, which nobody reads)
+            const int inext = min(i + 1, last);
+            stage_load(frame_rsrc(inext), voff, soff_next, A.Wp, act, st);
+            // all of this frame's sample reads, then the next frame's geometry
+            // (LDS reads complete in order, so waiting for the geometry never
+            // waits for more than what is issued before it)
+            float v[kVPW][kRows];
 #pragma unroll
             for (int q = 0; q < kVPW; ++q) {
-                const int colq = __builtin_amdgcn_readfirstlane(g[1 + kVPW * xg + q]);
-                const float* p = buf + (rowb + colq) + lane;
+                const float* p = buf + (rowb + col[q]) + lane;
 #pragma unroll
-                for (int r = 0; r < kRows; ++r) acc[q][r] += p[r * kLdsPitch];
-                // keep at most one velocity's row loads in flight
-                __builtin_amdgcn_sched_barrier(0);
+                for (int r = 0; r < kRows; ++r) v[q][r] = p[r * kLdsPitch];
             }
-            if (more) stage_store(lds + ((i + 1) & 1) * kLdsBuf, loff, act, st);
+            const int* gn = geo + (inext - f0) * kGeomInts;
+            const int* gs = geo + (min(i + 2, last) - f0) * kGeomInts;
+            const int nrow = gn[gw_row];
+            int ncol[kVPW];
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q) ncol[q] = gn[gw_col + q];
+            const int nsoff = gs[0];
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q)
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) acc[q][r] += v[q][r];
+            // The sums must be formed here, before the geometry read-back and
+            // the staging store: otherwise the compiler sinks the adds past
+            // them (and past the barrier), and a frame's LDS reads and adds can
+            // no longer overlap.  These statements emit no instruction.
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q)
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) asm volatile("" ::"v"(acc[q][r]));
+            rowb = __builtin_amdgcn_readfirstlane(nrow);
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(ncol[q]);
+            soff_next = __builtin_amdgcn_readfirstlane(nsoff);
+            stage_store(lds + ((i + 1) & 1) * kLdsBuf, loff, act, st);
             __syncthreads();
-            // next geometry chunk: must hold frames i + 1 and i + 2
-            if (i + 2 < A.n && i + 2 == f0 + kGeomChunk) {
-                f0 = i + 1;
+            // next geometry chunk: iteration i + 1 reads frames i + 2 and i + 3
+            // (frame i + 1's geometry and frame i + 2's origin are in registers)
+            if (i + 3 <= last && i + 3 == f0 + kGeomChunk) {
+                f0 = i + 2;
                 fill_geometry(A, geo, f0, min(A.n - f0, kGeomChunk), a0, b0, X0, Y0);
                 __syncthreads();
             }
