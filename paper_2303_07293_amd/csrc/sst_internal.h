@@ -47,6 +47,7 @@ constexpr int kStatThreads = 256;
 constexpr int kStatChunk = 8192;  // pixels per frame-statistics workgroup
 constexpr int kMaxK = 1024;       // largest k_max accepted
 constexpr int kMergeLds = 2048;   // entries ranked in LDS by the merge kernel
+constexpr int kPLds = 1024;       // variance-prefix entries the stack kernel keeps in LDS
 
 // One candidate kept by a (tile, velocity) before the per-velocity merge.
 struct Entry {

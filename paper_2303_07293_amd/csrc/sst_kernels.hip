@@ -299,21 +299,23 @@ __device__ __forceinline__ void stage_store(float* buf, int loff, bool act, cons
 // The S/N of a row is recomputed where it is needed rather than stored, to
 // keep the register footprint of this epilogue below the main loop's.
 struct SnCtx {
-    const int* IY;    // coverage intervals of y
-    const double* P;  // prefix sums of the frame variances
-    int n, h, b, Y0, xlo, xhi;
-    bool full;
-    float rs;  // 1/sqrt(V) of a fully covered pixel
+    const int* IYr;    // [kRows][2] y coverage intervals of the tile rows, this velocity row
+    const float* RSr;  // [kRows] 1/sqrt(V) of a pixel whose x samples are all inside
+    const double* P;   // prefix sums of the frame variances
+    int n, xlo, xhi;
+    bool xfull;        // this lane's column sees every frame in x
 };
 
+// S/N of row r of this lane's column (and its coverage).  A lane whose x
+// samples are all inside has coverage = the row's y interval, whose 1/sqrt(V)
+// is tabulated per row; other lanes combine both intervals.  Both forms are
+// the same arithmetic, rsqrtf((float)(P[hi + 1] - P[lo])) times the sum.
 __device__ __forceinline__ float sn_row(const SnCtx& c, float acc, int r, int& cov) {
-    if (c.full) {
-        cov = c.n;
-        return acc * c.rs;
+    const int ylo = c.IYr[2 * r], yhi = c.IYr[2 * r + 1];
+    if (c.xfull) {
+        cov = yhi - ylo + 1;
+        return cov > 0 ? acc * c.RSr[r] : -INFINITY;
     }
-    const int y = c.Y0 + r;
-    int ylo = c.n, yhi = -1;
-    if (y >= 0 && y < c.h) load_iv(c.IY, (long long)c.b * c.h + y, ylo, yhi);
     int lo, hi;
     cov = coverage(c.xlo, c.xhi, ylo, yhi, lo, hi);
     if (cov <= 0) return -INFINITY;
@@ -401,47 +403,39 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut
     }
 }
 
-__device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float (&acc)[kRows], int a, int b, int x,
-                                                bool xin, int lane, int Y0, int tile, float* col) {
+// rsm[r]: for a lane whose x samples are all inside, 1/sqrt(V) of tile row r
+// if that row can hold a candidate (inside the grid, coverage >= c_min), else
+// NaN, so that acc * rsm[r] > threshold is exactly the candidate test of the
+// threshold and coverage (NaN compares false).
+__device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float (&acc)[kRows],
+                                                const float (&rsm)[kRows], int a, int b, int x, bool xin, int lane,
+                                                int Y0, int tile, float* col, const int* IYr, const float* RSr,
+                                                const double* P, int xlo, int xhi) {
     const bool lane_emit = lane >= 1 && lane <= kWave - 2 && xin;
     const long long kc = (long long)(b - A.vby0 * kVBY) * A.nvx + a;
     SnCtx c;
-    c.IY = A.IY;
-    c.P = A.P;
+    c.IYr = IYr;
+    c.RSr = RSr;
+    c.P = P;
     c.n = A.n;
-    c.h = A.h;
-    c.b = b;
-    c.Y0 = Y0;
-    c.xlo = A.n;
-    c.xhi = -1;
-    if (xin) load_iv(A.IX, (long long)a * A.w + x, c.xlo, c.xhi);
-    // Fast path: every pixel of the tile sees all n frames (the fully
-    // covered rows form one interval of y, so the two end rows decide), and
-    // V = P[n] - P[0] is the same for the whole tile.
-    int y0lo = A.n, y0hi = -1, y1lo = A.n, y1hi = -1;
-    if (Y0 >= 0 && Y0 < A.h) load_iv(A.IY, (long long)b * A.h + Y0, y0lo, y0hi);
-    if (Y0 + kRows - 1 < A.h) load_iv(A.IY, (long long)b * A.h + Y0 + kRows - 1, y1lo, y1hi);
-    const bool full_y = y0lo == 0 && y0hi == A.n - 1 && y1lo == 0 && y1hi == A.n - 1;
-    c.full = full_y && __all(c.xlo == 0 && c.xhi == A.n - 1);
-    {
-        const double V = A.P[A.n] - A.P[0];
-        c.rs = V > 0.0 ? rsqrtf((float)V) : 0.f;
-    }
+    c.xlo = xlo;
+    c.xhi = xhi;
+    c.xfull = xlo == 0 && xhi == A.n - 1;
     unsigned fl = 0;
-    if (c.full) {
-        if (A.n >= A.cmin) {
+    if (c.xfull && lane_emit) {
 #pragma unroll
-            for (int r = 1; r <= kRows - 2; ++r)
-                if (lane_emit && Y0 + r < A.h && acc[r] * c.rs > A.thr) fl |= 1u << r;
-        }
-    } else {
+        for (int r = 1; r <= kRows - 2; ++r)
+            if (acc[r] * rsm[r] > A.thr) fl |= 1u << r;
+    }
+    if (__ballot(!c.xfull && lane_emit) != 0) {
+        // lanes near the frame's x edges: combine both coverage intervals
+        if (!c.xfull && lane_emit) {
 #pragma unroll
-        for (int r = 1; r <= kRows - 2; ++r) {
-            int cov;
-            const float s = sn_row(c, acc[r], r, cov);
-            if (lane_emit && Y0 + r < A.h && cov >= A.cmin && s > A.thr) fl |= 1u << r;
-            // bound the number of prefix-sum loads in flight
-            if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            for (int r = 1; r <= kRows - 2; ++r) {
+                int cov;
+                const float s = sn_row(c, acc[r], r, cov);
+                if (Y0 + r < A.h && cov >= A.cmin && s > A.thr) fl |= 1u << r;
+            }
         }
     }
     CandOut o;
@@ -590,18 +584,62 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
 
     const int x = X0 + lane;
     const bool xin = x >= 0 && x < A.w;
+    const bool bin = b < A.nvy;
+
+    // Coverage tables for the epilogue, staged once per workgroup: the y
+    // intervals of the block's velocity rows over the tile's rows, the
+    // variance prefix (when it fits) and each lane's x intervals.
+    __shared__ int sIY[kVBY * kRows * 2];
+    __shared__ float sRS[DETECT ? kVBY * kRows : 1];
+    __shared__ __attribute__((aligned(16))) float sRM[DETECT ? kVBY * kRows : 4];
+    __shared__ double sP[DETECT ? kPLds : 1];
+    const bool need_c = DETECT || A.mean || A.cov != nullptr;
+    int xlo[kVPW], xhi[kVPW];
+#pragma unroll
+    for (int q = 0; q < kVPW; ++q) {
+        xlo[q] = A.n;
+        xhi[q] = -1;
+        if (need_c && xin && aw + q < A.nvx) load_iv(A.IX, (long long)(aw + q) * A.w + x, xlo[q], xhi[q]);
+    }
+    if (need_c) {
+        for (int e = tid; e < kVBY * kRows; e += kThreads) {
+            const int bb = b0 + e / kRows, y = Y0 + e % kRows;
+            int lo = A.n, hi = -1;
+            if (bb < A.nvy && y >= 0 && y < A.h) load_iv(A.IY, (long long)bb * A.h + y, lo, hi);
+            sIY[2 * e] = lo;
+            sIY[2 * e + 1] = hi;
+        }
+    }
+    const bool p_lds = DETECT && A.n + 1 <= kPLds;
+    if (p_lds)
+        for (int e = tid; e <= A.n; e += kThreads) sP[e] = A.P[e];
+    if (DETECT) {
+        // per (velocity row, tile row): 1/sqrt(V) over the row's y interval
+        for (int e = tid; e < kVBY * kRows; e += kThreads) {
+            const int bb = b0 + e / kRows, y = Y0 + e % kRows;
+            int lo = A.n, hi = -1;
+            if (bb < A.nvy && y >= 0 && y < A.h) load_iv(A.IY, (long long)bb * A.h + y, lo, hi);
+            float rs = 0.f;
+            if (hi >= lo) {
+                const double V = A.P[hi + 1] - A.P[lo];
+                rs = V > 0.0 ? rsqrtf((float)V) : 0.f;
+            }
+            sRS[e] = rs;
+            sRM[e] = (hi - lo + 1 >= A.cmin && hi >= lo) ? rs : __builtin_nanf("");
+        }
+    }
+    if (need_c) __syncthreads();
+    const int* IYr = sIY + (wave % kVBY) * kRows * 2;
+    const float* RSr = sRS + (wave % kVBY) * kRows;
 
     if constexpr (!DETECT) {
         // plain stack: SUM or MEAN, optional coverage
-        if (b >= A.nvy || !xin) return;
-        const bool need_c = A.mean || A.cov != nullptr;
+        if (!bin || !xin) return;
 #pragma unroll
         for (int q = 0; q < kVPW; ++q) {
             const int a = aw + q;
             if (a < A.nvx) {
                 const long long kk = (long long)b * A.nvx + a;
-                int xlo = 0, xhi = -1;
-                if (need_c) load_iv(A.IX, (long long)a * A.w + x, xlo, xhi);
 #pragma unroll
                 for (int r = 0; r < kRows; ++r) {
                     const int y = Y0 + r;
@@ -610,32 +648,51 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
                         int c = 0;
                         if (need_c) {
                             int lo, hi;
-                            int ylo, yhi;
-                            load_iv(A.IY, (long long)b * A.h + y, ylo, yhi);
-                            c = max(0, coverage(xlo, xhi, ylo, yhi, lo, hi));
+                            c = max(0, coverage(xlo[q], xhi[q], IYr[2 * r], IYr[2 * r + 1], lo, hi));
                         }
                         if (A.mean) v = c > 0 ? v / (float)c : 0.f;
                         const long long o = (kk * A.h + y) * A.w + x;
                         A.out[o] = v;
                         if (A.cov) A.cov[o] = c;
                     }
-                    if ((r & 7) == 7) __builtin_amdgcn_sched_barrier(0);
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
         }
         return;
     } else {
-        if (b >= A.nvy) return;
+        if (!bin) return;
         // written out (not a loop) so that acc stays in registers: the
         // epilogue is too large for the unroller to replicate
         static_assert(kVPW == 3, "one call per velocity of the wave");
         float* col = lds + wave * (kRows * kWave);
-        if (aw + 0 < A.nvx) detect_epilogue(A, acc[0], aw + 0, b, x, xin, lane, Y0, tile, col);
-        __builtin_amdgcn_sched_barrier(0);
-        if (aw + 1 < A.nvx) detect_epilogue(A, acc[1], aw + 1, b, x, xin, lane, Y0, tile, col);
-        __builtin_amdgcn_sched_barrier(0);
-        if (aw + 2 < A.nvx) detect_epilogue(A, acc[2], aw + 2, b, x, xin, lane, Y0, tile, col);
+        float rsm[kRows];  // this wave's row multipliers (uniform), read once
+        {
+            const f4* src = reinterpret_cast<const f4*>(sRM + (wave % kVBY) * kRows);
+#pragma unroll
+            for (int k = 0; k < kRows / 4; ++k) {
+                const f4 t = src[k];
+                rsm[4 * k] = t.x;
+                rsm[4 * k + 1] = t.y;
+                rsm[4 * k + 2] = t.z;
+                rsm[4 * k + 3] = t.w;
+            }
+        }
+        auto epi = [&](const double* P) {
+            if (aw + 0 < A.nvx)
+                detect_epilogue(A, acc[0], rsm, aw + 0, b, x, xin, lane, Y0, tile, col, IYr, RSr, P, xlo[0], xhi[0]);
+            __builtin_amdgcn_sched_barrier(0);
+            if (aw + 1 < A.nvx)
+                detect_epilogue(A, acc[1], rsm, aw + 1, b, x, xin, lane, Y0, tile, col, IYr, RSr, P, xlo[1], xhi[1]);
+            __builtin_amdgcn_sched_barrier(0);
+            if (aw + 2 < A.nvx)
+                detect_epilogue(A, acc[2], rsm, aw + 2, b, x, xin, lane, Y0, tile, col, IYr, RSr, P, xlo[2], xhi[2]);
+        };
+        // two instantiations so that the common one reads the prefix from LDS
+        if (p_lds)
+            epi(sP);
+        else
+            epi(A.P);
     }
 }
 
