@@ -40,7 +40,7 @@ constexpr int kMaxFrames = 65535;
 constexpr int kMaxSide = 16384;
 constexpr int kMaxGrid = 65535;
 constexpr double kMaxShift = 1073741824.0;  // 2^30
-constexpr size_t kEntryBudget = size_t(1) << 30;
+constexpr size_t kEntryBudget = size_t(2) << 30;
 
 int check_dims(int n, int h, int w) {
     if (n < 1 || n > kMaxFrames) return fail(SST_E_ARG, "n = %d frames: need 1..%d", n, kMaxFrames);
@@ -102,7 +102,7 @@ struct Plan {
     int op = 0;
     int n = 0, h = 0, w = 0;
     int nvx = 0, nvy = 0, ldx = 0, ldy = 0, nvbx = 0, nvby = 0;
-    int halo = 0, step_x = 0, step_y = 0, tiles_x = 0, tiles_y = 0, ntiles = 0;
+    int halo = 0, step_x = 0, step_y = 0, tiles_x = 0, tiles_y = 0, ntiles = 0, nslot = 0;
     int padL = 0, padT = 0, Wp = 0, Hp = 0;
     bool staged = true;
     int kt = 0, rows_per_chunk = 0, nchunk = 0;
@@ -159,6 +159,7 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
     p.tiles_x = ceil_div(w, p.step_x);
     p.tiles_y = ceil_div(h, p.step_y);
     p.ntiles = p.tiles_x * p.tiles_y;
+    p.nslot = 2 * p.ntiles;  // one candidate slot per (tile, row half)
 
     int dxmin = 0, dxmax = 0, dymin = 0, dymax = 0, sx = 0, sy = 0;
     for (int i = 0; i < n; ++i) {
@@ -203,11 +204,11 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
         p.o_P = take(cur, (size_t)(n + 1) * sizeof(double));
         p.o_sdev = take(cur, (size_t)n * 2 * sizeof(double));
         p.kt = k_max;
-        const size_t per_row = (size_t)kVBY * nvx * p.ntiles * ((size_t)p.kt * sizeof(Entry) + sizeof(int32_t));
+        const size_t per_row = (size_t)kVBY * nvx * p.nslot * ((size_t)p.kt * sizeof(Entry) + sizeof(int32_t));
         p.rows_per_chunk = (int)std::max<size_t>(1, std::min<size_t>(p.nvby, kEntryBudget / per_row));
         const size_t nk = (size_t)p.rows_per_chunk * kVBY * nvx;
-        p.o_tcount = take(cur, nk * p.ntiles * sizeof(int32_t));
-        p.o_ent = take(cur, nk * p.ntiles * p.kt * sizeof(Entry));
+        p.o_tcount = take(cur, nk * p.nslot * sizeof(int32_t));
+        p.o_ent = take(cur, nk * p.nslot * p.kt * sizeof(Entry));
     }
     p.total = cur;
     return SST_OK;
@@ -283,7 +284,7 @@ StackArgs stack_args(const Plan& p, void* ws) {
     a.nvbx = p.nvbx;
     a.vby0 = 0;
     a.nvby = p.nvby;
-    a.ntiles = p.ntiles;
+    a.nslot = p.nslot;
     return a;
 }
 
@@ -480,7 +481,7 @@ int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, 
         const int b_first = r0 * kVBY;
         const int b_last = std::min(nvy, (r0 + rows) * kVBY);
         const int nk = (b_last - b_first) * nvx;
-        if ((e = launch_merge(a.tcount, a.ent, p.ntiles, p.kt, k_max, nvx, w, b_first * nvx, nk, cand, count, s)) !=
+        if ((e = launch_merge(a.tcount, a.ent, p.nslot, p.kt, k_max, nvx, w, b_first * nvx, nk, cand, count, s)) !=
             hipSuccess)
             return hip_fail(e, "merge kernel");
     }

@@ -16,19 +16,25 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Work decomposition of the stack kernels.  A workgroup is kWaves wave64s;
 // it owns a tile of 64 columns (one per lane) by kRows rows and a block of
-// kVBX x kVBY trial velocities.  Wave w handles the kVPW velocities
-// a0 + kVPW*(w / kVBY) + q (q < kVPW) of velocity row b0 + w % kVBY, so each
-// lane keeps kVPW * kRows float accumulators and every staged frame tile is
-// reused by all kVBX * kVBY velocities of the block.
+// kVBX x kVBY trial velocities, so every staged frame tile is reused by all
+// kVBX * kVBY velocities of the block.  Wave w handles kRowsW = kRows / 2
+// rows (half w % 2) of kVPW x velocities (group w / 4) and kVYW = 2
+// neighbouring y velocities (pair (w / 2) % 2): kVPW * kVYW * kRowsW float
+// accumulators per lane.  For one frame the two y velocities of a pair sample
+// rows a small uniform distance d apart, so one read of kRowsW + |d| staged
+// rows feeds both sets of accumulators.
 constexpr int kWave = 64;
 constexpr int kWaves = 8;
 constexpr int kThreads = kWave * kWaves;
 constexpr int kTileW = 64;
 constexpr int kRows = 32;
+constexpr int kRowsW = kRows / 2;  // rows per wave
 constexpr int kVBX = 6;
 constexpr int kVBY = 4;
-constexpr int kVPW = 3;  // velocities per wave
-static_assert(kVBX * kVBY == kVPW * kWaves, "every velocity of a block has one wave");
+constexpr int kVPW = 3;  // x velocities per wave
+constexpr int kVYW = 2;  // y velocities per wave
+constexpr int kDMax = 4; // largest |d| read once for both y velocities of a pair
+static_assert(kVBX * kVBY * 2 == kVPW * kVYW * kWaves, "every (velocity, row half) of a block has one wave");
 // LDS staging: the frame region a velocity block needs is the tile widened by
 // the spread of the block's shifts (at most kSMaxX / kSMaxY px) plus 3
 // columns of alignment slack for 16-byte staging.  A fixed window of
@@ -79,10 +85,10 @@ struct StackArgs {
     // detect
     float thr;
     int cmin;
-    int kt;      // entries kept per (tile, velocity)
-    int ntiles;  // tiles_x * tiles_y
-    int32_t* tcount;  // [velocities of this launch][ntiles]
-    Entry* ent;       // [velocities of this launch][ntiles][kt]
+    int kt;      // entries kept per slot
+    int nslot;   // slots per velocity: one per (tile, row half), 2 * tiles_x * tiles_y
+    int32_t* tcount;  // [velocities of this launch][nslot] candidates found (before keeping kt)
+    Entry* ent;       // [velocities of this launch][nslot][kt]
 };
 
 struct PrepArgs {
@@ -99,7 +105,7 @@ hipError_t launch_stats(const float* frames, int n, int h, int w, double* part, 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_cov(const int* D, int ld, int n, int nv, int size, int* I, hipStream_t s);
 hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, hipStream_t s);
-hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int ntiles, int kt, int k_max,
+hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int nslot, int kt, int k_max,
                         int nvx, int w, int k_first, int nk, void* cand, int32_t* count,
                         hipStream_t s);
 

@@ -16,6 +16,7 @@
 
 #include <climits>
 #include <cmath>
+#include <type_traits>
 
 namespace sst {
 
@@ -236,7 +237,7 @@ __device__ __forceinline__ int coverage(int xlo, int xhi, int ylo, int yhi, int&
 // and the row Y0 + (smallest y shift).  All offsets are in elements.
 constexpr int kGeomChunk = 256;
 constexpr int kGeomInts = 12;  // soff, col[2][3], row[4], 1 spare
-static_assert(kVBX == 2 * kVPW && kVBY == 4 && kWaves == 8, "geometry layout assumed below");
+static_assert(kVBX == 2 * kVPW && kVBY == 2 * kVYW && kWaves == 8, "geometry layout assumed below");
 
 // Fill the geometry of frames [f0, f0 + cnt) (one thread per frame).
 __device__ __forceinline__ void fill_geometry(const StackArgs& A, int* geo, int f0, int cnt, int a0, int b0, int X0,
@@ -294,19 +295,28 @@ __device__ __forceinline__ void stage_store(float* buf, int loff, bool act, cons
 }
 
 // S/N, peak test and candidate output of one (tile, velocity) for one wave.
-// Each lane holds one column of kRows accumulated sums.  Rows 0 and kRows-1
-// and lanes 0 and 63 are the 1-pixel halo: their S/N is only compared with.
-// The S/N of a row is recomputed where it is needed rather than stored, to
-// keep the register footprint of this epilogue below the main loop's.
+// The wave holds rows 16h .. 16h + 15 (h = row half) of the tile, one column
+// per lane.  Tile rows 0 and kRows - 1 and lanes 0 and 63 are the 1-pixel
+// halo: their S/N is only compared with.  The peak test of the wave's rows
+// next to the other half needs that half's boundary row, which every wave
+// publishes in LDS after the frame loop.  The candidate search works on a
+// column of kColRows rows, tile rows R0 .. R0 + 16 with R0 = 15h: the wave's
+// own 16 rows and the neighbouring half's boundary row; its rows 1 .. 15 are
+// the ones it may emit.  The S/N of a row is recomputed where it is needed
+// rather than stored, to keep the register footprint of this epilogue below
+// the main loop's.
+constexpr int kColRows = kRowsW + 1;
+constexpr unsigned kEmitRows = ((1u << (kColRows - 1)) - 1u) & ~1u;  // column rows 1 .. kColRows - 2
+
 struct SnCtx {
-    const int* IYr;    // [kRows][2] y coverage intervals of the tile rows, this velocity row
-    const float* RSr;  // [kRows] 1/sqrt(V) of a pixel whose x samples are all inside
+    const int* IYr;    // [kColRows][2] y coverage intervals of the column's rows
+    const float* RSr;  // [kColRows] 1/sqrt(V) of a pixel whose x samples are all inside
     const double* P;   // prefix sums of the frame variances
     int n, xlo, xhi;
     bool xfull;        // this lane's column sees every frame in x
 };
 
-// S/N of row r of this lane's column (and its coverage).  A lane whose x
+// S/N of column row r of this lane (and its coverage).  A lane whose x
 // samples are all inside has coverage = the row's y interval, whose 1/sqrt(V)
 // is tabulated per row; other lanes combine both intervals.  Both forms are
 // the same arithmetic, rsqrtf((float)(P[hi + 1] - P[lo])) times the sum.
@@ -327,14 +337,15 @@ __device__ __forceinline__ float sn_row(const SnCtx& c, float acc, int r, int& c
 struct CandOut {
     int32_t* tcount;
     Entry* ent;
-    long long slot;  // (velocity of this launch) * ntiles + tile
+    long long slot;  // (velocity of this launch) * nslot + 2 * tile + row half
     int kt, w;
 };
 
-// Peak test and candidate output for one (tile, velocity) whose column sums
-// are parked in LDS: col[r * 64 + lane] = S' of row r of this lane's column.
+// Peak test and candidate output for one (tile, velocity, row half) whose
+// column sums are parked in LDS: col[r * 64 + lane] = S' of column row r.
+// fl marks the rows (1 .. kColRows - 2) that pass threshold and coverage.
 __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut o, const float* col, unsigned fl,
-                                                    int lane, int x, int Y0) {
+                                                    int lane, int x, int Yc) {
     const int kt = o.kt;
     // 8-neighbour test with the raster tie rule: neighbours earlier in raster
     // order must be strictly smaller, later ones may tie.
@@ -344,7 +355,7 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut
     float Lm = __shfl_up(Sm, 1), Rm = __shfl_down(Sm, 1);
     float L0 = __shfl_up(S0, 1), R0 = __shfl_down(S0, 1);
 #pragma unroll 1
-    for (int r = 1; r <= kRows - 2; ++r) {
+    for (int r = 1; r <= kColRows - 2; ++r) {
         const float Sp = sn_row(c, col[(r + 1) * kWave + lane], r + 1, cv);
         const float Lp = __shfl_up(Sp, 1), Rp = __shfl_down(Sp, 1);
         if ((fl >> r) & 1u) {
@@ -366,12 +377,12 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut
     if (total <= kt) {
         int slot = wave_excl_scan(__popc(cm), lane);
 #pragma unroll 1
-        for (int r = 1; r <= kRows - 2; ++r) {
+        for (int r = 1; r <= kColRows - 2; ++r) {
             if ((cm >> r) & 1u) {
                 int cov;
                 const float v = col[r * kWave + lane];
                 const float s = sn_row(c, v, r, cov);
-                E[slot++] = Entry{s, v, (Y0 + r) * o.w + x, cov};
+                E[slot++] = Entry{s, v, (Yc + r) * o.w + x, cov};
             }
         }
         return;
@@ -383,10 +394,10 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut
         unsigned long long best = 0;
         int bestr = -1;
 #pragma unroll 1
-        for (int r = 1; r <= kRows - 2; ++r) {
+        for (int r = 1; r <= kColRows - 2; ++r) {
             if ((left >> r) & 1u) {
                 int cov;
-                const unsigned long long key = cand_key(sn_row(c, col[r * kWave + lane], r, cov), (Y0 + r) * o.w + x);
+                const unsigned long long key = cand_key(sn_row(c, col[r * kWave + lane], r, cov), (Yc + r) * o.w + x);
                 if (key > best) {
                     best = key;
                     bestr = r;
@@ -397,20 +408,21 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut
         if (bestr >= 0 && best == wb) {
             int cov;
             const float v = col[bestr * kWave + lane];
-            E[k] = Entry{sn_row(c, v, bestr, cov), v, (Y0 + bestr) * o.w + x, cov};
+            E[k] = Entry{sn_row(c, v, bestr, cov), v, (Yc + bestr) * o.w + x, cov};
             left &= ~(1u << bestr);
         }
     }
 }
 
-// rsm[r]: for a lane whose x samples are all inside, 1/sqrt(V) of tile row r
-// if that row can hold a candidate (inside the grid, coverage >= c_min), else
-// NaN, so that acc * rsm[r] > threshold is exactly the candidate test of the
-// threshold and coverage (NaN compares false).
-__device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float (&acc)[kRows],
-                                                const float (&rsm)[kRows], int a, int b, int x, bool xin, int lane,
-                                                int Y0, int tile, float* col, const int* IYr, const float* RSr,
-                                                const double* P, int xlo, int xhi) {
+// rsm[r]: for a lane whose x samples are all inside, 1/sqrt(V) of the wave's
+// row r if that row can hold a candidate (inside the grid, coverage >= c_min),
+// else NaN, so that acc * rsm[r] > threshold is exactly the threshold and
+// coverage test (NaN compares false).  xrow is the other row half's boundary
+// row of the same velocity; IYr and RSr start at column row 0 (tile row R0).
+__device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float (&acc)[kRowsW],
+                                                const float (&rsm)[kRowsW], int a, int b, int x, bool xin, int lane,
+                                                int h, int Y0, int tile, float* col, const float* xrow,
+                                                const int* IYr, const float* RSr, const double* P, int xlo, int xhi) {
     const bool lane_emit = lane >= 1 && lane <= kWave - 2 && xin;
     const long long kc = (long long)(b - A.vby0 * kVBY) * A.nvx + a;
     SnCtx c;
@@ -421,27 +433,28 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
     c.xlo = xlo;
     c.xhi = xhi;
     c.xfull = xlo == 0 && xhi == A.n - 1;
-    unsigned fl = 0;
+    unsigned fl = 0;  // bit r: the wave's row r passes threshold and coverage
     if (c.xfull && lane_emit) {
 #pragma unroll
-        for (int r = 1; r <= kRows - 2; ++r)
+        for (int r = 0; r < kRowsW; ++r)
             if (acc[r] * rsm[r] > A.thr) fl |= 1u << r;
     }
     if (__ballot(!c.xfull && lane_emit) != 0) {
         // lanes near the frame's x edges: combine both coverage intervals
         if (!c.xfull && lane_emit) {
 #pragma unroll
-            for (int r = 1; r <= kRows - 2; ++r) {
+            for (int r = 0; r < kRowsW; ++r) {
                 int cov;
-                const float s = sn_row(c, acc[r], r, cov);
-                if (Y0 + r < A.h && cov >= A.cmin && s > A.thr) fl |= 1u << r;
+                const float s = sn_row(c, acc[r], r + h, cov);
+                if (cov >= A.cmin && s > A.thr) fl |= 1u << r;
             }
         }
     }
+    fl = (fl << h) & kEmitRows;  // the wave's row r is column row r + h
     CandOut o;
     o.tcount = A.tcount;
     o.ent = A.ent;
-    o.slot = kc * A.ntiles + tile;
+    o.slot = kc * A.nslot + 2 * tile + h;
     o.kt = A.kt;
     o.w = A.w;
     if (__ballot(fl != 0) == 0) {
@@ -451,16 +464,61 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
     // Rare path (some pixel of this wave's column block clears the
     // threshold): park the sums in this wave's LDS slot and work from there
     // with runtime row loops, which keeps this code's register use small.
+    float* own = col + h * kWave;
 #pragma unroll
-    for (int r = 0; r < kRows; ++r) col[r * kWave + lane] = acc[r];
-    candidates_from_column(c, o, col, fl, lane, x, Y0);
+    for (int r = 0; r < kRowsW; ++r) own[r * kWave + lane] = acc[r];
+    col[(h ? 0 : kColRows - 1) * kWave + lane] = xrow[lane];
+    candidates_from_column(c, o, col, fl, lane, x, Y0 + (kRowsW - 1) * h);
 }
+
+// One frame's samples for a wave whose two y velocities sample rows D apart
+// (velocity S0 the upper one): staged rows j = 0 .. kRowsW + D - 1 from p
+// feed acc[.][S0][j] and acc[.][1 - S0][j - D].
+template <int D, int S0>
+__device__ __forceinline__ void accum_pair(const float* p, const int (&col)[kVPW],
+                                           float (&acc)[kVPW][kVYW][kRowsW]) {
+    float v[kVPW][kRowsW + D];
+#pragma unroll
+    for (int q = 0; q < kVPW; ++q)
+#pragma unroll
+        for (int j = 0; j < kRowsW + D; ++j) v[q][j] = p[col[q] + j * kLdsPitch];
+#pragma unroll
+    for (int q = 0; q < kVPW; ++q)
+#pragma unroll
+        for (int r = 0; r < kRowsW; ++r) {
+            acc[q][S0][r] += v[q][r];
+            acc[q][1 - S0][r] += v[q][r + D];
+        }
+}
+
+// The same for rows too far apart to share reads.
+__device__ __forceinline__ void accum_sep(const float* p0, const float* p1, const int (&col)[kVPW],
+                                          float (&acc)[kVPW][kVYW][kRowsW]) {
+#pragma unroll
+    for (int s = 0; s < kVYW; ++s) {
+        const float* p = s ? p1 : p0;
+        float v[kVPW][kRowsW];
+#pragma unroll
+        for (int q = 0; q < kVPW; ++q)
+#pragma unroll
+            for (int r = 0; r < kRowsW; ++r) v[q][r] = p[col[q] + r * kLdsPitch];
+#pragma unroll
+        for (int q = 0; q < kVPW; ++q)
+#pragma unroll
+            for (int r = 0; r < kRowsW; ++r) acc[q][s][r] += v[q][r];
+    }
+}
+
+template <int V>
+using ic = std::integral_constant<int, V>;
 
 template <bool DETECT, bool STAGED>
 __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
-    // LDS: two staging buffers during the frame loop (afterwards each wave's
-    // slot of kRows x 64 floats for the candidate search) + frame geometry
-    constexpr int kLdsFloats = (2 * kLdsBuf > kWaves * kRows * kWave) ? 2 * kLdsBuf : kWaves * kRows * kWave;
+    // LDS: two staging buffers during the frame loop; afterwards each wave's
+    // candidate column and the published boundary rows of every wave
+    constexpr int kColFloats = kWaves * kColRows * kWave;
+    constexpr int kXchFloats = kWaves * kVPW * kVYW * kWave;
+    constexpr int kLdsFloats = (2 * kLdsBuf > kColFloats + kXchFloats) ? 2 * kLdsBuf : kColFloats + kXchFloats;
     __shared__ __attribute__((aligned(16))) float lds[kLdsFloats];
     __shared__ int geo[STAGED ? kGeomChunk * kGeomInts : 1];
     const int tid = threadIdx.x;
@@ -473,17 +531,21 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
     const int a0 = (vb % A.nvbx) * kVBX;
     const int b0 = (A.vby0 + vb / A.nvbx) * kVBY;
-    const int xg = wave / kVBY;                // which kVPW-group of the block's x velocities
-    const int aw = a0 + kVPW * xg;             // this wave's first x velocity
-    const int b = b0 + wave % kVBY;            // this wave's velocity row
+    const int xg = wave / 4;          // which kVPW-group of the block's x velocities
+    const int yp = (wave / 2) % 2;    // which pair of the block's y velocities
+    const int h = wave % 2;           // row half
+    const int aw = a0 + kVPW * xg;    // this wave's first x velocity
+    const int bw = b0 + kVYW * yp;    // this wave's first y velocity
     const int X0 = tx * A.step_x - A.halo;
     const int Y0 = ty * A.step_y - A.halo;
 
-    float acc[kVPW][kRows];
+    float acc[kVPW][kVYW][kRowsW];
 #pragma unroll
     for (int q = 0; q < kVPW; ++q)
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) acc[q][r] = 0.f;
+        for (int s = 0; s < kVYW; ++s)
+#pragma unroll
+            for (int r = 0; r < kRowsW; ++r) acc[q][s][r] = 0.f;
 
     if constexpr (STAGED) {
         const int srow = 2 * wave + (lane >> 5);  // staged row of this lane's first load
@@ -496,61 +558,56 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
         int f0 = 0;
         fill_geometry(A, geo, 0, min(A.n, kGeomChunk), a0, b0, X0, Y0);
         __syncthreads();
-        // this wave's geometry of frame i: LDS row offset and the kVPW column
-        // offsets, plus the staging window origin of frame i + 1
-        const int gw_row = 1 + kVBX + wave % kVBY, gw_col = 1 + kVPW * xg;
-        auto geom = [&](int i, int& rowb, int (&col)[kVPW]) {
-            const int* g = geo + (i - f0) * kGeomInts;
-            rowb = __builtin_amdgcn_readfirstlane(g[gw_row]);
-#pragma unroll
-            for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(g[gw_col + q]);
-        };
+        // this wave's geometry of frame i: the LDS row offsets of its two y
+        // velocities and the kVPW column offsets, plus the staging window
+        // origin of frame i + 1
+        const int gw_row = 1 + kVBX + kVYW * yp, gw_col = 1 + kVPW * xg;
+        const int hoff = h * kRowsW * kLdsPitch;
         auto frame_rsrc = [&](int i) {
             return __builtin_amdgcn_make_buffer_rsrc((void*)(A.pad + (long long)i * A.fstride), 0, fbytes, 0x00020000);
         };
         f4 st[kStage];
         stage_load(frame_rsrc(0), voff, __builtin_amdgcn_readfirstlane(geo[0]), A.Wp, act, st);
         stage_store(lds, loff, act, st);
-        int rowb, col[kVPW];
-        geom(0, rowb, col);
+        int row0 = __builtin_amdgcn_readfirstlane(geo[gw_row]);
+        int row1 = __builtin_amdgcn_readfirstlane(geo[gw_row + 1]);
+        int col[kVPW];
+#pragma unroll
+        for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(geo[gw_col + q]);
         int soff_next = __builtin_amdgcn_readfirstlane(geo[min(1, last) * kGeomInts]);
         __syncthreads();
         for (int i = 0; i < A.n; ++i) {
-            const float* buf = lds + (i & 1) * kLdsBuf;
+            const float* buf = lds + (i & 1) * kLdsBuf + lane;
             // staging of frame i + 1 (the last iteration reloads frame n - 1
             // into the idle buffer, which nobody reads)
             const int inext = min(i + 1, last);
             stage_load(frame_rsrc(inext), voff, soff_next, A.Wp, act, st);
-            // all of this frame's sample reads, then the next frame's geometry
-            // (LDS reads complete in order, so waiting for the geometry never
-            // waits for more than what is issued before it)
-            float v[kVPW][kRows];
-#pragma unroll
-            for (int q = 0; q < kVPW; ++q) {
-                const float* p = buf + (rowb + col[q]) + lane;
-#pragma unroll
-                for (int r = 0; r < kRows; ++r) v[q][r] = p[r * kLdsPitch];
-            }
+            // the next frame's geometry (a few broadcast reads), then this
+            // frame's samples
             const int* gn = geo + (inext - f0) * kGeomInts;
             const int* gs = geo + (min(i + 2, last) - f0) * kGeomInts;
-            const int nrow = gn[gw_row];
+            const int nrow0 = gn[gw_row], nrow1 = gn[gw_row + 1];
             int ncol[kVPW];
 #pragma unroll
             for (int q = 0; q < kVPW; ++q) ncol[q] = gn[gw_col + q];
             const int nsoff = gs[0];
-#pragma unroll
-            for (int q = 0; q < kVPW; ++q)
-#pragma unroll
-                for (int r = 0; r < kRows; ++r) acc[q][r] += v[q][r];
-            // The sums must be formed here, before the geometry read-back and
-            // the staging store: otherwise the compiler sinks the adds past
-            // them (and past the barrier), and a frame's LDS reads and adds can
-            // no longer overlap.  These statements emit no instruction.
-#pragma unroll
-            for (int q = 0; q < kVPW; ++q)
-#pragma unroll
-                for (int r = 0; r < kRows; ++r) asm volatile("" ::"v"(acc[q][r]));
-            rowb = __builtin_amdgcn_readfirstlane(nrow);
+            const int d = (row1 - row0) / kLdsPitch;
+            const float* pb = buf + min(row0, row1) + hoff;
+            // one block per read pattern, each updating the sums in place
+            // (a chain of two-way branches keeps every sum in one register)
+            if (d == 0) accum_pair<0, 0>(pb, col, acc);
+            if (d == 1) accum_pair<1, 0>(pb, col, acc);
+            if (d == 2) accum_pair<2, 0>(pb, col, acc);
+            if (d == 3) accum_pair<3, 0>(pb, col, acc);
+            if (d == 4) accum_pair<4, 0>(pb, col, acc);
+            if (d == -1) accum_pair<1, 1>(pb, col, acc);
+            if (d == -2) accum_pair<2, 1>(pb, col, acc);
+            if (d == -3) accum_pair<3, 1>(pb, col, acc);
+            if (d == -4) accum_pair<4, 1>(pb, col, acc);
+            if (d < -kDMax || d > kDMax) accum_sep(buf + row0 + hoff, buf + row1 + hoff, col, acc);
+            static_assert(kDMax == 4, "one case per shared-read distance");
+            row0 = __builtin_amdgcn_readfirstlane(nrow0);
+            row1 = __builtin_amdgcn_readfirstlane(nrow1);
 #pragma unroll
             for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(ncol[q]);
             soff_next = __builtin_amdgcn_readfirstlane(nsoff);
@@ -569,22 +626,24 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
         // LDS region: every sample is read from the padded copy through L2.
         for (int i = 0; i < A.n; ++i) {
             const int* rx = A.DX + (long long)i * A.ldx + aw;
-            const int dyw = A.DY[(long long)i * A.ldy + b];
-            const float* base = A.pad + (long long)i * A.fstride + (long long)(Y0 + dyw + A.padT) * A.Wp +
-                                (X0 + lane + A.padL);
+            const int* ry = A.DY + (long long)i * A.ldy + bw;
 #pragma unroll
-            for (int q = 0; q < kVPW; ++q) {
-                const float* p = base + rx[q];
+            for (int s = 0; s < kVYW; ++s) {
+                const float* base = A.pad + (long long)i * A.fstride +
+                                    (long long)(Y0 + h * kRowsW + ry[s] + A.padT) * A.Wp + (X0 + lane + A.padL);
 #pragma unroll
-                for (int r = 0; r < kRows; ++r) acc[q][r] += p[(long long)r * A.Wp];
-                __builtin_amdgcn_sched_barrier(0);
+                for (int q = 0; q < kVPW; ++q) {
+                    const float* p = base + rx[q];
+#pragma unroll
+                    for (int r = 0; r < kRowsW; ++r) acc[q][s][r] += p[(long long)r * A.Wp];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         }
     }
 
     const int x = X0 + lane;
     const bool xin = x >= 0 && x < A.w;
-    const bool bin = b < A.nvy;
 
     // Coverage tables for the epilogue, staged once per workgroup: the y
     // intervals of the block's velocity rows over the tile's rows, the
@@ -611,9 +670,9 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
         }
     }
     const bool p_lds = DETECT && A.n + 1 <= kPLds;
-    if (p_lds)
-        for (int e = tid; e <= A.n; e += kThreads) sP[e] = A.P[e];
     if (DETECT) {
+        if (p_lds)
+            for (int e = tid; e <= A.n; e += kThreads) sP[e] = A.P[e];
         // per (velocity row, tile row): 1/sqrt(V) over the row's y interval
         for (int e = tid; e < kVBY * kRows; e += kThreads) {
             const int bb = b0 + e / kRows, y = Y0 + e % kRows;
@@ -627,67 +686,85 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
             sRS[e] = rs;
             sRM[e] = (hi - lo + 1 >= A.cmin && hi >= lo) ? rs : __builtin_nanf("");
         }
+        // publish the row next to the other half: row kRowsW - 1 of the upper
+        // half, row 0 of the lower one
+        float* xo = lds + kColFloats + wave * (kVPW * kVYW * kWave);
+#pragma unroll
+        for (int q = 0; q < kVPW; ++q)
+#pragma unroll
+            for (int s = 0; s < kVYW; ++s) xo[(q * kVYW + s) * kWave + lane] = h ? acc[q][s][0] : acc[q][s][kRowsW - 1];
     }
     if (need_c) __syncthreads();
-    const int* IYr = sIY + (wave % kVBY) * kRows * 2;
-    const float* RSr = sRS + (wave % kVBY) * kRows;
 
     if constexpr (!DETECT) {
         // plain stack: SUM or MEAN, optional coverage
-        if (!bin || !xin) return;
+        if (!xin) return;
 #pragma unroll
         for (int q = 0; q < kVPW; ++q) {
-            const int a = aw + q;
-            if (a < A.nvx) {
-                const long long kk = (long long)b * A.nvx + a;
 #pragma unroll
-                for (int r = 0; r < kRows; ++r) {
-                    const int y = Y0 + r;
-                    if (y < A.h) {
-                        float v = acc[q][r];
-                        int c = 0;
-                        if (need_c) {
-                            int lo, hi;
-                            c = max(0, coverage(xlo[q], xhi[q], IYr[2 * r], IYr[2 * r + 1], lo, hi));
+            for (int s = 0; s < kVYW; ++s) {
+                const int a = aw + q, bb = bw + s;
+                if (a < A.nvx && bb < A.nvy) {
+                    const long long kk = (long long)bb * A.nvx + a;
+                    const int* IYr = sIY + (bb - b0) * kRows * 2;
+#pragma unroll
+                    for (int r = 0; r < kRowsW; ++r) {
+                        const int tr = h * kRowsW + r;
+                        const int y = Y0 + tr;
+                        if (y < A.h) {
+                            float v = acc[q][s][r];
+                            int c = 0;
+                            if (need_c) {
+                                int lo, hi;
+                                c = max(0, coverage(xlo[q], xhi[q], IYr[2 * tr], IYr[2 * tr + 1], lo, hi));
+                            }
+                            if (A.mean) v = c > 0 ? v / (float)c : 0.f;
+                            const long long o = (kk * A.h + y) * A.w + x;
+                            A.out[o] = v;
+                            if (A.cov) A.cov[o] = c;
                         }
-                        if (A.mean) v = c > 0 ? v / (float)c : 0.f;
-                        const long long o = (kk * A.h + y) * A.w + x;
-                        A.out[o] = v;
-                        if (A.cov) A.cov[o] = c;
                     }
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
-            __builtin_amdgcn_sched_barrier(0);
         }
         return;
     } else {
-        if (!bin) return;
-        // written out (not a loop) so that acc stays in registers: the
-        // epilogue is too large for the unroller to replicate
-        static_assert(kVPW == 3, "one call per velocity of the wave");
-        float* col = lds + wave * (kRows * kWave);
-        float rsm[kRows];  // this wave's row multipliers (uniform), read once
-        {
-            const f4* src = reinterpret_cast<const f4*>(sRM + (wave % kVBY) * kRows);
+        // written out per velocity (not a loop) so that acc stays in
+        // registers: the epilogue is too large for the unroller to replicate
+        float* col = lds + wave * (kColRows * kWave);
+        const float* xin_rows = lds + kColFloats + (wave ^ 1) * (kVPW * kVYW * kWave);
+        const int R0 = (kRowsW - 1) * h;
+        auto one = [&](auto qc, auto sc, const double* P) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value, s = decltype(sc)::value;
+            const int bb = bw + s;
+            if (aw + q < A.nvx && bb < A.nvy) {
+                const int vr = kVYW * yp + s;  // velocity row within the block
+                float rsm[kRowsW];  // this row half's multipliers (uniform)
+                const f4* src = reinterpret_cast<const f4*>(sRM + vr * kRows + h * kRowsW);
 #pragma unroll
-            for (int k = 0; k < kRows / 4; ++k) {
-                const f4 t = src[k];
-                rsm[4 * k] = t.x;
-                rsm[4 * k + 1] = t.y;
-                rsm[4 * k + 2] = t.z;
-                rsm[4 * k + 3] = t.w;
+                for (int k = 0; k < kRowsW / 4; ++k) {
+                    const f4 t = src[k];
+                    rsm[4 * k] = t.x;
+                    rsm[4 * k + 1] = t.y;
+                    rsm[4 * k + 2] = t.z;
+                    rsm[4 * k + 3] = t.w;
+                }
+                detect_epilogue(A, acc[q][s], rsm, aw + q, bb, x, xin, lane, h, Y0, tile, col,
+                                xin_rows + (q * kVYW + s) * kWave, sIY + (vr * kRows + R0) * 2, sRS + vr * kRows + R0,
+                                P, xlo[q], xhi[q]);
             }
-        }
-        auto epi = [&](const double* P) {
-            if (aw + 0 < A.nvx)
-                detect_epilogue(A, acc[0], rsm, aw + 0, b, x, xin, lane, Y0, tile, col, IYr, RSr, P, xlo[0], xhi[0]);
             __builtin_amdgcn_sched_barrier(0);
-            if (aw + 1 < A.nvx)
-                detect_epilogue(A, acc[1], rsm, aw + 1, b, x, xin, lane, Y0, tile, col, IYr, RSr, P, xlo[1], xhi[1]);
-            __builtin_amdgcn_sched_barrier(0);
-            if (aw + 2 < A.nvx)
-                detect_epilogue(A, acc[2], rsm, aw + 2, b, x, xin, lane, Y0, tile, col, IYr, RSr, P, xlo[2], xhi[2]);
         };
+        auto epi = [&](const double* P) __attribute__((always_inline)) {
+            one(ic<0>{}, ic<0>{}, P);
+            one(ic<0>{}, ic<1>{}, P);
+            one(ic<1>{}, ic<0>{}, P);
+            one(ic<1>{}, ic<1>{}, P);
+            one(ic<2>{}, ic<0>{}, P);
+            one(ic<2>{}, ic<1>{}, P);
+        };
+        static_assert(kVPW == 3 && kVYW == 2, "one call per velocity of the wave");
         // two instantiations so that the common one reads the prefix from LDS
         if (p_lds)
             epi(sP);
@@ -700,7 +777,7 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
 // One workgroup per velocity: gather the entries kept by every tile, rank
 // them by key and write the first k_max in order; count = all candidates.
 __global__ __launch_bounds__(kAux) void k_merge(const int32_t* __restrict__ tcount, const Entry* __restrict__ ent,
-                                                   int ntiles, int kt, int k_max, int nvx, int w, int k_first,
+                                                   int nslot, int kt, int k_max, int nvx, int w, int k_first,
                                                    sst_candidate* __restrict__ cand, int32_t* __restrict__ count) {
     const int kc = blockIdx.x;
     const int k = k_first + kc;
@@ -712,10 +789,10 @@ __global__ __launch_bounds__(kAux) void k_merge(const int32_t* __restrict__ tcou
     __shared__ long long bi[4];
     if (threadIdx.x == 0) nst = 0;
     __syncthreads();
-    const int32_t* tc = tcount + (long long)kc * ntiles;
-    const Entry* E = ent + (long long)kc * ntiles * kt;
+    const int32_t* tc = tcount + (long long)kc * nslot;
+    const Entry* E = ent + (long long)kc * nslot * kt;
     long long tot = 0;
-    for (int t = threadIdx.x; t < ntiles; t += kAux) {
+    for (int t = threadIdx.x; t < nslot; t += kAux) {
         const int c = tc[t];
         tot += c;
         const int s = min(c, kt);
@@ -757,7 +834,7 @@ __global__ __launch_bounds__(kAux) void k_merge(const int32_t* __restrict__ tcou
         for (int r = 0; r < nout; ++r) {
             unsigned long long best = 0;
             long long bidx = -1;
-            for (int t = threadIdx.x; t < ntiles; t += kAux) {
+            for (int t = threadIdx.x; t < nslot; t += kAux) {
                 const int s = min(tc[t], kt);
                 for (int e = 0; e < s; ++e) {
                     const Entry en = E[(long long)t * kt + e];
@@ -849,9 +926,9 @@ hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int ntiles, int kt, int k_max, int nvx, int w,
+hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int nslot, int kt, int k_max, int nvx, int w,
                         int k_first, int nk, void* cand, int32_t* count, hipStream_t s) {
-    hipLaunchKernelGGL(k_merge, dim3(nk), dim3(kAux), 0, s, tcount, ent, ntiles, kt, k_max, nvx, w, k_first,
+    hipLaunchKernelGGL(k_merge, dim3(nk), dim3(kAux), 0, s, tcount, ent, nslot, kt, k_max, nvx, w, k_first,
                        static_cast<sst_candidate*>(cand), count);
     return hipGetLastError();
 }
