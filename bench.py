@@ -15,6 +15,7 @@ workload.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -32,6 +33,36 @@ PEAK_FP32_ADD_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
+# Profile summary of the stacking kernel on the full field, holding the HBM
+# bytes per launch measured with the profiler's FETCH_SIZE / WRITE_SIZE
+# counters (each scaled by what the counter reads for a plain 1 GiB copy) and
+# a hash of the kernel sources it was taken on.
+PROFILE = os.path.join(ROOT, "profiles", "k_stack_detect_64x1024x1024_grid81x81.md")
+KERNEL_SOURCES = ("paper_2303_07293_amd/csrc/sst_kernels.hip", "paper_2303_07293_amd/csrc/sst_internal.h",
+                  "paper_2303_07293_amd/csrc/sst_api.cpp")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the stacking kernel from the committed profile,
+    or None if the kernel sources changed since the counters were taken."""
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16] or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(f, n_vel: int, seed: int = 0):
     import oracle
     rng = np.random.default_rng(seed)
@@ -46,6 +77,18 @@ def cpu_baseline(f, n_vel: int, seed: int = 0):
                       f"numpy float64 oracle incl. frame statistics, {dt:.1f} s"}
 
 
+def copy_reference(torch, mib: int):
+    """A plain copy of known size on the device (read mib MiB, write mib MiB)."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": mib, "bytes_read": n * 4, "bytes_written": n * 4, "repeats": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +96,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["full", "tiny"], default="full")
     ap.add_argument("--cpu-velocities", type=int, default=32, help="oracle sample size (0: skip)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (three times) and exit: "
+                         "the reference point that scales the HBM byte counters of a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -61,6 +107,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_mib > 0:
+        copy_reference(torch, args.copy_mib)
+        return
     import synth
     import paper_2303_07293_amd as sst
 
@@ -95,7 +144,8 @@ def main():
     kern_ms_step = kern_ms / args.steps
     achieved = updates / (kern_ms_step * 1e-3) / 1e12  # TFLOP/s at one FP32 add per update
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_ADD_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_ADD_TFLOPS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_FP32_ADD_TFLOPS, 4),
+            "traffic": measured_traffic() if args.workload == "full" else None, "traffic_unit": "B/launch",
             "kernel": "k_stack<detect>", "kernel_ms_per_step": round(kern_ms_step, 4),
             "launches_per_step": launches / args.steps}
     out = {
