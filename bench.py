@@ -89,12 +89,57 @@ def copy_reference(torch, mib: int):
     print(json.dumps({"copy_mib": mib, "bytes_read": n * 4, "bytes_written": n * 4, "repeats": 3}), flush=True)
 
 
+def prep_bench(torch, sst, args):
+    """The steps the paper runs before the search, on survey-shaped frames:
+    64 raw 2048x2048 frames binned 2x2, then static-source removal by the
+    per-pixel median and co-adding of 13-frame groups on the binned frames.
+    Each is HBM-bound: reported as algorithmic bytes (read once + written
+    once) per kernel time against the HBM peak."""
+    import synth
+    n, side, group = 64, 2048, 13
+    rng = np.random.default_rng(synth.SEED_BASE + 5)
+    raw = torch.from_numpy(rng.normal(100.0, 10.0, size=(n, side, side)).astype(np.float32)).to("cuda:0")
+    binned = sst.sst_bin2x2(raw)
+    torch.cuda.synchronize()
+    h = w = side // 2
+    ng = n // group
+    cases = {
+        "bin2x2": (lambda: sst.sst_bin2x2(raw), 4 * n * side * side + 4 * n * h * w),
+        "median_subtract": (lambda: sst.sst_median_subtract(binned), 4 * n * h * w * 2),
+        "coadd13": (lambda: sst.sst_coadd(binned, group), 4 * ng * group * h * w + 4 * ng * h * w),
+    }
+    res = {}
+    for name, (fn, nbytes) in cases.items():
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[name] = {"ms": round(ms, 4), "bytes": nbytes, "GB/s": round(gbs, 1),
+                     "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    print(json.dumps({"metric": "preprocessing HBM throughput", "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"prep {n}x{side}x{side} -> bin 2x2 -> median, co-add {group}"},
+                      "kernels": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["full", "tiny"], default="full")
+    ap.add_argument("--workload", choices=["full", "tiny", "prep"], default="full",
+                    help="full: the search on the full field; tiny: the small field; prep: the steps before the "
+                         "search (2x2 binning, median removal, co-adding) timed on their own")
+    ap.add_argument("--storage", choices=["f32", "bf16", "f16"], default="f32",
+                    help="frame storage: 16-bit frames with per-frame scales (quantised on the GPU before the "
+                         "timed region); arithmetic stays float32")
     ap.add_argument("--cpu-velocities", type=int, default=32, help="oracle sample size (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (three times) and exit: "
@@ -112,10 +157,19 @@ def main():
         return
     import synth
     import paper_2303_07293_amd as sst
+    if args.workload == "prep":
+        prep_bench(torch, sst, args)
+        return
 
     f = synth.config2() if args.workload == "full" else synth.config1()
     dev = torch.device("cuda:0")
     frames = torch.from_numpy(f.frames).to(dev)
+    scale = None
+    if args.storage != "f32":
+        # centred storage: each frame's mean removed before rounding (S/N unchanged)
+        frames, scale, _ = sst.sst_quantize(frames, torch.bfloat16 if args.storage == "bf16" else torch.float16,
+                                            center=True)
+        torch.cuda.synchronize()
     n, h, w = f.frames.shape
     nk = len(f.vx) * len(f.vy)
     nb = sst.sst_workspace_bytes(sst.SST_OP_DETECT, n, h, w, f.t, f.t_ref, f.vx, f.vy, f.k_max)
@@ -125,7 +179,7 @@ def main():
 
     def step():
         sst.sst_detect(frames, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max,
-                       ws=ws, cand=cand, count=count)
+                       scale=scale, ws=ws, cand=cand, count=count)
 
     for _ in range(args.warmup):
         step()
@@ -152,7 +206,7 @@ def main():
         "metric": "frame*pixel*velocity updates/s", "value": value, "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f.name, "frames": n, "height": h, "width": w, "velocities": nk,
+        "config": {"workload": f.name, "storage": args.storage, "frames": n, "height": h, "width": w, "velocities": nk,
                    "threshold": f.threshold, "k_max": f.k_max, "candidates_last_step": int(count.sum().item())},
         "roofline": roof,
     }

@@ -55,7 +55,11 @@ extern "C" {
 #define SST_E_DEVICE (-5)      /* a HIP runtime call failed */
 #define SST_E_UNSUPPORTED (-6) /* valid request this build does not handle */
 
-/* frame storage types */
+/* frame storage types.  16-bit frames carry a per-frame float32 scale s_i:
+ * the frame value is the float32 product s_i * (stored value), and every
+ * later step (statistics, stacking, S/N) works on those float32 values
+ * exactly as on float32 frames; sums stay float32.  Storage only: the
+ * search itself is not computed in 16 bits. */
 #define SST_F32 0
 #define SST_BF16 1
 #define SST_F16 2
@@ -64,6 +68,7 @@ extern "C" {
 #define SST_OP_STACK 0
 #define SST_OP_DETECT 1
 #define SST_OP_STATS 2
+#define SST_OP_QUANT 3
 
 /* plain-stack modes */
 #define SST_SUM 0
@@ -87,11 +92,34 @@ typedef struct sst_candidate {
 int sst_shift_table(const double* t, int n, double t_ref, const double* v, int nv, int32_t* out);
 
 /* Bytes of device workspace an operation needs for this problem (0 on error,
- * with sst_last_error set).  op = SST_OP_STACK, SST_OP_DETECT or SST_OP_STATS;
+ * with sst_last_error set).  op = SST_OP_STACK, SST_OP_DETECT, SST_OP_STATS or
+ * SST_OP_QUANT (the last two need only n, h, w);
  * the shift tables enter because the zero-padded frame copy is sized by the
  * largest shift.  k_max is used by SST_OP_DETECT only. */
 size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double t_ref,
                            const double* vx, int nvx, const double* vy, int nvy, int k_max);
+
+/* 16-bit storage of float32 frames with a per-frame offset and scale (a
+ * data-layout step before the search, not part of the paper's method):
+ *   offset[i] = float32 of the float64 mean of frame i if center != 0, else 0
+ *   scale[i]  = max_p |F_i(p) - offset[i]| * 2^-14   (1 for a constant frame)
+ *   q[i][p]   = round-to-nearest-even of the float32 quotient
+ *               fl32(F_i(p) - offset[i]) / scale[i]
+ * in bfloat16 (dtype SST_BF16) or IEEE half (SST_F16), as raw 16-bit words.
+ * |q| <= 2^14, so neither format overflows; IEEE half keeps 11 significant
+ * bits and bfloat16 8.  The stored frame value is scale[i] * q (pass q and
+ * scale to the search as 16-bit frames); with center != 0 it is the frame
+ * minus its offset, which leaves every S/N unchanged (the search removes
+ * each frame's mean) while the rounding error scales with |F - mean| rather
+ * than |F|.  Add offset[i] back for absolute levels.
+ * frames: dev float32 [n][h][w] (finite); q: dev uint16 [n][h][w];
+ * scale: dev float32 [n]; offset: dev float32 [n], written only when
+ * center != 0 (may be NULL otherwise).
+ * ws: dev, >= sst_workspace_bytes(SST_OP_QUANT, ...).
+ * Errors: SST_E_ARG (NULL pointer, dtype not 16-bit, bad size),
+ * SST_E_WORKSPACE.  Asynchronous on `stream`. */
+int sst_quantize(const float* frames, int n, int h, int w, int dtype, int center, void* q, float* scale,
+                 float* offset, void* ws, size_t ws_bytes, void* stream);
 
 /* Per-frame statistics (the S/N normaliser's inputs): stats[2i] = mean of
  * frame i, stats[2i+1] = population variance, both float64, dev [n][2].
@@ -129,6 +157,38 @@ int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, 
                float threshold, int min_coverage, int k_max,
                sst_candidate* cand, int32_t* count, double* frame_stats,
                void* ws, size_t ws_bytes, void* stream);
+
+/* ---- steps the paper runs before the search (float32 frames) ----
+ * out must not overlap frames in any of the three. */
+
+/* Static-source removal (paper Sec. 2.1: the median combination of a group's
+ * frames is removed from each frame, leaving moving sources):
+ *   med(p)    = median over i of F_i(p)  (odd n: the middle value; even n:
+ *               the float32 mean of the two middle values, (a + b) * 0.5)
+ *   out_i(p)  = F_i(p) - med(p)          (one float32 subtraction)
+ * frames, out: dev float32 [n][h][w]; median: dev float32 [h][w] receiving
+ * med, or NULL.  n <= 256 (SST_E_UNSUPPORTED beyond).  Finite input.
+ * Errors: SST_E_ARG, SST_E_UNSUPPORTED, SST_E_DEVICE.  Asynchronous. */
+int sst_median_subtract(const float* frames, int n, int h, int w, float* out, float* median, void* stream);
+
+/* Co-adding (paper Sec. 2.1 and 2.2: every N consecutive frames are summed
+ * into one longer exposure for the slow-mover search):
+ *   out[g][p] = sum over j < group, ascending j, of F[g*group + j][p]  (float32)
+ * for the n / group complete groups (trailing frames that do not fill a
+ * group are not used).  t: host [n] or NULL; t_out: host [n / group]
+ * receiving each group's mean timestamp (float64), or NULL (needs t).
+ * frames: dev float32 [n][h][w]; out: dev float32 [n / group][h][w].
+ * Errors: SST_E_ARG (group outside 1..n, NULL pointers, non-finite t),
+ * SST_E_DEVICE.  Asynchronous on `stream` (t_out is written before return). */
+int sst_coadd(const float* frames, int n, int h, int w, int group, float* out, const double* t, double* t_out,
+              void* stream);
+
+/* 2x2 binning (paper Sec. 2.3: binned frames for the fast-mover search):
+ *   out[i][y][x] = (F[2y][2x] + F[2y][2x+1]) + (F[2y+1][2x] + F[2y+1][2x+1])
+ * summed in float32 in that order; an odd last row or column is dropped.
+ * frames: dev float32 [n][h][w] (h, w >= 2); out: dev float32
+ * [n][h/2][w/2].  Errors: SST_E_ARG, SST_E_DEVICE.  Asynchronous. */
+int sst_bin2x2(const float* frames, int n, int h, int w, float* out, void* stream);
 
 /* Kernel timing for measurements.  Between sst_profile_begin() and
  * sst_profile_end(), every launch of the stacking kernel (the dominant cost

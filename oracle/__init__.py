@@ -15,6 +15,9 @@ values), written from the paper's statement of the method:
   finds movers that show in half or more of a group's frames.
 
 The readings taken where the paper is silent are listed in `sst_oracle.py`.
+`quant.py` holds the 16-bit storage format (a data-layout step, not part of
+the paper's method); `prep.py` the steps the paper runs before the search
+(static-source removal by the median, co-adding, 2x2 binning).
 """
 
 from .sst_oracle import (  # noqa: F401
@@ -30,3 +33,5 @@ from .sst_oracle import (  # noqa: F401
     stack,
     stack_velocity,
 )
+from .quant import dequantize_frames, frame_offsets, frame_scales, quantize_frames  # noqa: F401,E402
+from .prep import bin2x2, coadd, median_subtract  # noqa: F401,E402

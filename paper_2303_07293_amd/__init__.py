@@ -13,17 +13,22 @@ from .binding import (  # noqa: F401
     SST_F32,
     SST_MEAN,
     SST_OP_DETECT,
+    SST_OP_QUANT,
     SST_OP_STACK,
     SST_OP_STATS,
     SST_SUM,
     SstError,
     candidates_to_numpy,
     load,
+    sst_bin2x2,
+    sst_coadd,
     sst_detect,
     sst_frame_stats,
     sst_last_error,
+    sst_median_subtract,
     sst_profile_begin,
     sst_profile_end,
+    sst_quantize,
     sst_shift_table,
     sst_stack,
     sst_workspace_bytes,

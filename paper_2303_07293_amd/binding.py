@@ -26,7 +26,7 @@ SST_E_DEVICE = -5
 SST_E_UNSUPPORTED = -6
 
 SST_F32, SST_BF16, SST_F16 = 0, 1, 2
-SST_OP_STACK, SST_OP_DETECT, SST_OP_STATS = 0, 1, 2
+SST_OP_STACK, SST_OP_DETECT, SST_OP_STATS, SST_OP_QUANT = 0, 1, 2, 3
 SST_SUM, SST_MEAN = 0, 1
 
 # the 32-byte sst_candidate record
@@ -35,7 +35,8 @@ CANDIDATE_DTYPE = np.dtype([
     ("snr", np.float32), ("flux", np.float32), ("coverage", np.int32), ("rank", np.int32),
 ])
 
-EXPORTS = ("sst_shift_table", "sst_workspace_bytes", "sst_frame_stats", "sst_stack", "sst_detect",
+EXPORTS = ("sst_shift_table", "sst_workspace_bytes", "sst_quantize", "sst_median_subtract", "sst_coadd", "sst_bin2x2",
+           "sst_frame_stats", "sst_stack", "sst_detect",
            "sst_profile_begin", "sst_profile_end", "sst_last_error", "sst_version")
 
 
@@ -67,6 +68,14 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.sst_shift_table.restype = _i
     lib.sst_workspace_bytes.argtypes = [_i, _i, _i, _i, _p, _d, _p, _i, _p, _i, _i]
     lib.sst_workspace_bytes.restype = _sz
+    lib.sst_quantize.argtypes = [_p, _i, _i, _i, _i, _i, _p, _p, _p, _p, _sz, _p]
+    lib.sst_quantize.restype = _i
+    lib.sst_median_subtract.argtypes = [_p, _i, _i, _i, _p, _p, _p]
+    lib.sst_median_subtract.restype = _i
+    lib.sst_coadd.argtypes = [_p, _i, _i, _i, _i, _p, _p, _p, _p]
+    lib.sst_coadd.restype = _i
+    lib.sst_bin2x2.argtypes = [_p, _i, _i, _i, _p, _p]
+    lib.sst_bin2x2.restype = _i
     lib.sst_frame_stats.argtypes = [_p, _i, _p, _i, _i, _i, _p, _p, _sz, _p]
     lib.sst_frame_stats.restype = _i
     lib.sst_stack.argtypes = [_p, _i, _p, _i, _i, _i, _p, _d, _p, _i, _p, _i, _p, _i, _p, _p, _p, _sz, _p]
@@ -159,6 +168,86 @@ def _workspace(nbytes: int, device, ws=None):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
+def sst_quantize(frames, dtype, center: bool = False, ws=None):
+    """16-bit copy of float32 frames with per-frame scales (see sst.h).
+
+    dtype is torch.bfloat16 or torch.float16.  Returns (q, scale, offset): q
+    has that dtype and the frames' shape, scale and offset are float32 [n];
+    frame value = scale[i] * q[i] (+ offset[i] for absolute levels; offset is
+    zero unless center)."""
+    import torch
+    _check_frames(frames)
+    if frames.dtype != torch.float32:
+        raise TypeError("sst_quantize takes float32 frames")
+    code = {torch.bfloat16: SST_BF16, torch.float16: SST_F16}.get(dtype)
+    if code is None:
+        raise TypeError(f"dtype {dtype} is not bfloat16/float16")
+    n, h, w = frames.shape
+    nb = sst_workspace_bytes(SST_OP_QUANT, n, h, w)
+    ws = _workspace(nb, frames.device, ws)
+    q = torch.empty((n, h, w), dtype=dtype, device=frames.device)
+    scale = torch.empty((n,), dtype=torch.float32, device=frames.device)
+    offset = torch.zeros((n,), dtype=torch.float32, device=frames.device)
+    _check(load().sst_quantize(_dev(frames), n, h, w, code, int(bool(center)), _dev(q), _dev(scale), _dev(offset),
+                               _dev(ws), ws.numel(), _stream(frames.device)))
+    return q, scale, offset
+
+
+def _f32_frames(frames):
+    import torch
+    _check_frames(frames)
+    if frames.dtype != torch.float32:
+        raise TypeError("float32 frames expected")
+    return frames.shape
+
+
+def sst_median_subtract(frames, out=None, with_median: bool = False):
+    """F_i - (per-pixel median over the frames); float32 [n][h][w] (and the
+    median [h][w] if asked)."""
+    import torch
+    n, h, w = _f32_frames(frames)
+    if out is None:
+        out = torch.empty_like(frames)
+    med = torch.empty((h, w), dtype=torch.float32, device=frames.device) if with_median else None
+    _check(load().sst_median_subtract(_dev(frames), n, h, w, _dev(out), _dev(med), _stream(frames.device)))
+    return (out, med) if with_median else out
+
+
+def sst_coadd(frames, group: int, t=None):
+    """Sums of each complete group of `group` consecutive frames:
+    float32 [n // group][h][w] (and the groups' mean timestamps if t given)."""
+    import torch
+    n, h, w = _f32_frames(frames)
+    ng = n // group if group >= 1 else 0
+    out = torch.empty((max(ng, 1), h, w), dtype=torch.float32, device=frames.device)
+    tv = None if t is None else _f64(t)
+    if tv is not None and len(tv) != n:
+        raise ValueError("t must have one value per frame")
+    t_out = None if tv is None else np.empty(max(ng, 1), dtype=np.float64)
+    _check(load().sst_coadd(_dev(frames), n, h, w, int(group), _dev(out), _ptr(tv), _ptr(t_out),
+                            _stream(frames.device)))
+    out = out[:ng]
+    return (out, t_out[:ng]) if tv is not None else out
+
+
+def sst_bin2x2(frames):
+    """2x2 block sums: float32 [n][h // 2][w // 2]."""
+    import torch
+    n, h, w = _f32_frames(frames)
+    out = torch.empty((n, max(h // 2, 1), max(w // 2, 1)), dtype=torch.float32, device=frames.device)
+    _check(load().sst_bin2x2(_dev(frames), n, h, w, _dev(out), _stream(frames.device)))
+    return out
+
+
+def _check_scale(frames, scale):
+    import torch
+    if frames.dtype == torch.float32:
+        return None if scale is None else _dev(scale)
+    if scale is None or scale.dtype != torch.float32 or not scale.is_cuda or scale.numel() != frames.shape[0]:
+        raise ValueError("16-bit frames need a float32 device tensor of per-frame scales")
+    return _dev(scale.contiguous())
+
+
 def sst_frame_stats(frames, scale=None, ws=None):
     """Per-frame (mean, population variance), float64 [n][2] on the device."""
     import torch
@@ -167,7 +256,8 @@ def sst_frame_stats(frames, scale=None, ws=None):
     nb = sst_workspace_bytes(SST_OP_STATS, n, h, w)
     ws = _workspace(nb, frames.device, ws)
     stats = torch.empty((n, 2), dtype=torch.float64, device=frames.device)
-    _check(load().sst_frame_stats(_dev(frames), _frames_dtype(frames), _dev(scale), n, h, w, _dev(stats),
+    _check(load().sst_frame_stats(_dev(frames), _frames_dtype(frames), _check_scale(frames, scale), n, h, w,
+                                  _dev(stats),
                                   _dev(ws), ws.numel(), _stream(frames.device)))
     return stats
 
@@ -188,7 +278,8 @@ def sst_stack(frames, t, t_ref: float, vx, vy, bg=None, mode: int = SST_SUM, wit
         out = torch.empty((len(vy), len(vx), h, w), dtype=torch.float32, device=frames.device)
     if with_coverage and cov is None:
         cov = torch.empty((len(vy), len(vx), h, w), dtype=torch.int32, device=frames.device)
-    _check(load().sst_stack(_dev(frames), _frames_dtype(frames), _dev(scale), n, h, w, _ptr(t), float(t_ref),
+    _check(load().sst_stack(_dev(frames), _frames_dtype(frames), _check_scale(frames, scale), n, h, w, _ptr(t),
+                            float(t_ref),
                             _ptr(vx), len(vx), _ptr(vy), len(vy), _ptr(bgv), mode, _dev(out), _dev(cov), _dev(ws),
                             ws.numel(), _stream(frames.device)))
     return (out, cov) if with_coverage else out
@@ -214,7 +305,8 @@ def sst_detect(frames, t, t_ref: float, vx, vy, threshold: float, min_coverage: 
     if count is None:
         count = torch.empty((nk,), dtype=torch.int32, device=frames.device)
     stats = np.empty((n, 2), dtype=np.float64) if want_stats else None
-    _check(load().sst_detect(_dev(frames), _frames_dtype(frames), _dev(scale), n, h, w, _ptr(t), float(t_ref),
+    _check(load().sst_detect(_dev(frames), _frames_dtype(frames), _check_scale(frames, scale), n, h, w, _ptr(t),
+                             float(t_ref),
                              _ptr(vx), len(vx), _ptr(vy), len(vy), float(threshold), int(min_coverage), int(k_max),
                              _dev(cand), _dev(count), _ptr(stats), _dev(ws), ws.numel(), _stream(frames.device)))
     return (cand, count, stats) if want_stats else (cand, count)

@@ -109,7 +109,7 @@ struct Plan {
     std::vector<int32_t> DX, DY;
     // workspace offsets (bytes)
     size_t o_tab = 0, o_part = 0, o_b = 0, o_s2 = 0, o_P = 0, o_b32 = 0, o_sdev = 0;
-    size_t o_ix = 0, o_iy = 0, o_pad = 0, o_tcount = 0, o_ent = 0, total = 0;
+    size_t o_ix = 0, o_iy = 0, o_pad = 0, o_tcount = 0, o_ent = 0, o_qpart = 0, total = 0;
 };
 
 size_t take(size_t& cur, size_t bytes) {
@@ -128,7 +128,8 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
     p.w = w;
     p.nchunk = (int)(((long long)h * w + kStatChunk - 1) / kStatChunk);
     size_t cur = 0;
-    if (op == SST_OP_STATS) {
+    if (op == SST_OP_STATS || op == SST_OP_QUANT) {
+        if (op == SST_OP_QUANT) p.o_qpart = take(cur, (size_t)n * p.nchunk * sizeof(float));
         p.o_part = take(cur, (size_t)n * p.nchunk * 3 * sizeof(double));
         p.o_b = take(cur, (size_t)n * sizeof(double));
         p.o_s2 = take(cur, (size_t)n * sizeof(double));
@@ -218,7 +219,7 @@ int check_frames(const void* frames, int dtype, const float* scale) {
     if (!frames) return fail(SST_E_ARG, "frames is NULL");
     if (dtype == SST_BF16 || dtype == SST_F16) {
         if (!scale) return fail(SST_E_ARG, "16-bit frames need a per-frame scale array");
-        return fail(SST_E_UNSUPPORTED, "16-bit frame storage is not implemented in this build");
+        return SST_OK;
     }
     if (dtype != SST_F32) return fail(SST_E_ARG, "unknown frame dtype %d", dtype);
     return SST_OK;
@@ -288,9 +289,12 @@ StackArgs stack_args(const Plan& p, void* ws) {
     return a;
 }
 
-int prep_and_cov(const Plan& p, const void* frames, const float* b32, void* ws, hipStream_t s) {
+int prep_and_cov(const Plan& p, const void* frames, int dtype, const float* scale, const float* b32, void* ws,
+                 hipStream_t s) {
     PrepArgs pa{};
-    pa.frames = static_cast<const float*>(frames);
+    pa.frames = frames;
+    pa.dtype = dtype;
+    pa.scale = scale;
     pa.b32 = b32;
     pa.pad = at<float>(ws, p.o_pad);
     pa.n = p.n;
@@ -406,6 +410,76 @@ size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double 
     return p.total;
 }
 
+int sst_quantize(const float* frames, int n, int h, int w, int dtype, int center, void* q, float* scale,
+                 float* offset, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (!frames || !q || !scale) return fail(SST_E_ARG, "frames, q and scale must not be NULL");
+    if (dtype != SST_BF16 && dtype != SST_F16) return fail(SST_E_ARG, "quantize: dtype %d is not 16-bit", dtype);
+    if (center && !offset) return fail(SST_E_ARG, "quantize: center needs an offset array");
+    Plan p;
+    int rc;
+    if ((rc = make_plan(SST_OP_QUANT, n, h, w, nullptr, 0, nullptr, 0, nullptr, 0, 0, p))) return rc;
+    if ((rc = check_ws(p, ws, ws_bytes))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (center) {
+        // offset = float32 of each frame's float64 mean (the statistics kernels)
+        e = launch_stats(frames, SST_F32, nullptr, n, h, w, at<double>(ws, p.o_part), p.nchunk, at<double>(ws, p.o_b),
+                         at<double>(ws, p.o_s2), offset, at<double>(ws, p.o_P), nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
+    }
+    e = launch_quantize(frames, n, h, w, dtype, center ? offset : nullptr, at<float>(ws, p.o_qpart), p.nchunk, scale,
+                        q, s);
+    if (e != hipSuccess) return hip_fail(e, "quantize kernels");
+    return SST_OK;
+}
+
+int sst_median_subtract(const float* frames, int n, int h, int w, float* out, float* median, void* stream) {
+    g_err.clear();
+    int rc = check_dims(n, h, w);
+    if (rc) return rc;
+    if (!frames || !out) return fail(SST_E_ARG, "frames and out must not be NULL");
+    if (n > kMedianMaxFrames)
+        return fail(SST_E_UNSUPPORTED, "median of %d frames: at most %d per call", n, kMedianMaxFrames);
+    hipError_t e = launch_median_sub(frames, n, h, w, out, median, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "median kernel");
+    return SST_OK;
+}
+
+int sst_coadd(const float* frames, int n, int h, int w, int group, float* out, const double* t, double* t_out,
+              void* stream) {
+    g_err.clear();
+    int rc = check_dims(n, h, w);
+    if (rc) return rc;
+    if (!frames || !out) return fail(SST_E_ARG, "frames and out must not be NULL");
+    if (group < 1 || group > n) return fail(SST_E_ARG, "group = %d: need 1..n (%d)", group, n);
+    if (t_out && !t) return fail(SST_E_ARG, "t_out needs t");
+    const int ng = n / group;
+    if (t_out) {
+        for (int i = 0; i < n; ++i)
+            if (!std::isfinite(t[i])) return fail(SST_E_ARG, "t[%d] is not finite", i);
+        for (int g = 0; g < ng; ++g) {
+            double acc = 0.0;
+            for (int j = 0; j < group; ++j) acc += t[g * group + j];
+            t_out[g] = acc / group;
+        }
+    }
+    hipError_t e = launch_coadd(frames, h, w, group, ng, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "co-add kernel");
+    return SST_OK;
+}
+
+int sst_bin2x2(const float* frames, int n, int h, int w, float* out, void* stream) {
+    g_err.clear();
+    int rc = check_dims(n, h, w);
+    if (rc) return rc;
+    if (!frames || !out) return fail(SST_E_ARG, "frames and out must not be NULL");
+    if (h < 2 || w < 2) return fail(SST_E_ARG, "binning needs frames of at least 2x2 (got %dx%d)", w, h);
+    hipError_t e = launch_bin2x2(frames, n, h, w, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "binning kernel");
+    return SST_OK;
+}
+
 int sst_frame_stats(const void* frames, int dtype, const float* scale, int n, int h, int w, double* stats, void* ws,
                     size_t ws_bytes, void* stream) {
     g_err.clear();
@@ -416,7 +490,7 @@ int sst_frame_stats(const void* frames, int dtype, const float* scale, int n, in
     if ((rc = make_plan(SST_OP_STATS, n, h, w, nullptr, 0, nullptr, 0, nullptr, 0, 0, p))) return rc;
     if ((rc = check_ws(p, ws, ws_bytes))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_stats(static_cast<const float*>(frames), n, h, w, at<double>(ws, p.o_part), p.nchunk,
+    hipError_t e = launch_stats(frames, dtype, scale, n, h, w, at<double>(ws, p.o_part), p.nchunk,
                                 at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
                                 at<double>(ws, p.o_P), stats, s);
     if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
@@ -439,7 +513,7 @@ int sst_stack(const void* frames, int dtype, const float* scale, int n, int h, i
     if ((rc = check_ws(p, ws, ws_bytes))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((rc = upload_tables(p, bg, ws, s))) return rc;
-    if ((rc = prep_and_cov(p, frames, bg ? at<float>(ws, p.o_b32) : nullptr, ws, s))) return rc;
+    if ((rc = prep_and_cov(p, frames, dtype, scale, bg ? at<float>(ws, p.o_b32) : nullptr, ws, s))) return rc;
     StackArgs a = stack_args(p, ws);
     a.out = out;
     a.cov = cov;
@@ -462,11 +536,11 @@ int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, 
     if ((rc = check_ws(p, ws, ws_bytes))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((rc = upload_tables(p, nullptr, ws, s))) return rc;
-    hipError_t e = launch_stats(static_cast<const float*>(frames), n, h, w, at<double>(ws, p.o_part), p.nchunk,
+    hipError_t e = launch_stats(frames, dtype, scale, n, h, w, at<double>(ws, p.o_part), p.nchunk,
                                 at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
                                 at<double>(ws, p.o_P), at<double>(ws, p.o_sdev), s);
     if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
-    if ((rc = prep_and_cov(p, frames, at<float>(ws, p.o_b32), ws, s))) return rc;
+    if ((rc = prep_and_cov(p, frames, dtype, scale, at<float>(ws, p.o_b32), ws, s))) return rc;
     StackArgs a = stack_args(p, ws);
     a.thr = threshold;
     a.cmin = min_coverage > 0 ? min_coverage : (n + 1) / 2;

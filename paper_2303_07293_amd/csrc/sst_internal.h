@@ -92,21 +92,31 @@ struct StackArgs {
 };
 
 struct PrepArgs {
-    const float* frames;
-    const float* b32;  // [n] subtracted per frame, or nullptr
+    const void* frames;  // [n][h][w] of dtype
+    int dtype;           // SST_F32, SST_BF16, SST_F16
+    const float* scale;  // [n] per-frame multiplier of 16-bit frames
+    const float* b32;    // [n] subtracted per frame, or nullptr
     float* pad;
     int n, h, w, Hp, Wp, padL, padT;
 };
 
 // launch wrappers (sst_kernels.hip); each returns a hipError_t
-hipError_t launch_stats(const float* frames, int n, int h, int w, double* part, int nchunk,
-                        double* b, double* s2, float* b32, double* P, double* stats_dev,
-                        hipStream_t s);
+hipError_t launch_stats(const void* frames, int dtype, const float* scale, int n, int h, int w,
+                        double* part, int nchunk, double* b, double* s2, float* b32, double* P,
+                        double* stats_dev, hipStream_t s);
+hipError_t launch_quantize(const float* frames, int n, int h, int w, int dtype, const float* offset,
+                           float* part, int nchunk, float* scale, void* q, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_cov(const int* D, int ld, int n, int nv, int size, int* I, hipStream_t s);
 hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, hipStream_t s);
 hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int nslot, int kt, int k_max,
                         int nvx, int w, int k_first, int nk, void* cand, int32_t* count,
                         hipStream_t s);
+
+// preprocessing kernels (sst_prep.hip)
+constexpr int kMedianMaxFrames = 256;  // frames staged in LDS per pixel column
+hipError_t launch_median_sub(const float* F, int n, int h, int w, float* out, float* med, hipStream_t s);
+hipError_t launch_coadd(const float* F, int h, int w, int group, int ng, float* out, hipStream_t s);
+hipError_t launch_bin2x2(const float* F, int n, int h, int w, float* out, hipStream_t s);
 
 }  // namespace sst

@@ -5,7 +5,8 @@
 // Data flow of one detect call (paper Sec. 2.1: remove the static sky, shift
 // each frame along a trial linear motion, sum, keep significant peaks):
 //   k_stats_partial/k_stats_final  per-frame mean b_i, variance s2_i, prefix P
-//   k_prep                         zero-padded copy of F_i - b_i (float32)
+//   k_prep                         zero-padded copy of F_i - b_i (float32);
+//                                  16-bit frames are scaled to float32 here
 //   k_cov                          per (velocity component, coordinate) the
 //                                  first/last frame whose sample is in frame
 //   k_stack<detect>                accumulate, S/N, 8-neighbour peaks, keep the
@@ -100,13 +101,32 @@ __device__ __forceinline__ void load_iv(const int* I, long long e, int& lo, int&
     hi = (int)(v >> 32);
 }
 
+// ------------------------------------------------------------ frame values
+// Frame value of a stored sample: float32 as is, or a 16-bit sample times
+// its frame's scale (one float32 product; the 16-bit to float32 conversion
+// is exact).
+template <int DT>
+__device__ __forceinline__ float frame_value(const void* f, long long e, float sc) {
+    if constexpr (DT == SST_F32) {
+        return static_cast<const float*>(f)[e];
+    } else if constexpr (DT == SST_BF16) {
+        const unsigned bits = static_cast<const uint16_t*>(f)[e];
+        return sc * __uint_as_float(bits << 16);
+    } else {
+        return sc * (float)static_cast<const _Float16*>(f)[e];
+    }
+}
+
 // ------------------------------------------------------- frame statistics
 // One workgroup per (chunk of kStatChunk pixels, frame): the chunk's sum and
 // sum of squared deviations from the chunk mean, both float64.
-__global__ __launch_bounds__(kAux) void k_stats_partial(const float* __restrict__ frames, long long npx,
+template <int DT>
+__global__ __launch_bounds__(kAux) void k_stats_partial(const void* __restrict__ frames,
+                                                           const float* __restrict__ scale, long long npx,
                                                            int nchunk, double* __restrict__ part) {
     const int i = blockIdx.y, c = blockIdx.x;
-    const float* f = frames + (long long)i * npx;
+    const long long f0 = (long long)i * npx;
+    const float sc = DT == SST_F32 ? 1.f : scale[i];
     const long long base = (long long)c * kStatChunk;
     const int cnt = (int)min((long long)kStatChunk, npx - base);
     constexpr int PER = kStatChunk / kAux;
@@ -116,7 +136,7 @@ __global__ __launch_bounds__(kAux) void k_stats_partial(const float* __restrict_
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int e = j * kAux + threadIdx.x;
-        v[j] = e < cnt ? f[base + e] : 0.f;
+        v[j] = e < cnt ? frame_value<DT>(frames, f0 + base + e, sc) : 0.f;
         s += (double)v[j];
     }
     const double sum = block_sum_f64(s, sh);
@@ -181,6 +201,7 @@ __global__ __launch_bounds__(kAux) void k_stats_final(const double* __restrict__
 // pad[i][yp][xp] = F_i(xp - padL, yp - padT) - b32[i] inside the frame, 0
 // outside: out-of-frame samples then add nothing, and every staging read of
 // the stack kernel is an unconditional aligned 16-byte load.
+template <int DT>
 __global__ __launch_bounds__(kAux) void k_prep(const PrepArgs a) {
     const int i = blockIdx.z, yp = blockIdx.y;
     const int xp = (blockIdx.x * kAux + threadIdx.x) * 4;
@@ -189,16 +210,74 @@ __global__ __launch_bounds__(kAux) void k_prep(const PrepArgs a) {
     float o[4] = {0.f, 0.f, 0.f, 0.f};
     if (y >= 0 && y < a.h) {
         const float bb = a.b32 ? a.b32[i] : 0.f;
-        const float* row = a.frames + ((long long)i * a.h + y) * a.w;
+        const float sc = DT == SST_F32 ? 1.f : a.scale[i];
+        const long long row = ((long long)i * a.h + y) * a.w;
         const int x0 = xp - a.padL;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int x = x0 + k;
-            o[k] = (x >= 0 && x < a.w) ? row[x] - bb : 0.f;
+            o[k] = (x >= 0 && x < a.w) ? frame_value<DT>(a.frames, row + x, sc) - bb : 0.f;
         }
     }
     f4* dst = reinterpret_cast<f4*>(a.pad + (long long)i * a.Hp * a.Wp + (long long)yp * a.Wp + xp);
     *dst = f4{o[0], o[1], o[2], o[3]};
+}
+
+// -------------------------------------------------------------- quantiser
+// 16-bit storage with a per-frame offset o_i (0, or float32 of the frame
+// mean) and scale s_i = max|F_i - o_i| * 2^-14 (1 for a constant frame):
+// stored q = round-to-nearest-even of the float32 quotient (F - o_i) / s_i
+// (the difference rounded to float32 first) in bfloat16 or IEEE half.
+// |q| <= 2^14, so neither format overflows.
+__global__ __launch_bounds__(kAux) void k_absmax_partial(const float* __restrict__ frames, long long npx,
+                                                            const float* __restrict__ offset, int nchunk,
+                                                            float* __restrict__ part) {
+    const int i = blockIdx.y, c = blockIdx.x;
+    const float* f = frames + (long long)i * npx;
+    const float off = offset ? offset[i] : 0.f;
+    const long long base = (long long)c * kStatChunk;
+    const int cnt = (int)min((long long)kStatChunk, npx - base);
+    float m = 0.f;
+    for (int e = threadIdx.x; e < cnt; e += kAux) m = fmaxf(m, fabsf(f[base + e] - off));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    __shared__ float sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(long long)i * nchunk + c] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+}
+
+__global__ __launch_bounds__(kAux) void k_absmax_final(const float* __restrict__ part, int nchunk, int n,
+                                                          float* __restrict__ scale) {
+    for (int i = threadIdx.x; i < n; i += kAux) {
+        float m = 0.f;
+        for (int c = 0; c < nchunk; ++c) m = fmaxf(m, part[(long long)i * nchunk + c]);
+        scale[i] = m > 0.f ? ldexpf(m, -14) : 1.f;
+    }
+}
+
+// float32 -> bfloat16 bits, round to nearest even (finite input)
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <int DT>
+__global__ __launch_bounds__(kAux) void k_quantize(const float* __restrict__ frames, long long npx,
+                                                      const float* __restrict__ offset,
+                                                      const float* __restrict__ scale, uint16_t* __restrict__ q) {
+    const int i = blockIdx.y;
+    const long long e = (long long)blockIdx.x * kAux + threadIdx.x;
+    if (e >= npx) return;
+    const float off = offset ? offset[i] : 0.f;
+    const float v = (frames[(long long)i * npx + e] - off) / scale[i];
+    uint16_t bits;
+    if constexpr (DT == SST_BF16) {
+        bits = bf16_rne(v);
+    } else {
+        bits = __builtin_bit_cast(uint16_t, (_Float16)v);
+    }
+    q[(long long)i * npx + e] = bits;
 }
 
 // ------------------------------------------------------ coverage intervals
@@ -887,10 +966,16 @@ __global__ __launch_bounds__(kAux) void k_merge(const int32_t* __restrict__ tcou
 }
 
 // ------------------------------------------------------------- launchers
-hipError_t launch_stats(const float* frames, int n, int h, int w, double* part, int nchunk, double* b, double* s2,
-                        float* b32, double* P, double* stats_dev, hipStream_t s) {
+hipError_t launch_stats(const void* frames, int dtype, const float* scale, int n, int h, int w, double* part,
+                        int nchunk, double* b, double* s2, float* b32, double* P, double* stats_dev, hipStream_t s) {
     const long long npx = (long long)h * w;
-    hipLaunchKernelGGL(k_stats_partial, dim3(nchunk, n), dim3(kAux), 0, s, frames, npx, nchunk, part);
+    const dim3 grid(nchunk, n);
+    if (dtype == SST_BF16)
+        hipLaunchKernelGGL(k_stats_partial<SST_BF16>, grid, dim3(kAux), 0, s, frames, scale, npx, nchunk, part);
+    else if (dtype == SST_F16)
+        hipLaunchKernelGGL(k_stats_partial<SST_F16>, grid, dim3(kAux), 0, s, frames, scale, npx, nchunk, part);
+    else
+        hipLaunchKernelGGL(k_stats_partial<SST_F32>, grid, dim3(kAux), 0, s, frames, scale, npx, nchunk, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kAux), 0, s, part, nchunk, n, npx, b, s2, b32, P,
@@ -898,9 +983,32 @@ hipError_t launch_stats(const float* frames, int n, int h, int w, double* part, 
     return hipGetLastError();
 }
 
+hipError_t launch_quantize(const float* frames, int n, int h, int w, int dtype, const float* offset, float* part,
+                           int nchunk, float* scale, void* q, hipStream_t s) {
+    const long long npx = (long long)h * w;
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nchunk, n), dim3(kAux), 0, s, frames, npx, offset, nchunk, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(kAux), 0, s, part, nchunk, n, scale);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const dim3 grid((unsigned)((npx + kAux - 1) / kAux), n);
+    uint16_t* qb = static_cast<uint16_t*>(q);
+    if (dtype == SST_BF16)
+        hipLaunchKernelGGL(k_quantize<SST_BF16>, grid, dim3(kAux), 0, s, frames, npx, offset, scale, qb);
+    else
+        hipLaunchKernelGGL(k_quantize<SST_F16>, grid, dim3(kAux), 0, s, frames, npx, offset, scale, qb);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
     const int c4 = a.Wp / 4;
-    hipLaunchKernelGGL(k_prep, dim3((c4 + kAux - 1) / kAux, a.Hp, a.n), dim3(kAux), 0, s, a);
+    const dim3 grid((c4 + kAux - 1) / kAux, a.Hp, a.n);
+    if (a.dtype == SST_BF16)
+        hipLaunchKernelGGL(k_prep<SST_BF16>, grid, dim3(kAux), 0, s, a);
+    else if (a.dtype == SST_F16)
+        hipLaunchKernelGGL(k_prep<SST_F16>, grid, dim3(kAux), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_prep<SST_F32>, grid, dim3(kAux), 0, s, a);
     return hipGetLastError();
 }
 

@@ -33,7 +33,7 @@ def lib():
 def header_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(sst_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(sst_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():
@@ -199,3 +199,41 @@ def test_binding_fails_loudly_without_library(tmp_path):
     finally:
         B._lib = saved
     importlib.reload  # keep linters quiet
+
+
+def test_quantize_argument_errors(lib):
+    f = FAKE
+
+    def call(frames=f, n=2, dtype=B.SST_BF16, center=0, q=f, scale=f, offset=f, wsb=1 << 30):
+        return lib.sst_quantize(frames, n, 4, 4, dtype, center, q, scale, offset, f, wsb, None)
+    assert call(frames=None) == B.SST_E_ARG
+    assert call(dtype=B.SST_F32) == B.SST_E_ARG
+    assert call(q=None) == B.SST_E_ARG
+    assert call(scale=None) == B.SST_E_ARG
+    assert call(center=1, offset=None) == B.SST_E_ARG
+    assert call(n=0) == B.SST_E_ARG
+    assert call(wsb=2) == B.SST_E_WORKSPACE
+    assert sst.sst_workspace_bytes(B.SST_OP_QUANT, 2, 4, 4) > 0
+
+
+def test_16bit_frames_need_scale_array(lib):
+    assert _detect(lib, dtype=B.SST_BF16) == B.SST_E_ARG
+    assert "scale" in sst.sst_last_error()
+    assert lib.sst_frame_stats(FAKE, B.SST_F16, None, 2, 4, 4, FAKE, FAKE, 1 << 30, None) == B.SST_E_ARG
+
+
+def test_preprocessing_argument_errors(lib):
+    f = FAKE
+    assert lib.sst_median_subtract(None, 3, 4, 4, f, None, None) == B.SST_E_ARG
+    assert lib.sst_median_subtract(f, 3, 4, 4, None, None, None) == B.SST_E_ARG
+    assert lib.sst_median_subtract(f, 257, 4, 4, f, None, None) == B.SST_E_UNSUPPORTED
+    assert lib.sst_median_subtract(f, 0, 4, 4, f, None, None) == B.SST_E_ARG
+    t = np.arange(6, dtype=np.float64)
+    tout = np.zeros(6)
+    assert lib.sst_coadd(f, 6, 4, 4, 0, f, None, None, None) == B.SST_E_ARG
+    assert lib.sst_coadd(f, 6, 4, 4, 7, f, None, None, None) == B.SST_E_ARG
+    assert lib.sst_coadd(f, 6, 4, 4, 2, f, None, _p(tout), None) == B.SST_E_ARG
+    t[3] = np.nan
+    assert lib.sst_coadd(f, 6, 4, 4, 2, f, _p(t), _p(tout), None) == B.SST_E_ARG
+    assert lib.sst_bin2x2(f, 2, 1, 4, f, None) == B.SST_E_ARG
+    assert lib.sst_bin2x2(None, 2, 4, 4, f, None) == B.SST_E_ARG

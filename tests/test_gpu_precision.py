@@ -1,0 +1,223 @@
+"""16-bit frame storage on the GPU (through the C ABI).
+
+* the quantiser (scales and 16-bit words) is bit-exact against the oracle's;
+* statistics, stacks and candidate lists computed from 16-bit frames obey the
+  same parity rules as float32 frames, against the float64 oracle run on the
+  oracle's own dequantised frames F' = scale_i * q;
+* on the full field, the error of 16-bit storage against the float64 oracle
+  on the original float32 frames is measured and bounded by the format's
+  unit roundoff, and detections are compared with the float32 GPU path.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sst_oracle as so
+import synth
+from parity import compare_velocity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+KINDS = {"bf16": ("bfloat16", 2.0 ** -8), "f16": ("float16", 2.0 ** -11)}
+
+
+@pytest.fixture(scope="module")
+def sst():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_07293_amd as m
+    m.load()
+    return m
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _tdtype(kind):
+    return getattr(torch, KINDS[kind][0])
+
+
+def _upload_q(q, kind):
+    return torch.from_numpy(np.ascontiguousarray(q).view(np.int16)).to("cuda:0").view(_tdtype(kind))
+
+
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+@pytest.mark.parametrize("center", [False, True])
+def test_quantize_bit_exact(sst, kind, center):
+    rng = np.random.default_rng(5)
+    f = rng.normal(100, 10, size=(5, 37, 203)).astype(np.float32)
+    f[1] = rng.normal(0, 1e-3, size=f[1].shape)
+    f[2] = 0.0
+    # frame 3: max 2^14 gives scale 1, so these values are exact rounding ties
+    f[3] = 1.0
+    f[3, 0, 0] = 2.0 ** 14
+    f[3, 1, :4] = [1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -11, -(1 + 3 * 2 ** -11)]
+    f[4] = rng.uniform(-5, 5, size=f[4].shape)
+    _say(f"case quantize {kind} center={center}")
+    q, s, o = sst.sst_quantize(torch.from_numpy(f).to("cuda:0"), _tdtype(kind), center=center)
+    torch.cuda.synchronize()
+    qw, sw, ow = oracle.quantize_frames(f, kind, center=center)
+    assert np.array_equal(o.cpu().numpy(), ow)
+    assert np.array_equal(s.cpu().numpy(), sw)
+    got = q.cpu().view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(got, qw), int((got != qw).sum())
+
+
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_stats_and_stack_16bit(sst, kind):
+    f = synth.small_case(41, 7, 70, 130, 7, 5, vmax=3.0, sky=100.0, sigma=10.0)
+    _say(f"case {f.name} {kind}")
+    q, s, _ = oracle.quantize_frames(f.frames, kind)
+    fd = oracle.dequantize_frames(q, s, kind)
+    qt = _upload_q(q, kind)
+    st = torch.from_numpy(s).to("cuda:0")
+    stats = sst.sst_frame_stats(qt, scale=st).cpu().numpy()
+    b, s2 = oracle.frame_stats(fd)
+    assert np.allclose(stats[:, 0], b, rtol=1e-13) and np.allclose(stats[:, 1], s2, rtol=1e-11)
+    out, cov = sst.sst_stack(qt, f.t, f.t_ref, f.vx, f.vy, with_coverage=True, scale=st)
+    torch.cuda.synchronize()
+    dx = oracle.shift_table(f.t, f.t_ref, f.vx)
+    dy = oracle.shift_table(f.t, f.t_ref, f.vy)
+    for k in range(len(f.vx) * len(f.vy)):
+        a, bb = k % len(f.vx), k // len(f.vx)
+        S, c, _, A = so.stack_velocity(fd, dx[:, a], dy[:, bb], absolute=True)
+        assert np.array_equal(cov[bb, a].cpu().numpy(), c)
+        err = np.abs(out[bb, a].cpu().numpy().astype(np.float64) - S)
+        assert np.all(err <= 1e-5 * A + 1e-30), k
+
+
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+@pytest.mark.parametrize("center", [False, True])
+def test_detect_16bit(sst, kind, center):
+    f = synth.small_case(42, 12, 97, 61, 6, 4, vmax=4.0, sky=100.0, sigma=2.0)
+    _say(f"case {f.name} {kind} center={center}")
+    q, s, _ = oracle.quantize_frames(f.frames, kind, center=center)
+    fd = oracle.dequantize_frames(q, s, kind)
+    cand, count = sst.sst_detect(_upload_q(q, kind), f.t, f.t_ref, f.vx, f.vy, 2.5, 0, 6,
+                                 scale=torch.from_numpy(s).to("cuda:0"))
+    torch.cuda.synchronize()
+    got = sst.candidates_to_numpy(cand)
+    cnt = count.cpu().numpy()
+    nvx = len(f.vx)
+    ks = list(range(nvx * len(f.vy)))
+    ref = oracle.detect(fd, f.t, f.t_ref, f.vx, f.vy, 2.5, 0, 6, velocities=ks, keep_maps=True)
+    b, _ = oracle.frame_stats(fd)
+    marg = sum(compare_velocity(got[k], int(cnt[k]), ref[k], f.n, float(np.abs(b).max()), 2.5, ref["c_min"], 6, f.w)
+               for k in ks)
+    _say(f"  {int(cnt.sum())} candidates, {marg} marginal decisions")
+    assert marg <= 4
+
+
+def test_16bit_frames_need_scale(sst):
+    x = torch.zeros((2, 8, 8), dtype=torch.bfloat16, device="cuda:0")
+    with pytest.raises(ValueError):
+        sst.sst_frame_stats(x)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+@pytest.mark.parametrize("center", [False, True])
+def test_precision_full_field(sst, kind, center):
+    """Full field stored in 16 bits.  Error of the background-subtracted
+    stack S' (the quantity the S/N is made of) against the float64 oracle on
+    the original float32 frames, its S/N error, and agreement of the
+    candidate lists with the float32 path.  Bounds: every stored sample of
+    F - o carries one rounding of relative size <= u (the format's unit
+    roundoff) and each frame's mean moves by at most u max|F - o|, so
+    |dS'| <= 2 u sum_i max|F_i - o_i| plus float32 summation terms."""
+    f = synth.config2()
+    _say(f"case {f.name} {kind} center={center}")
+    fr = torch.from_numpy(f.frames).to("cuda:0")
+    q, s, o = sst.sst_quantize(fr, _tdtype(kind), center=center)
+    u = KINDS[kind][1]
+    st16 = sst.sst_frame_stats(q, scale=s).cpu().numpy()
+    b64, s2_64 = oracle.frame_stats(f.frames)
+    ov = o.cpu().numpy().astype(np.float64)
+    M = np.abs(f.frames.reshape(f.n, -1).astype(np.float64) - ov[:, None]).max(axis=1)
+    ks = [0, 80, 3280, 6480, 6560, 41 * 81 + 7, 1234, 4321]
+    dx = oracle.shift_table(f.t, f.t_ref, f.vx)
+    dy = oracle.shift_table(f.t, f.t_ref, f.vy)
+    worst_b, worst_rel, sq, npx, worst_sn = 0.0, 0.0, 0.0, 0, 0.0
+    for k in ks:
+        a, b = k % 81, k // 81
+        out = sst.sst_stack(q, f.t, f.t_ref, f.vx[a:a + 1], f.vy[b:b + 1], bg=st16[:, 0], scale=s)
+        torch.cuda.synchronize()
+        S, c, V, A = so.stack_velocity(f.frames, dx[:, a], dy[:, b], offsets=b64, weights=s2_64, absolute=True)
+        g = out[0, 0].cpu().numpy().astype(np.float64)
+        err = np.abs(g - S)
+        # in-frame samples of each pixel: the bound sums M over at most c frames
+        bound = 2 * u * c * M.max() + 4 * f.n * 2.0 ** -24 * c * (np.abs(f.frames).max() + M.max()) + 1e-30
+        worst_b = max(worst_b, float((err / bound).max()))
+        m = c >= f.min_coverage
+        rel = err[m] / A[m]
+        worst_rel = max(worst_rel, float(rel.max()))
+        sq += float((rel ** 2).sum())
+        npx += int(m.sum())
+        # the flux part of the S/N error (the variances move by O(u) relative)
+        worst_sn = max(worst_sn, float((err[m] / np.sqrt(V[m])).max()))
+    rms = (sq / max(npx, 1)) ** 0.5
+    _say(f"  S' error: max/bound {worst_b:.3g}; |dS'|/A' over c >= c_min: max {worst_rel:.3g} rms {rms:.3g}; "
+         f"flux part of |dSN| max {worst_sn:.3g} (u = {u:.3g})")
+    assert worst_b <= 1.0
+    # detections: 16-bit against float32 storage, whole grid
+    c16, n16 = sst.sst_detect(q, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, scale=s)
+    c32, n32 = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max)
+    g16, g32 = sst.candidates_to_numpy(c16), sst.candidates_to_numpy(c32)
+    n16, n32 = n16.cpu().numpy(), n32.cpu().numpy()
+
+    def snmap(g, n):
+        out = {}
+        for k in range(len(n)):
+            m = min(int(n[k]), f.k_max)
+            for x, y, sn in zip(g[k]["x"][:m], g[k]["y"][:m], g[k]["snr"][:m]):
+                out[(k, int(y), int(x))] = float(sn)
+        return out
+
+    m16, m32 = snmap(g16, n16), snmap(g32, n32)
+    common = m16.keys() & m32.keys()
+    dsn = max((abs(m16[key] - m32[key]) for key in common), default=0.0)
+    diff = sorted(m16.keys() ^ m32.keys())
+    only = sorted(m16.get(key, m32.get(key)) for key in diff)
+    _say(f"  detections: float32 {len(m32)}, {kind} {len(m16)}, common {len(common)}, max |dSN| on common "
+         f"{dsn:.3g}; S/N of the differing ones: {[round(v, 3) for v in only[:12]]}")
+    # A detection can only flip where its S/N or a neighbour's moves across the
+    # threshold or a tie.  S/N error bound: the S' bound over the smallest V a
+    # candidate can have (c_min frames of the smallest variance), plus the
+    # O(u) relative change of the variances.
+    v_min = f.min_coverage * float(s2_64.min())
+    sn_bound = (2 * u * f.n * M.max() + 4 * f.n * 2.0 ** -24 * f.n * np.abs(f.frames).max()) / np.sqrt(v_min)
+    sn_bound += 2 * u * max(max(m32.values()), max(m16.values()))
+    _say(f"  S/N error bound {sn_bound:.3g}; differing detections {len(only)}")
+    assert dsn <= sn_bound
+    # each differing detection sits within the bound of the threshold or of
+    # one of its neighbours (float64 S/N of the original frames at 3x3 pixels)
+    fr64 = f.frames.astype(np.float64)
+
+    def sn_at(k, y, x):
+        a, b = k % 81, k // 81
+        if not (0 <= x < f.w and 0 <= y < f.h):
+            return -np.inf
+        xs, ys = x + dx[:, a], y + dy[:, b]
+        ok = (xs >= 0) & (xs < f.w) & (ys >= 0) & (ys < f.h)
+        if ok.sum() < f.min_coverage:
+            return -np.inf
+        idx = np.nonzero(ok)[0]
+        sp = float(np.sum(fr64[idx, ys[idx], xs[idx]] - b64[idx]))
+        return sp / float(np.sqrt(np.sum(s2_64[idx])))
+
+    near = 0
+    for k, y, x in diff:
+        c0 = sn_at(k, y, x)
+        nb = [sn_at(k, y + j, x + i) for j in (-1, 0, 1) for i in (-1, 0, 1) if i or j]
+        gap = min([abs(c0 - f.threshold)] + [abs(c0 - v) for v in nb])
+        assert gap <= 2 * sn_bound, ((k, y, x), c0, gap)
+        near += gap <= 2 * dsn
+    _say(f"  every differing detection is within the bound of the threshold or a neighbour "
+         f"({near} of {len(diff)} within twice the largest S/N change seen)")
