@@ -69,6 +69,7 @@ extern "C" {
 #define SST_OP_DETECT 1
 #define SST_OP_STATS 2
 #define SST_OP_QUANT 3
+#define SST_OP_REFINE 4
 
 /* plain-stack modes */
 #define SST_SUM 0
@@ -92,8 +93,8 @@ typedef struct sst_candidate {
 int sst_shift_table(const double* t, int n, double t_ref, const double* v, int nv, int32_t* out);
 
 /* Bytes of device workspace an operation needs for this problem (0 on error,
- * with sst_last_error set).  op = SST_OP_STACK, SST_OP_DETECT, SST_OP_STATS or
- * SST_OP_QUANT (the last two need only n, h, w);
+ * with sst_last_error set).  op = SST_OP_STACK, SST_OP_DETECT, SST_OP_STATS,
+ * SST_OP_QUANT or SST_OP_REFINE (the last three need only n, h, w);
  * the shift tables enter because the zero-padded frame copy is sized by the
  * largest shift.  k_max is used by SST_OP_DETECT only. */
 size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double t_ref,
@@ -157,6 +158,33 @@ int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, 
                float threshold, int min_coverage, int k_max,
                sst_candidate* cand, int32_t* count, double* frame_stats,
                void* ws, size_t ws_bytes, void* stream);
+
+/* Sub-pixel refinement of detections by gradient ascent on a differentiable
+ * stacked S/N.  The search returns tracks on its integer grid (paper Sec.
+ * 2.1); here theta = (x0, y0, vx, vy) is continuous.  For each candidate a
+ * cutout x cutout stack is sampled bilinearly along the track,
+ *   Cut(u,v) = sum_i bilin(F_i - b_i; x0 + u + vx dt_i, y0 + v + vy dt_i),
+ *   dt_i = t[i] - t_ref, u, v in [-R, R], R = cutout / 2,
+ * frame values outside the frame count as 0 (as in the search), b_i the
+ * frame means; the objective is the PSF-weighted S/N
+ *   SN = sum w(u,v) Cut(u,v) / sqrt(sum w(u,v)^2 * sum_i s2_i),
+ *   w = Gaussian of the given FWHM centred on the track,
+ * whose normaliser does not depend on theta (0 if every frame is constant).
+ * Its gradient is exact almost everywhere (bilinear sampling is piecewise
+ * linear; at an integer sample position the right derivative is taken).
+ * `steps` ascent steps theta <- theta + lr * grad SN are taken inside the
+ * call; steps = 0 only evaluates.  On return params holds the final theta,
+ * snr[c] = SN(theta) and grad[c] = dSN/dtheta at that theta.
+ * Arithmetic: float32 sums; float64 only in the frame statistics.
+ * frames: dev [n][h][w] of dtype (scale as for sst_detect); t: host [n];
+ * params: dev float32 [n_cand][4] (in/out); snr: dev float32 [n_cand];
+ * grad: dev float32 [n_cand][4] or NULL.  cutout odd in 1..63; fwhm > 0.
+ * ws: dev, >= sst_workspace_bytes(SST_OP_REFINE, ...).  The call waits for
+ * the stream once (upload of the time offsets).
+ * Errors: SST_E_ARG, SST_E_UNSORTED, SST_E_WORKSPACE, SST_E_DEVICE. */
+int sst_refine(const void* frames, int dtype, const float* scale, int n, int h, int w,
+               const double* t, double t_ref, int n_cand, float* params, int cutout, float fwhm,
+               int steps, float lr, float* snr, float* grad, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- steps the paper runs before the search (float32 frames) ----
  * out must not overlap frames in any of the three. */

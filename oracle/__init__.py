@@ -17,7 +17,8 @@ values), written from the paper's statement of the method:
 The readings taken where the paper is silent are listed in `sst_oracle.py`.
 `quant.py` holds the 16-bit storage format (a data-layout step, not part of
 the paper's method); `prep.py` the steps the paper runs before the search
-(static-source removal by the median, co-adding, 2x2 binning).
+(static-source removal by the median, co-adding, 2x2 binning); `refine.py`
+the differentiable sub-pixel refinement of a detection.
 """
 
 from .sst_oracle import (  # noqa: F401
@@ -35,3 +36,4 @@ from .sst_oracle import (  # noqa: F401
 )
 from .quant import dequantize_frames, frame_offsets, frame_scales, quantize_frames  # noqa: F401,E402
 from .prep import bin2x2, coadd, median_subtract  # noqa: F401,E402
+from . import refine  # noqa: F401,E402

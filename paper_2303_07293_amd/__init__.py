@@ -14,6 +14,7 @@ from .binding import (  # noqa: F401
     SST_MEAN,
     SST_OP_DETECT,
     SST_OP_QUANT,
+    SST_OP_REFINE,
     SST_OP_STACK,
     SST_OP_STATS,
     SST_SUM,
@@ -29,7 +30,9 @@ from .binding import (  # noqa: F401
     sst_profile_begin,
     sst_profile_end,
     sst_quantize,
+    sst_refine,
     sst_shift_table,
     sst_stack,
     sst_workspace_bytes,
 )
+from .autograd import StackedSNR, stacked_snr  # noqa: F401,E402

@@ -26,7 +26,7 @@ SST_E_DEVICE = -5
 SST_E_UNSUPPORTED = -6
 
 SST_F32, SST_BF16, SST_F16 = 0, 1, 2
-SST_OP_STACK, SST_OP_DETECT, SST_OP_STATS, SST_OP_QUANT = 0, 1, 2, 3
+SST_OP_STACK, SST_OP_DETECT, SST_OP_STATS, SST_OP_QUANT, SST_OP_REFINE = 0, 1, 2, 3, 4
 SST_SUM, SST_MEAN = 0, 1
 
 # the 32-byte sst_candidate record
@@ -36,7 +36,7 @@ CANDIDATE_DTYPE = np.dtype([
 ])
 
 EXPORTS = ("sst_shift_table", "sst_workspace_bytes", "sst_quantize", "sst_median_subtract", "sst_coadd", "sst_bin2x2",
-           "sst_frame_stats", "sst_stack", "sst_detect",
+           "sst_frame_stats", "sst_stack", "sst_detect", "sst_refine",
            "sst_profile_begin", "sst_profile_end", "sst_last_error", "sst_version")
 
 
@@ -83,6 +83,8 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.sst_detect.argtypes = [_p, _i, _p, _i, _i, _i, _p, _d, _p, _i, _p, _i, _f, _i, _i, _p, _p, _p, _p, _sz,
                                _p]
     lib.sst_detect.restype = _i
+    lib.sst_refine.argtypes = [_p, _i, _p, _i, _i, _i, _p, _d, _i, _p, _i, _f, _i, _f, _p, _p, _p, _sz, _p]
+    lib.sst_refine.restype = _i
     lib.sst_profile_begin.argtypes = []
     lib.sst_profile_begin.restype = _i
     lib.sst_profile_end.argtypes = [_p, _p]
@@ -310,6 +312,33 @@ def sst_detect(frames, t, t_ref: float, vx, vy, threshold: float, min_coverage: 
                              _ptr(vx), len(vx), _ptr(vy), len(vy), float(threshold), int(min_coverage), int(k_max),
                              _dev(cand), _dev(count), _ptr(stats), _dev(ws), ws.numel(), _stream(frames.device)))
     return (cand, count, stats) if want_stats else (cand, count)
+
+
+def sst_refine(frames, t, t_ref: float, params, cutout: int = 33, fwhm: float = 2.5, steps: int = 20,
+               lr: float = 0.05, scale=None, ws=None):
+    """Gradient ascent of the bilinear PSF-weighted stacked S/N (see sst.h).
+
+    params: float32 device tensor [n_cand][4] of (x0, y0, vx, vy); it is not
+    modified.  Returns (theta, snr, grad): the final parameters, SN and
+    dSN/dtheta there (steps = 0 evaluates at params)."""
+    import torch
+    _check_frames(frames)
+    n, h, w = frames.shape
+    t = _f64(t)
+    if len(t) != n:
+        raise ValueError("t must have one value per frame")
+    if params.dim() != 2 or params.shape[1] != 4 or params.dtype != torch.float32 or not params.is_cuda:
+        raise ValueError("params must be a float32 device tensor [n_cand][4]")
+    nc = params.shape[0]
+    theta = params.detach().clone().contiguous()
+    snr = torch.empty((nc,), dtype=torch.float32, device=frames.device)
+    grad = torch.empty((nc, 4), dtype=torch.float32, device=frames.device)
+    nb = sst_workspace_bytes(SST_OP_REFINE, n, h, w)
+    ws = _workspace(nb, frames.device, ws)
+    _check(load().sst_refine(_dev(frames), _frames_dtype(frames), _check_scale(frames, scale), n, h, w, _ptr(t),
+                             float(t_ref), nc, _dev(theta), int(cutout), float(fwhm), int(steps), float(lr),
+                             _dev(snr), _dev(grad), _dev(ws), ws.numel(), _stream(frames.device)))
+    return theta, snr, grad
 
 
 def sst_profile_begin() -> None:

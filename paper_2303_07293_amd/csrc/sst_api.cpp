@@ -109,7 +109,7 @@ struct Plan {
     std::vector<int32_t> DX, DY;
     // workspace offsets (bytes)
     size_t o_tab = 0, o_part = 0, o_b = 0, o_s2 = 0, o_P = 0, o_b32 = 0, o_sdev = 0;
-    size_t o_ix = 0, o_iy = 0, o_pad = 0, o_tcount = 0, o_ent = 0, o_qpart = 0, total = 0;
+    size_t o_ix = 0, o_iy = 0, o_pad = 0, o_tcount = 0, o_ent = 0, o_qpart = 0, o_dt = 0, total = 0;
 };
 
 size_t take(size_t& cur, size_t bytes) {
@@ -128,8 +128,9 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
     p.w = w;
     p.nchunk = (int)(((long long)h * w + kStatChunk - 1) / kStatChunk);
     size_t cur = 0;
-    if (op == SST_OP_STATS || op == SST_OP_QUANT) {
+    if (op == SST_OP_STATS || op == SST_OP_QUANT || op == SST_OP_REFINE) {
         if (op == SST_OP_QUANT) p.o_qpart = take(cur, (size_t)n * p.nchunk * sizeof(float));
+        if (op == SST_OP_REFINE) p.o_dt = take(cur, (size_t)n * sizeof(float));
         p.o_part = take(cur, (size_t)n * p.nchunk * 3 * sizeof(double));
         p.o_b = take(cur, (size_t)n * sizeof(double));
         p.o_s2 = take(cur, (size_t)n * sizeof(double));
@@ -431,6 +432,67 @@ int sst_quantize(const float* frames, int n, int h, int w, int dtype, int center
     e = launch_quantize(frames, n, h, w, dtype, center ? offset : nullptr, at<float>(ws, p.o_qpart), p.nchunk, scale,
                         q, s);
     if (e != hipSuccess) return hip_fail(e, "quantize kernels");
+    return SST_OK;
+}
+
+int sst_refine(const void* frames, int dtype, const float* scale, int n, int h, int w, const double* t, double t_ref,
+               int n_cand, float* params, int cutout, float fwhm, int steps, float lr, float* snr, float* grad,
+               void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_frames(frames, dtype, scale);
+    if (rc) return rc;
+    if ((rc = check_dims(n, h, w))) return rc;
+    if ((rc = check_times(t, n, t_ref))) return rc;
+    if (n_cand < 0 || n_cand > (1 << 24)) return fail(SST_E_ARG, "n_cand = %d: need 0..2^24", n_cand);
+    if (n_cand > 0 && (!params || !snr)) return fail(SST_E_ARG, "params and snr must not be NULL");
+    if (cutout < 1 || cutout > 63 || cutout % 2 == 0) return fail(SST_E_ARG, "cutout = %d: need odd 1..63", cutout);
+    if (!(fwhm > 0.f) || !std::isfinite(fwhm)) return fail(SST_E_ARG, "fwhm must be positive and finite");
+    if (steps < 0 || steps > 100000) return fail(SST_E_ARG, "steps = %d: need 0..100000", steps);
+    if (!std::isfinite(lr)) return fail(SST_E_ARG, "lr is not finite");
+    Plan p;
+    if ((rc = make_plan(SST_OP_REFINE, n, h, w, nullptr, 0, nullptr, 0, nullptr, 0, 0, p))) return rc;
+    if ((rc = check_ws(p, ws, ws_bytes))) return rc;
+    if (n_cand == 0) return SST_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_stats(frames, dtype, scale, n, h, w, at<double>(ws, p.o_part), p.nchunk,
+                                at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
+                                at<double>(ws, p.o_P), nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
+    std::vector<float> dt(n);
+    for (int i = 0; i < n; ++i) dt[i] = (float)(t[i] - t_ref);
+    if ((e = hipMemcpyAsync(at<float>(ws, p.o_dt), dt.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(dt)");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    // PSF: Gaussian of the given FWHM; the sum of its squared weights in float64
+    const double sig = (double)fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    const int R = cutout / 2;
+    double sw2 = 0.0;
+    for (int v = -R; v <= R; ++v)
+        for (int u = -R; u <= R; ++u) {
+            const double wv = std::exp(-(double)(u * u + v * v) / (2.0 * sig * sig));
+            sw2 += wv * wv;
+        }
+    RefineArgs a{};
+    a.frames = frames;
+    a.dtype = dtype;
+    a.scale = scale;
+    a.b32 = at<float>(ws, p.o_b32);
+    a.P = at<double>(ws, p.o_P);
+    a.dt = at<float>(ws, p.o_dt);
+    a.n = n;
+    a.h = h;
+    a.w = w;
+    a.params = params;
+    a.snr = snr;
+    a.grad = grad;
+    a.nc = n_cand;
+    a.cutout = cutout;
+    a.steps = steps;
+    a.lr = lr;
+    a.inv2s2 = (float)(1.0 / (2.0 * sig * sig));
+    a.sw2 = sw2;
+    if ((e = launch_refine(a, s)) != hipSuccess) return hip_fail(e, "refine kernel");
     return SST_OK;
 }
 

@@ -7,6 +7,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "../../include/sst.h"
+
 namespace sst {
 
 // clang vector types (HIP's int4/float4 wrappers are structs that keep
@@ -63,6 +65,22 @@ struct Entry {
     int32_t cov;
 };
 
+// ------------------------------------------------------------ frame values
+// Frame value of a stored sample: float32 as is, or a 16-bit sample times
+// its frame's scale (one float32 product; the 16-bit to float32 conversion
+// is exact).
+template <int DT>
+__device__ __forceinline__ float frame_value(const void* f, long long e, float sc) {
+    if constexpr (DT == SST_F32) {
+        return static_cast<const float*>(f)[e];
+    } else if constexpr (DT == SST_BF16) {
+        const unsigned bits = static_cast<const uint16_t*>(f)[e];
+        return sc * __uint_as_float(bits << 16);
+    } else {
+        return sc * (float)static_cast<const _Float16*>(f)[e];
+    }
+}
+
 struct StackArgs {
     const float* pad;   // zero-padded, background-subtracted frames [n][Hp][Wp]
     long long fstride;  // Hp * Wp
@@ -112,6 +130,24 @@ hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, hipStream_
 hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int nslot, int kt, int k_max,
                         int nvx, int w, int k_first, int nk, void* cand, int32_t* count,
                         hipStream_t s);
+
+// sub-pixel refinement (sst_refine.hip)
+struct RefineArgs {
+    const void* frames;  // [n][h][w] of dtype
+    int dtype;
+    const float* scale;  // [n] for 16-bit frames
+    const float* b32;    // [n] frame means (float32)
+    const double* P;     // [n+1] variance prefix; P[n] = total variance
+    const float* dt;     // [n] t_i - t_ref
+    int n, h, w;
+    float* params;  // [nc][4] x0, y0, vx, vy (in/out)
+    float* snr;     // [nc]
+    float* grad;    // [nc][4] or nullptr
+    int nc, cutout, steps;
+    float lr, inv2s2;  // ascent step; 1 / (2 s^2) of the PSF
+    double sw2;        // sum of the squared PSF weights
+};
+hipError_t launch_refine(const RefineArgs& a, hipStream_t s);
 
 // preprocessing kernels (sst_prep.hip)
 constexpr int kMedianMaxFrames = 256;  // frames staged in LDS per pixel column

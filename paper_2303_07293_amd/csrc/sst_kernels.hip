@@ -101,22 +101,6 @@ __device__ __forceinline__ void load_iv(const int* I, long long e, int& lo, int&
     hi = (int)(v >> 32);
 }
 
-// ------------------------------------------------------------ frame values
-// Frame value of a stored sample: float32 as is, or a 16-bit sample times
-// its frame's scale (one float32 product; the 16-bit to float32 conversion
-// is exact).
-template <int DT>
-__device__ __forceinline__ float frame_value(const void* f, long long e, float sc) {
-    if constexpr (DT == SST_F32) {
-        return static_cast<const float*>(f)[e];
-    } else if constexpr (DT == SST_BF16) {
-        const unsigned bits = static_cast<const uint16_t*>(f)[e];
-        return sc * __uint_as_float(bits << 16);
-    } else {
-        return sc * (float)static_cast<const _Float16*>(f)[e];
-    }
-}
-
 // ------------------------------------------------------- frame statistics
 // One workgroup per (chunk of kStatChunk pixels, frame): the chunk's sum and
 // sum of squared deviations from the chunk mean, both float64.

@@ -237,3 +237,25 @@ def test_preprocessing_argument_errors(lib):
     assert lib.sst_coadd(f, 6, 4, 4, 2, f, _p(t), _p(tout), None) == B.SST_E_ARG
     assert lib.sst_bin2x2(f, 2, 1, 4, f, None) == B.SST_E_ARG
     assert lib.sst_bin2x2(None, 2, 4, 4, f, None) == B.SST_E_ARG
+
+
+def test_refine_argument_errors(lib):
+    f = FAKE
+    t = np.arange(4, dtype=np.float64)
+
+    def call(frames=f, n=4, tt=t, nc=2, params=f, cutout=33, fwhm=2.5, steps=5, lr=0.01, snr=f, wsb=1 << 30):
+        return lib.sst_refine(frames, 0, None, n, 8, 8, _p(tt), 0.0, nc, params, cutout, fwhm, steps, lr, snr, None, f,
+                              wsb, None)
+    assert call(frames=None) == B.SST_E_ARG
+    assert call(params=None) == B.SST_E_ARG
+    assert call(snr=None) == B.SST_E_ARG
+    assert call(cutout=32) == B.SST_E_ARG
+    assert call(cutout=65) == B.SST_E_ARG
+    assert call(fwhm=0.0) == B.SST_E_ARG
+    assert call(fwhm=float("nan")) == B.SST_E_ARG
+    assert call(steps=-1) == B.SST_E_ARG
+    assert call(lr=float("inf")) == B.SST_E_ARG
+    assert call(nc=-1) == B.SST_E_ARG
+    assert call(tt=np.array([0.0, 2.0, 1.0, 3.0])) == B.SST_E_UNSORTED
+    assert call(wsb=4) == B.SST_E_WORKSPACE
+    assert sst.sst_workspace_bytes(B.SST_OP_REFINE, 4, 8, 8) > 0

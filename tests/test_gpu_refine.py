@@ -1,0 +1,217 @@
+"""GPU parity of the differentiable refinement (sst_refine and the autograd
+binding) against the float64 oracle (oracle/refine.py).
+
+Tolerances follow the kernel's float32 arithmetic, u = 2^-24: every term of
+a sum passes through at most K = n ceil((C+1)^2 / 256) sequential additions
+in a thread plus an 8-level workgroup reduction and ~10 roundings in its
+coefficient, so a sum errs by at most (K + 20) u times the sum of its
+|terms|; sample positions x0 + vx dt are formed in float32 (error
+<= 2u (|x0| + 2 |vx| |dt|)), which moves SN by at most L times that; the
+frame means are rounded to float32 once.  Gradients are compared only where
+no frame's sample lies within that position error of a pixel boundary
+(there bilinear sampling has a kink and either one-sided derivative is
+right).
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import refine
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+U = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def sst():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_07293_amd as m
+    m.load()
+    return m
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _field(seed=61, n=16, h=80, w=100):
+    f = synth.small_case(seed, n, h, w, 1, 1, vmax=6.0, sky=100.0, sigma=10.0, n_movers=3)
+    for m in f.movers:  # brighter movers so that the objective has structure
+        m.amp *= 3
+    return synth.Field(f.name, synth.fields._frames(np.random.default_rng(seed), f.t, f.t_ref, h, w, 100.0, 10.0,
+                                                    f.movers), f.t, f.t_ref, f.vx, f.vy, movers=f.movers)
+
+
+def _thetas(f, rng, k):
+    th = []
+    for m in f.movers:
+        th.append([m.x0 + rng.uniform(-0.7, 0.7), m.y0 + rng.uniform(-0.7, 0.7), m.vx + rng.uniform(-0.5, 0.5),
+                   m.vy + rng.uniform(-0.5, 0.5)])
+    while len(th) < k:
+        th.append([rng.uniform(-20, f.w + 20), rng.uniform(-20, f.h + 20), rng.uniform(-8, 8), rng.uniform(-8, 8)])
+    th.append([3.3, 2.6, 0.4, -0.2])          # cutout hanging over the corner
+    th.append([f.w + 60.0, f.h + 70.0, 0.0, 0.0])  # entirely outside: SN 0
+    return np.array(th, np.float32)
+
+
+def _tol(f, th, m, C, sn, b):
+    dtmax = float(np.max(np.abs(f.t - f.t_ref)))
+    K = f.n * math.ceil((C + 1) ** 2 / 256)
+    dpos = 2 * U * (max(abs(th[0]), abs(th[1])) + 2 * max(abs(th[2]), abs(th[3])) * dtmax + 1.0)
+    sum_w = float(refine.psf_weights(C, 2.5).sum())
+    t_sn = (K + 20) * U * m["A"] + m["L"] * dpos + U * float(np.abs(b).sum()) * sum_w / m["norm"] + 4 * U * abs(sn)
+    t_g = (K + 20) * U * m["Ag"] * (1 + dtmax) + dpos * m["Ag"] * (1 + dtmax)
+    return t_sn, t_g, dpos
+
+
+def test_refine_evaluate_matches_oracle(sst):
+    f = _field()
+    C = 33
+    rng = np.random.default_rng(5)
+    th = _thetas(f, rng, 24)
+    _say(f"case refine evaluate {len(th)} candidates, {f.n}x{f.h}x{f.w}, cutout {C}")
+    fr = torch.from_numpy(f.frames).to("cuda:0")
+    theta, snr, grad = sst.sst_refine(fr, f.t, f.t_ref, torch.from_numpy(th).to("cuda:0"), cutout=C, steps=0)
+    torch.cuda.synchronize()
+    assert torch.equal(theta.cpu(), torch.from_numpy(th))
+    snr, grad = snr.cpu().numpy().astype(np.float64), grad.cpu().numpy().astype(np.float64)
+    stats = oracle.frame_stats(f.frames)
+    worst, n_g = 0.0, 0
+    for c in range(len(th)):
+        sn, g, m = refine.objective(f.frames, f.t, f.t_ref, th[c].astype(np.float64), C, 2.5, stats, absolute=True)
+        t_sn, t_g, dpos = _tol(f, th[c].astype(np.float64), m, C, sn, stats[0])
+        assert abs(snr[c] - sn) <= t_sn, (c, snr[c], sn, t_sn)
+        worst = max(worst, abs(snr[c] - sn) / max(t_sn, 1e-30))
+        if m["kink"] > dpos:
+            assert np.all(np.abs(grad[c] - g) <= t_g + 4 * U * np.abs(g)), (c, grad[c], g, t_g)
+            n_g += 1
+    assert snr[-1] == 0.0 and np.all(grad[-1] == 0.0)
+    _say(f"  SN within {worst:.3g} of its bound; gradients compared on {n_g} of {len(th)}")
+
+
+def test_refine_ascent_matches_oracle(sst):
+    f = _field()
+    C, steps, lr = 21, 20, 0.003
+    rng = np.random.default_rng(6)
+    th = _thetas(f, rng, 3)[:3]
+    _say(f"case refine ascent {len(th)} candidates, {steps} steps, lr {lr}")
+    fr = torch.from_numpy(f.frames).to("cuda:0")
+    theta, snr, _ = sst.sst_refine(fr, f.t, f.t_ref, torch.from_numpy(th).to("cuda:0"), cutout=C, steps=steps,
+                                   lr=lr)
+    _, sn0, _ = sst.sst_refine(fr, f.t, f.t_ref, torch.from_numpy(th).to("cuda:0"), cutout=C, steps=0)
+    torch.cuda.synchronize()
+    theta, snr, sn0 = theta.cpu().numpy(), snr.cpu().numpy(), sn0.cpu().numpy()
+    assert np.all(snr >= sn0)
+    for c in range(len(th)):
+        ref_th, ref_sn, _, path = refine.ascend(f.frames, f.t, f.t_ref, th[c].astype(np.float64), steps, lr, C)
+        assert np.all(np.diff(path) >= -1e-9)
+        assert np.all(np.abs(theta[c] - ref_th) <= 2e-3), (c, theta[c], ref_th)
+        assert abs(snr[c] - ref_sn) <= 1e-3 * max(1.0, abs(ref_sn)), (c, snr[c], ref_sn)
+
+
+def test_autograd_function(sst):
+    f = _field()
+    fr = torch.from_numpy(f.frames).to("cuda:0")
+    th = torch.from_numpy(_thetas(f, np.random.default_rng(7), 3)[:3]).to("cuda:0").requires_grad_(True)
+    s = sst.stacked_snr(th, fr, f.t, f.t_ref, cutout=21)
+    (s * torch.tensor([1.0, 2.0, -0.5], device="cuda:0")).sum().backward()
+    _, _, g = sst.sst_refine(fr, f.t, f.t_ref, th.detach(), cutout=21, steps=0)
+    want = g * torch.tensor([1.0, 2.0, -0.5], device="cuda:0")[:, None]
+    assert torch.equal(th.grad, want)
+    # a torch optimiser climbing the objective
+    p = th.detach().clone().requires_grad_(True)
+    opt = torch.optim.SGD([p], lr=0.01, maximize=True)
+    s0 = sst.stacked_snr(p, fr, f.t, f.t_ref, cutout=21).detach()
+    for _ in range(10):
+        opt.zero_grad()
+        sst.stacked_snr(p, fr, f.t, f.t_ref, cutout=21).sum().backward()
+        opt.step()
+    s1 = sst.stacked_snr(p, fr, f.t, f.t_ref, cutout=21).detach()
+    assert torch.all(s1 >= s0)
+
+
+def test_refine_16bit_frames(sst):
+    f = _field()
+    q, s, _ = oracle.quantize_frames(f.frames, "f16", center=True)
+    fd = oracle.dequantize_frames(q, s, "f16")
+    th = _thetas(f, np.random.default_rng(8), 6)
+    qt = torch.from_numpy(q.view(np.int16)).to("cuda:0").view(torch.float16)
+    _, snr, _ = sst.sst_refine(qt, f.t, f.t_ref, torch.from_numpy(th).to("cuda:0"), cutout=33, steps=0,
+                               scale=torch.from_numpy(s).to("cuda:0"))
+    snr = snr.cpu().numpy()
+    stats = oracle.frame_stats(fd)
+    for c in range(len(th)):
+        sn, _, m = refine.objective(fd, f.t, f.t_ref, th[c].astype(np.float64), 33, 2.5, stats, absolute=True)
+        t_sn, _, _ = _tol(f, th[c].astype(np.float64), m, 33, sn, stats[0])
+        assert abs(snr[c] - sn) <= t_sn, (c, snr[c], sn)
+
+
+@pytest.mark.slow
+def test_refine_full_field_candidates(sst):
+    """4096 candidates drawn from the full field's detections, jittered by up
+    to 0.5 px and 0.5 px/h, 33x33 cutouts over 64 frames, 20 ascent steps;
+    gradients checked against float32 central differences (h = 1e-3) on the
+    GPU and against the float64 oracle gradient."""
+    f = synth.config2()
+    fr = torch.from_numpy(f.frames).to("cuda:0")
+    cand, count = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max)
+    g = sst.candidates_to_numpy(cand)
+    cnt = count.cpu().numpy()
+    pool = []
+    for k in range(len(cnt)):
+        for j in range(min(int(cnt[k]), f.k_max)):
+            pool.append((g[k]["x"][j], g[k]["y"][j], f.vx[g[k]["ivx"][j]], f.vy[g[k]["ivy"][j]]))
+    pool = np.array(pool, np.float64)
+    rng = np.random.default_rng(synth.SEED_BASE + 5)
+    pick = pool[rng.integers(0, len(pool), 4096)]
+    th = (pick + np.concatenate([rng.uniform(-0.5, 0.5, (4096, 2)), rng.uniform(-0.5, 0.5, (4096, 2))], axis=1))
+    th = th.astype(np.float32)
+    tht = torch.from_numpy(th).to("cuda:0")
+    _, sn0, g0 = sst.sst_refine(fr, f.t, f.t_ref, tht, steps=0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    th20, sn20, _ = sst.sst_refine(fr, f.t, f.t_ref, tht, steps=20, lr=0.002)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    up = float((sn20 - sn0).mean())
+    _say(f"  {len(pool)} detections, 4096 candidates x 20 steps: {ms:.2f} ms; mean SN {float(sn0.mean()):.3f} -> "
+         f"{float(sn20.mean()):.3f}; SN rose for {int((sn20 >= sn0).sum())} of 4096")
+    assert up > 0
+    # central differences in float32 on the GPU, h = 1e-3, on 32 candidates
+    sub = tht[:32]
+    g_an = g0[:32].cpu().numpy().astype(np.float64)
+    h = 1e-3
+    fd = np.zeros((32, 4))
+    for j in range(4):
+        e = torch.zeros(4, device="cuda:0")
+        e[j] = h
+        _, sp, _ = sst.sst_refine(fr, f.t, f.t_ref, sub + e, steps=0)
+        _, sm, _ = sst.sst_refine(fr, f.t, f.t_ref, sub - e, steps=0)
+        fd[:, j] = (sp - sm).cpu().numpy().astype(np.float64) / (2 * h)
+    stats = oracle.frame_stats(f.frames)
+    dtmax = float(np.max(np.abs(f.t - f.t_ref)))
+    checked, worst = 0, 0.0
+    for c in range(32):
+        sn, go, m = refine.objective(f.frames, f.t, f.t_ref, th[c].astype(np.float64), 33, 2.5, stats, absolute=True)
+        if m["kink"] <= h * (1 + dtmax):
+            continue  # a sample crosses a pixel boundary inside the stencil
+        t_sn, t_g, dpos = _tol(f, th[c].astype(np.float64), m, 33, sn, stats[0])
+        # float32 differences: each SN carries t_sn, divided by 2h; the
+        # stencil's curvature term of a piecewise-linear sampler is zero
+        assert np.all(np.abs(fd[c] - g_an[c]) <= 2 * t_sn / (2 * h) + 1e-3 * np.abs(g_an[c])), (c, fd[c], g_an[c])
+        assert np.all(np.abs(g_an[c] - go) <= t_g + 4 * U * np.abs(go)), (c, g_an[c], go)
+        worst = max(worst, float(np.max(np.abs(g_an[c] - go) / (t_g + 1e-30))))
+        checked += 1
+    _say(f"  gradient checks (central differences and float64 oracle) on {checked} of 32 candidates; "
+         f"oracle gradient within {worst:.3g} of its bound")
+    assert checked >= 8
