@@ -168,15 +168,103 @@ def refine_bench(torch, sst, args):
                                  "detections_pool": len(pool), "mean_snr_after": float(sn.mean())}}), flush=True)
 
 
+def batch_bench(torch, sst, args):
+    """Many fields per call.  batch: the 16 uneven fields of the batching
+    workload (24-160 frames, 512^2-2048^2, grids 41^2-121^2); tinybatch: 64
+    fields of the small field's shape (32 x 128^2, 21^2 grid).  Each field is
+    prepared once (sst_plan_detect); timed are (a) plain sst_detect calls, one
+    per field, (b) the prepared runs enqueued back to back, (c) the same runs
+    captured in one graph and replayed, (d) the runs spread over 4 streams,
+    (e) (d) captured in one graph.  Value: updates/s of (e)."""
+    import synth
+    dev = torch.device("cuda:0")
+    if args.workload == "batch":
+        specs = synth.config3()
+    else:
+        base = synth.config1(noise=False)
+        specs = [synth.FieldSpec(f"tiny{k}", synth.SEED_BASE + 400 + k, base.n, base.h, len(base.vx), base.t, 3)
+                 for k in range(64)]
+    fields = []
+    for sp in sorted(specs, key=lambda s: -s.updates):  # largest first
+        f = sp.make()
+        fr = torch.from_numpy(f.frames).to(dev)
+        plan = sst.sst_plan_detect(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max)
+        out = (torch.empty((plan.nk, f.k_max, 8), dtype=torch.int32, device=dev),
+               torch.empty((plan.nk,), dtype=torch.int32, device=dev))
+        fields.append((f.name, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, fr, plan, out,
+                       sp.updates))
+        del f
+        if args.workload == "batch":
+            print(f"prepared {sp.name}", file=sys.stderr, flush=True)
+    total = sum(x[-1] for x in fields)
+
+    def eager():
+        for (_, t, t_ref, vx, vy, thr, cmin, kmax, fr, plan, (c, n), _) in fields:
+            sst.sst_detect(fr, t, t_ref, vx, vy, thr, cmin, kmax, ws=plan.ws, cand=c, count=n)
+
+    def runs():
+        for (*_, fr, plan, (c, n), _) in fields:
+            plan.run(fr, cand=c, count=n)
+
+    # the same runs spread over 4 streams (fields round-robin, default
+    # priority): independent fields can then share the GPU
+    streams = [torch.cuda.Stream() for _ in range(4)]
+
+    def runs_parallel():
+        cur = torch.cuda.current_stream()
+        for st in streams:
+            st.wait_stream(cur)
+        for k, (*_, fr, plan, (c, n), _) in enumerate(fields):
+            with torch.cuda.stream(streams[k % len(streams)]):
+                plan.run(fr, cand=c, count=n)
+        for st in streams:
+            cur.wait_stream(st)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    reps = max(1, args.steps // (5 if args.workload == "batch" else 1))
+    t_runs = timed(runs, reps)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        runs()
+    torch.cuda.synchronize()
+    t_graph = timed(graph.replay, reps)
+    t_par = timed(runs_parallel, reps)
+    graph4 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph4):
+        runs_parallel()
+    torch.cuda.synchronize()
+    t_graph4 = timed(graph4.replay, reps)
+    # the eager path re-uploads the tables into the plans' workspaces: last
+    t_eager = timed(eager, reps)
+    print(json.dumps({"metric": "frame*pixel*velocity updates/s", "value": total / t_graph4, "unit": "updates/s",
+                      "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": t_graph4 * 1e3, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": f"{args.workload}: {len(fields)} fields, {total:.3g} updates",
+                                 "fields": [x[0] for x in fields]},
+                      "ms_eager_calls": t_eager * 1e3, "ms_prepared_runs": t_runs * 1e3,
+                      "ms_graph_replay": t_graph * 1e3, "ms_prepared_runs_4_streams": t_par * 1e3,
+                      "ms_graph_replay_4_streams": t_graph4 * 1e3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["full", "tiny", "prep", "refine"], default="full",
+    ap.add_argument("--workload", choices=["full", "tiny", "prep", "refine", "batch", "tinybatch"], default="full",
                     help="full: the search on the full field; tiny: the small field; prep: the steps before the "
                          "search (2x2 binning, median removal, co-adding) timed on their own; refine: sub-pixel "
-                         "refinement of 4096 full-field detections (33x33 cutouts, 20 ascent steps)")
+                         "refinement of 4096 full-field detections (33x33 cutouts, 20 ascent steps); batch: 16 "
+                         "uneven fields as prepared runs, back to back and as one graph; tinybatch: 64 small "
+                         "fields likewise")
     ap.add_argument("--storage", choices=["f32", "bf16", "f16"], default="f32",
                     help="frame storage: 16-bit frames with per-frame scales (quantised on the GPU before the "
                          "timed region); arithmetic stays float32")
@@ -202,6 +290,9 @@ def main():
         return
     if args.workload == "refine":
         refine_bench(torch, sst, args)
+        return
+    if args.workload in ("batch", "tinybatch"):
+        batch_bench(torch, sst, args)
         return
 
     f = synth.config2() if args.workload == "full" else synth.config1()

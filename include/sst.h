@@ -159,6 +159,34 @@ int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, 
                sst_candidate* cand, int32_t* count, double* frame_stats,
                void* ws, size_t ws_bytes, void* stream);
 
+/* ---- prepared searches: set-up once, enqueue-only runs ----
+ * A run of a prepared plan enqueues kernels only: no host synchronisation,
+ * no allocation and no memset, so it may be captured into a hipGraph (for
+ * example many fields of a night in one graph) and replayed; replays read
+ * the frames and write cand/count at the addresses given when captured. */
+typedef struct sst_plan sst_plan;
+
+/* Prepare sst_detect for one geometry (frame count and size, timestamps,
+ * velocity grid) and detection settings.  Validates the arguments as
+ * sst_detect does, computes the shift tables and uploads them into `ws`
+ * (waits for `stream` once).  ws: dev, >= sst_workspace_bytes(SST_OP_DETECT,
+ * ...); it belongs to the plan until sst_plan_destroy: do not use it for
+ * other calls meanwhile.  *plan receives a host object (free it with
+ * sst_plan_destroy).  Errors: as sst_detect. */
+int sst_plan_detect(int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
+                    const double* vy, int nvy, float threshold, int min_coverage, int k_max,
+                    void* ws, size_t ws_bytes, void* stream, sst_plan** plan);
+
+/* The search of sst_detect for frames of the prepared geometry (same
+ * results bit for bit).  frames/dtype/scale/cand/count as for sst_detect.
+ * Runs of plans that share a workspace must not overlap in time.
+ * Errors: SST_E_ARG, SST_E_DEVICE (launch failures). */
+int sst_plan_run(const sst_plan* plan, const void* frames, int dtype, const float* scale,
+                 sst_candidate* cand, int32_t* count, void* stream);
+
+/* Free a plan (NULL is ignored).  The workspace is the caller's again. */
+void sst_plan_destroy(sst_plan* plan);
+
 /* Sub-pixel refinement of detections by gradient ascent on a differentiable
  * stacked S/N.  The search returns tracks on its integer grid (paper Sec.
  * 2.1); here theta = (x0, y0, vx, vy) is continuous.  For each candidate a

@@ -19,6 +19,7 @@ from .binding import (  # noqa: F401
     SST_OP_STATS,
     SST_SUM,
     SstError,
+    SstPlan,
     candidates_to_numpy,
     load,
     sst_bin2x2,
@@ -27,6 +28,7 @@ from .binding import (  # noqa: F401
     sst_frame_stats,
     sst_last_error,
     sst_median_subtract,
+    sst_plan_detect,
     sst_profile_begin,
     sst_profile_end,
     sst_quantize,

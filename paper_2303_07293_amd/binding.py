@@ -36,7 +36,8 @@ CANDIDATE_DTYPE = np.dtype([
 ])
 
 EXPORTS = ("sst_shift_table", "sst_workspace_bytes", "sst_quantize", "sst_median_subtract", "sst_coadd", "sst_bin2x2",
-           "sst_frame_stats", "sst_stack", "sst_detect", "sst_refine",
+           "sst_frame_stats", "sst_stack", "sst_detect", "sst_refine", "sst_plan_detect", "sst_plan_run",
+           "sst_plan_destroy",
            "sst_profile_begin", "sst_profile_end", "sst_last_error", "sst_version")
 
 
@@ -85,6 +86,13 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.sst_detect.restype = _i
     lib.sst_refine.argtypes = [_p, _i, _p, _i, _i, _i, _p, _d, _i, _p, _i, _f, _i, _f, _p, _p, _p, _sz, _p]
     lib.sst_refine.restype = _i
+    lib.sst_plan_detect.argtypes = [_i, _i, _i, _p, _d, _p, _i, _p, _i, _f, _i, _i, _p, _sz, _p,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+    lib.sst_plan_detect.restype = _i
+    lib.sst_plan_run.argtypes = [_p, _p, _i, _p, _p, _p, _p]
+    lib.sst_plan_run.restype = _i
+    lib.sst_plan_destroy.argtypes = [_p]
+    lib.sst_plan_destroy.restype = None
     lib.sst_profile_begin.argtypes = []
     lib.sst_profile_begin.restype = _i
     lib.sst_profile_end.argtypes = [_p, _p]
@@ -339,6 +347,56 @@ def sst_refine(frames, t, t_ref: float, params, cutout: int = 33, fwhm: float = 
                              float(t_ref), nc, _dev(theta), int(cutout), float(fwhm), int(steps), float(lr),
                              _dev(snr), _dev(grad), _dev(ws), ws.numel(), _stream(frames.device)))
     return theta, snr, grad
+
+
+class SstPlan:
+    """A prepared detect problem (sst_plan_detect).  It owns its workspace
+    tensor; `run` enqueues kernels only and may be captured in a graph."""
+
+    def __init__(self, handle, ws, n, h, w, nk, k_max):
+        self._h = handle
+        self.ws = ws
+        self.n, self.h, self.w, self.nk, self.k_max = n, h, w, nk, k_max
+
+    def run(self, frames, scale=None, cand=None, count=None):
+        import torch
+        _check_frames(frames)
+        if tuple(frames.shape) != (self.n, self.h, self.w):
+            raise ValueError(f"frames {tuple(frames.shape)} do not match the plan {(self.n, self.h, self.w)}")
+        if self._h is None:
+            raise RuntimeError("plan was destroyed")
+        if cand is None:
+            cand = torch.empty((self.nk, self.k_max, 8), dtype=torch.int32, device=frames.device)
+        if count is None:
+            count = torch.empty((self.nk,), dtype=torch.int32, device=frames.device)
+        _check(load().sst_plan_run(self._h, _dev(frames), _frames_dtype(frames), _check_scale(frames, scale),
+                                   _dev(cand), _dev(count), _stream(frames.device)))
+        return cand, count
+
+    def close(self):
+        if self._h is not None:
+            load().sst_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sst_plan_detect(n: int, h: int, w: int, t, t_ref: float, vx, vy, threshold: float, min_coverage: int = 0,
+                    k_max: int = 64, device="cuda:0") -> SstPlan:
+    """Prepare sst_detect for one geometry (uploads the shift tables once)."""
+    import torch
+    t, vx, vy = _f64(t), _f64(vx), _f64(vy)
+    nb = sst_workspace_bytes(SST_OP_DETECT, n, h, w, t, t_ref, vx, vy, k_max)
+    ws = torch.empty(nb, dtype=torch.uint8, device=device)
+    handle = ctypes.c_void_p()
+    _check(load().sst_plan_detect(n, h, w, _ptr(t), float(t_ref), _ptr(vx), len(vx), _ptr(vy), len(vy),
+                                  float(threshold), int(min_coverage), int(k_max), _dev(ws), ws.numel(),
+                                  _stream(torch.device(device)), ctypes.byref(handle)))
+    return SstPlan(handle, ws, n, h, w, len(vx) * len(vy), k_max)
 
 
 def sst_profile_begin() -> None:

@@ -5,6 +5,7 @@
 #include "sst_internal.h"
 
 #include <algorithm>
+#include <new>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -343,7 +344,49 @@ hipError_t launch_stack_profiled(const StackArgs& a, bool detect, bool staged, h
     return e;
 }
 
+// Everything a detect call enqueues after the shift tables are in the
+// workspace: kernels only (no host synchronisation, no allocation, no
+// memset), so the sequence can be captured into a graph.
+int detect_enqueue(const Plan& p, void* ws, const void* frames, int dtype, const float* scale, float threshold,
+                   int min_coverage, int k_max, sst_candidate* cand, int32_t* count, bool stats_out, hipStream_t s) {
+    hipError_t e = launch_stats(frames, dtype, scale, p.n, p.h, p.w, at<double>(ws, p.o_part), p.nchunk,
+                                at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
+                                at<double>(ws, p.o_P), stats_out ? at<double>(ws, p.o_sdev) : nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
+    int rc;
+    if ((rc = prep_and_cov(p, frames, dtype, scale, at<float>(ws, p.o_b32), ws, s))) return rc;
+    StackArgs a = stack_args(p, ws);
+    a.thr = threshold;
+    a.cmin = min_coverage > 0 ? min_coverage : (p.n + 1) / 2;
+    a.kt = p.kt;
+    a.tcount = at<int32_t>(ws, p.o_tcount);
+    a.ent = at<Entry>(ws, p.o_ent);
+    for (int r0 = 0; r0 < p.nvby; r0 += p.rows_per_chunk) {
+        const int rows = std::min(p.rows_per_chunk, p.nvby - r0);
+        a.vby0 = r0;
+        a.nvby = rows;
+        if ((e = launch_stack_profiled(a, true, p.staged, s)) != hipSuccess) return hip_fail(e, "detect kernel");
+        const int b_first = r0 * kVBY;
+        const int b_last = std::min(p.nvy, (r0 + rows) * kVBY);
+        const int nk = (b_last - b_first) * p.nvx;
+        if ((e = launch_merge(a.tcount, a.ent, p.nslot, p.kt, k_max, p.nvx, p.w, b_first * p.nvx, nk, cand, count,
+                              s)) != hipSuccess)
+            return hip_fail(e, "merge kernel");
+    }
+    return SST_OK;
+}
+
 }  // namespace
+
+// A prepared detect problem: its geometry and the workspace that holds its
+// shift tables.
+struct sst_plan {
+    Plan p;
+    void* ws = nullptr;
+    float threshold = 0.f;
+    int min_coverage = 0;
+    int k_max = 0;
+};
 
 extern "C" {
 
@@ -598,36 +641,53 @@ int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, 
     if ((rc = check_ws(p, ws, ws_bytes))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((rc = upload_tables(p, nullptr, ws, s))) return rc;
-    hipError_t e = launch_stats(frames, dtype, scale, n, h, w, at<double>(ws, p.o_part), p.nchunk,
-                                at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
-                                at<double>(ws, p.o_P), at<double>(ws, p.o_sdev), s);
-    if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
-    if ((rc = prep_and_cov(p, frames, dtype, scale, at<float>(ws, p.o_b32), ws, s))) return rc;
-    StackArgs a = stack_args(p, ws);
-    a.thr = threshold;
-    a.cmin = min_coverage > 0 ? min_coverage : (n + 1) / 2;
-    a.kt = p.kt;
-    a.tcount = at<int32_t>(ws, p.o_tcount);
-    a.ent = at<Entry>(ws, p.o_ent);
-    for (int r0 = 0; r0 < p.nvby; r0 += p.rows_per_chunk) {
-        const int rows = std::min(p.rows_per_chunk, p.nvby - r0);
-        a.vby0 = r0;
-        a.nvby = rows;
-        if ((e = launch_stack_profiled(a, true, p.staged, s)) != hipSuccess) return hip_fail(e, "detect kernel");
-        const int b_first = r0 * kVBY;
-        const int b_last = std::min(nvy, (r0 + rows) * kVBY);
-        const int nk = (b_last - b_first) * nvx;
-        if ((e = launch_merge(a.tcount, a.ent, p.nslot, p.kt, k_max, nvx, w, b_first * nvx, nk, cand, count, s)) !=
-            hipSuccess)
-            return hip_fail(e, "merge kernel");
-    }
+    if ((rc = detect_enqueue(p, ws, frames, dtype, scale, threshold, min_coverage, k_max, cand, count,
+                             frame_stats != nullptr, s)))
+        return rc;
     if (frame_stats) {
-        e = hipMemcpyAsync(frame_stats, at<double>(ws, p.o_sdev), (size_t)n * 2 * sizeof(double),
-                           hipMemcpyDeviceToHost, s);
+        hipError_t e = hipMemcpyAsync(frame_stats, at<double>(ws, p.o_sdev), (size_t)n * 2 * sizeof(double),
+                                      hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(frame stats)");
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     }
     return SST_OK;
 }
+
+int sst_plan_detect(int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx, const double* vy,
+                    int nvy, float threshold, int min_coverage, int k_max, void* ws, size_t ws_bytes, void* stream,
+                    sst_plan** plan) {
+    g_err.clear();
+    if (!plan) return fail(SST_E_ARG, "plan is NULL");
+    *plan = nullptr;
+    if (std::isnan(threshold)) return fail(SST_E_ARG, "threshold is NaN");
+    sst_plan* pl = new (std::nothrow) sst_plan;
+    if (!pl) return fail(SST_E_DEVICE, "out of host memory");
+    int rc = make_plan(SST_OP_DETECT, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, pl->p);
+    if (!rc) rc = check_ws(pl->p, ws, ws_bytes);
+    if (!rc) rc = upload_tables(pl->p, nullptr, ws, static_cast<hipStream_t>(stream));
+    if (rc) {
+        delete pl;
+        return rc;
+    }
+    pl->ws = ws;
+    pl->threshold = threshold;
+    pl->min_coverage = min_coverage;
+    pl->k_max = k_max;
+    *plan = pl;
+    return SST_OK;
+}
+
+int sst_plan_run(const sst_plan* plan, const void* frames, int dtype, const float* scale, sst_candidate* cand,
+                 int32_t* count, void* stream) {
+    g_err.clear();
+    if (!plan) return fail(SST_E_ARG, "plan is NULL");
+    int rc = check_frames(frames, dtype, scale);
+    if (rc) return rc;
+    if (!cand || !count) return fail(SST_E_ARG, "cand/count is NULL");
+    return detect_enqueue(plan->p, plan->ws, frames, dtype, scale, plan->threshold, plan->min_coverage, plan->k_max,
+                          cand, count, false, static_cast<hipStream_t>(stream));
+}
+
+void sst_plan_destroy(sst_plan* plan) { delete plan; }
 
 }  // extern "C"

@@ -10,9 +10,11 @@ code of the method.
 
 from .fields import (  # noqa: F401
     Field,
+    FieldSpec,
     Mover,
     config1,
     config2,
+    config3,
     config_diagnostic,
     pure_noise,
     render_movers,

@@ -153,6 +153,56 @@ def config2(n_movers: int = 50, h: int = 1024, w: int = 1024) -> Field:
                  threshold=5.0, min_coverage=32, k_max=64, movers=movers, sky=100.0, sigma=10.0)
 
 
+@dataclasses.dataclass
+class FieldSpec:
+    """A field of a batch whose frames are made on demand (`make`)."""
+    name: str
+    seed: int
+    n: int
+    side: int
+    grid: int  # odd: velocities -(grid//2) .. grid//2 px/h at 1 px/h on both axes
+    t: np.ndarray
+    n_movers: int
+
+    @property
+    def updates(self) -> int:
+        return self.n * self.side * self.side * self.grid * self.grid
+
+    def make(self) -> Field:
+        rng = np.random.default_rng(self.seed)
+        vmax = self.grid // 2
+        movers = []
+        for _ in range(self.n_movers):
+            amp = float(math.exp(rng.uniform(math.log(2.0), math.log(30.0))))
+            vx, vy = (float(v) for v in rng.uniform(-vmax, vmax, size=2))
+            movers.append(Mover(float(rng.uniform(0, self.side)), float(rng.uniform(0, self.side)), vx, vy, amp, 2.5))
+        frames = _frames(rng, self.t, float(self.t[0]), self.side, self.side, 100.0, 10.0, movers)
+        g = np.arange(-vmax, vmax + 1, dtype=np.float64)
+        return Field(self.name, frames, self.t, float(self.t[0]), g, g.copy(), threshold=5.0,
+                     min_coverage=(self.n + 1) // 2, k_max=64, movers=movers, sky=100.0, sigma=10.0)
+
+
+def config3(n_fields: int = 16) -> List[FieldSpec]:
+    """Batch of uneven fields: frame counts uniform in 24..160, sides drawn
+    from {512, 768, 1024, 2048}, velocity grids n x n with n odd in 41..121
+    (1 px/h), timestamps over 4 h with 10% of the slots dropped, config 2's
+    noise and movers (50 per 1024^2, scaled by area)."""
+    rng = np.random.default_rng(SEED_BASE + 3)
+    out = []
+    for k in range(n_fields):
+        n = int(rng.integers(24, 161))
+        side = int(rng.choice([512, 768, 1024, 2048]))
+        grid = int(rng.choice(np.arange(41, 122, 2)))
+        m = int(round(n / 0.9))
+        slots = np.arange(m, dtype=np.float64) * (4.0 / (m - 1))
+        keep = np.sort(rng.choice(m, size=n, replace=False))
+        t = slots[keep]
+        n_movers = max(1, int(round(50 * side * side / 1024 ** 2)))
+        out.append(FieldSpec(f"batch{k} {n}x{side}x{side} grid{grid}x{grid}", int(SEED_BASE + 300 + k), n, side, grid,
+                             t, n_movers))
+    return out
+
+
 def config_diagnostic(n_frames: int = 32) -> Field:
     """Diagnostic shape for the stack's HBM roof: config 2's noise and grid
     with fewer frames (the materialised stack is HBM-bound only for small N)."""

@@ -259,3 +259,20 @@ def test_refine_argument_errors(lib):
     assert call(tt=np.array([0.0, 2.0, 1.0, 3.0])) == B.SST_E_UNSORTED
     assert call(wsb=4) == B.SST_E_WORKSPACE
     assert sst.sst_workspace_bytes(B.SST_OP_REFINE, 4, 8, 8) > 0
+
+
+def test_plan_argument_errors(lib):
+    h = ctypes.c_void_p()
+    t = np.arange(4, dtype=np.float64)
+    v = np.array([0.0, 1.0])
+    assert lib.sst_plan_detect(4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 5.0, 0, 4, FAKE, 1 << 40, None, None) \
+        == B.SST_E_ARG
+    assert lib.sst_plan_detect(4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, float("nan"), 0, 4, FAKE, 1 << 40, None,
+                               ctypes.byref(h)) == B.SST_E_ARG
+    assert h.value is None
+    assert lib.sst_plan_detect(4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 5.0, 0, 0, FAKE, 1 << 40, None,
+                               ctypes.byref(h)) == B.SST_E_ARG
+    assert lib.sst_plan_detect(4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 5.0, 0, 4, FAKE, 10, None,
+                               ctypes.byref(h)) == B.SST_E_WORKSPACE
+    assert lib.sst_plan_run(None, FAKE, 0, None, FAKE, FAKE, None) == B.SST_E_ARG
+    lib.sst_plan_destroy(None)

@@ -1,0 +1,123 @@
+"""Prepared searches and graph capture (through the C ABI).
+
+* a run of a prepared plan gives the same candidate lists, bit for bit, as
+  sst_detect on the same frames;
+* the runs of several fields of different geometry are captured into one
+  hipGraph, on one stream or as parallel branches; each replay, with eager
+  work in between that rewrites the frames, reproduces eager sst_detect on the
+  current frames bit for bit, and one field is checked against the float64
+  oracle.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare_velocity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sst():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_07293_amd as m
+    m.load()
+    return m
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+FIELDS = [(50, 10, 70, 130, 7, 5, 3.0), (51, 16, 64, 64, 6, 4, 2.0), (52, 8, 33, 97, 5, 9, 6.0),
+          (53, 12, 97, 61, 6, 4, 4.0), (54, 1, 40, 70, 2, 3, 2.0), (55, 24, 128, 128, 13, 11, 5.0)]
+
+
+def _case(spec, seed_shift=0):
+    seed, n, h, w, nvx, nvy, vmax = spec
+    f = synth.small_case(seed, n, h, w, nvx, nvy, vmax=vmax, sky=50.0, sigma=5.0)
+    if seed_shift:
+        g = synth.small_case(seed + 1000 * seed_shift, n, h, w, nvx, nvy, vmax=vmax, sky=50.0, sigma=5.0)
+        f.frames = g.frames  # same geometry, new pixels
+    return f
+
+
+def test_plan_run_matches_detect(sst):
+    f = _case(FIELDS[0])
+    _say(f"case plan {f.name}")
+    plan = sst.sst_plan_detect(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, 2.5, 0, 8)
+    for shift in (0, 1, 2):
+        g = _case(FIELDS[0], shift)
+        fr = torch.from_numpy(g.frames).to("cuda:0")
+        c1, n1 = plan.run(fr)
+        c2, n2 = sst.sst_detect(fr, g.t, g.t_ref, g.vx, g.vy, 2.5, 0, 8)
+        torch.cuda.synchronize()
+        assert torch.equal(c1, c2) and torch.equal(n1, n2)
+    plan.close()
+
+
+@pytest.mark.parametrize("n_streams", [1, 3])
+def test_graph_capture_of_many_fields(sst, n_streams):
+    cases = [_case(s) for s in FIELDS]
+    _say(f"case graph of {len(cases)} fields on {n_streams} branches")
+    plans = [sst.sst_plan_detect(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, 2.5, 0, 8) for f in cases]
+    frames = [torch.from_numpy(f.frames).to("cuda:0") for f in cases]
+    outs = [(torch.empty((p.nk, 8, 8), dtype=torch.int32, device="cuda:0"),
+             torch.empty((p.nk,), dtype=torch.int32, device="cuda:0")) for p in plans]
+    # warm-up outside the capture, then capture every field's run
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for p, fr, (c, n) in zip(plans, frames, outs):
+            p.run(fr, cand=c, count=n)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    # capture: the fields round-robin over n_streams branches that fork from
+    # and join the capture stream
+    branches = [torch.cuda.Stream() for _ in range(n_streams)]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        cur = torch.cuda.current_stream()
+        for st in branches:
+            st.wait_stream(cur)
+        for k, (p, fr, (c, n)) in enumerate(zip(plans, frames, outs)):
+            with torch.cuda.stream(branches[k % n_streams]):
+                p.run(fr, cand=c, count=n)
+        for st in branches:
+            cur.wait_stream(st)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        new = [_case(s, rep + 1) for s in FIELDS]
+        for fr, g in zip(frames, new):
+            fr.copy_(torch.from_numpy(g.frames))  # eager work between replays
+        for c, n in outs:
+            c.fill_(-7)
+            n.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k, (g, (c, n)) in enumerate(zip(new, outs)):
+            ce, ne = sst.sst_detect(frames[k], g.t, g.t_ref, g.vx, g.vy, 2.5, 0, 8)
+            torch.cuda.synchronize()
+            assert torch.equal(c, ce) and torch.equal(n, ne), (rep, k)
+        _say(f"  replay {rep}: {len(new)} fields match eager runs")
+    # one field of the last replay against the oracle
+    g = new[1]
+    got = sst.candidates_to_numpy(outs[1][0])
+    cnt = outs[1][1].cpu().numpy()
+    ks = list(range(len(g.vx) * len(g.vy)))
+    ref = oracle.detect(g.frames, g.t, g.t_ref, g.vx, g.vy, 2.5, 0, 8, velocities=ks, keep_maps=True)
+    b, _ = oracle.frame_stats(g.frames)
+    marg = sum(compare_velocity(got[k], int(cnt[k]), ref[k], g.n, float(np.abs(b).max()), 2.5, ref["c_min"], 8, g.w)
+               for k in ks)
+    assert marg <= 4
+    for p in plans:
+        p.close()
