@@ -264,6 +264,7 @@ StackArgs stack_args(const Plan& p, void* ws) {
     StackArgs a{};
     a.pad = at<float>(ws, p.o_pad);
     a.fstride = (long long)p.Hp * p.Wp;
+    a.gchunk = (int)std::max<long long>(1, std::min<long long>(kGeomChunk, 0x7FFFFFFFll / (a.fstride * 4)));
     a.n = p.n;
     a.h = p.h;
     a.w = p.w;

@@ -56,6 +56,7 @@ constexpr int kStatChunk = 8192;  // pixels per frame-statistics workgroup
 constexpr int kMaxK = 1024;       // largest k_max accepted
 constexpr int kMergeLds = 2048;   // entries ranked in LDS by the merge kernel
 constexpr int kPLds = 1024;       // variance-prefix entries the stack kernel keeps in LDS
+constexpr int kGeomChunk = 256;   // frames whose block geometry the stack kernel keeps in LDS
 
 // One candidate kept by a (tile, velocity) before the per-velocity merge.
 struct Entry {
@@ -93,6 +94,7 @@ struct StackArgs {
     const int* IX;    // [nvx][w][2]: first and last frame whose x sample is in the frame
     const int* IY;    // [nvy][h][2]
     const double* P;  // [n+1] prefix sums of the frame variances
+    int gchunk;     // frames per geometry chunk (their padded frames span < 2^31 bytes)
     int tiles_x, tiles_y, step_x, step_y, halo;
     int nvbx;        // velocity blocks along x
     int vby0, nvby;  // velocity-block rows handled by this launch

@@ -294,20 +294,24 @@ __device__ __forceinline__ int coverage(int xlo, int xhi, int ylo, int yhi, int&
 
 // -------------------------------------------------------------- stacking
 // Per-frame geometry of a workgroup's velocity block, kept in LDS for a
-// chunk of kGeomChunk frames.  For frame i the staged window is the
-// kStageW x kLdsRows region of the padded copy whose origin is the
-// 16-byte aligned column at or left of X0 + (smallest x shift of the block)
-// and the row Y0 + (smallest y shift).  All offsets are in elements.
-constexpr int kGeomChunk = 256;
-constexpr int kGeomInts = 12;  // soff, col[2][3], row[4], 1 spare
+// chunk of at most kGeomChunk frames (fewer when a chunk's frames would span
+// more than 2^31 bytes of the padded copy: every staging read of a chunk is
+// a 31-bit byte offset from one buffer descriptor).  For frame i the staged
+// window is the kStageW x kLdsRows region of the padded copy whose origin is
+// the 16-byte aligned column at or left of X0 + (smallest x shift of the
+// block) and the row Y0 + (smallest y shift).  Entry k holds frame f0 + k
+// for k < cnt and repeats the chunk's last frame for k = cnt, cnt + 1, so
+// that the frame loop reads entries j + 1 and j + 2 without bounds tests.
+constexpr int kGeomInts = 12;  // window byte offset, col[2][3], row[4], 1 spare
 static_assert(kVBX == 2 * kVPW && kVBY == 2 * kVYW && kWaves == 8, "geometry layout assumed below");
 
-// Fill the geometry of frames [f0, f0 + cnt) (one thread per frame).
+// Fill the geometry of frames [f0, f0 + cnt) (one thread per entry).
 __device__ __forceinline__ void fill_geometry(const StackArgs& A, int* geo, int f0, int cnt, int a0, int b0, int X0,
                                               int Y0) {
     const int t = threadIdx.x;
-    if (t < cnt) {
-        const int i = f0 + t;
+    if (t < cnt + 2) {
+        const int k = min(t, cnt - 1);
+        const int i = f0 + k;
         const int* rx = A.DX + (long long)i * A.ldx + a0;
         const int* ry = A.DY + (long long)i * A.ldy + b0;
         int dx[kVBX], dy[kVBY];
@@ -325,7 +329,9 @@ __device__ __forceinline__ void fill_geometry(const StackArgs& A, int* geo, int 
         const int c0 = gx0 - xa;
         const int gy0 = Y0 + dymin + A.padT;
         int* g = geo + t * kGeomInts;
-        g[0] = gy0 * A.Wp + xa;  // window origin within frame i of the padded copy
+        // window origin: bytes from the chunk's first frame (< 2^31 by the
+        // chunk size)
+        g[0] = (int)(((long long)k * A.fstride + (long long)gy0 * A.Wp + xa) * 4);
 #pragma unroll
         for (int j = 0; j < kVBX; ++j) g[1 + j] = c0 + dx[j] - dxmin;  // LDS column of velocity j
 #pragma unroll
@@ -339,14 +345,14 @@ constexpr int kStage = kLdsRows / (2 * kWaves);  // staging loads per thread and
 
 // Staging: wave w, load j covers staged row 2*(w + kWaves*j) + (lane >> 5),
 // float4 column lane & 31 (lanes with column >= kC4 idle).  The per-lane part
-// of the address is constant; the frame and j parts are scalar.
-__device__ __forceinline__ void stage_load(__amdgpu_buffer_rsrc_t rsrc, int voff, int soff, int Wp, bool act,
+// of the address is constant; the frame and j parts are scalar byte offsets.
+__device__ __forceinline__ void stage_load(__amdgpu_buffer_rsrc_t rsrc, int voff, int sbyte, int Wp, bool act,
                                            f4 (&st)[kStage]) {
 #pragma unroll
     for (int j = 0; j < kStage; ++j) {
         if (act)
             st[j] = __builtin_bit_cast(
-                f4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, (soff + j * 2 * kWaves * Wp) * 4, 0));
+                f4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, sbyte + j * 2 * kWaves * Wp * 4, 0));
     }
 }
 
@@ -583,7 +589,7 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
     constexpr int kXchFloats = kWaves * kVPW * kVYW * kWave;
     constexpr int kLdsFloats = (2 * kLdsBuf > kColFloats + kXchFloats) ? 2 * kLdsBuf : kColFloats + kXchFloats;
     __shared__ __attribute__((aligned(16))) float lds[kLdsFloats];
-    __shared__ int geo[STAGED ? kGeomChunk * kGeomInts : 1];
+    __shared__ int geo[STAGED ? (kGeomChunk + 2) * kGeomInts : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -616,71 +622,64 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
         const bool act = scol < kC4;
         const int voff = (srow * A.Wp + 4 * scol) * 4;  // bytes, per lane
         const int loff = srow * kLdsPitch + 4 * scol;   // floats, per lane
-        const unsigned fbytes = (unsigned)min((long long)A.fstride * 4, 0x7FFFFFFFll);
-        const int last = A.n - 1;
-        int f0 = 0;
-        fill_geometry(A, geo, 0, min(A.n, kGeomChunk), a0, b0, X0, Y0);
-        __syncthreads();
-        // this wave's geometry of frame i: the LDS row offsets of its two y
+        // this wave's geometry of frame j: the LDS row offsets of its two y
         // velocities and the kVPW column offsets, plus the staging window
-        // origin of frame i + 1
+        // of frame j + 1
         const int gw_row = 1 + kVBX + kVYW * yp, gw_col = 1 + kVPW * xg;
         const int hoff = h * kRowsW * kLdsPitch;
-        auto frame_rsrc = [&](int i) {
-            return __builtin_amdgcn_make_buffer_rsrc((void*)(A.pad + (long long)i * A.fstride), 0, fbytes, 0x00020000);
-        };
         f4 st[kStage];
-        stage_load(frame_rsrc(0), voff, __builtin_amdgcn_readfirstlane(geo[0]), A.Wp, act, st);
-        stage_store(lds, loff, act, st);
-        int row0 = __builtin_amdgcn_readfirstlane(geo[gw_row]);
-        int row1 = __builtin_amdgcn_readfirstlane(geo[gw_row + 1]);
-        int col[kVPW];
-#pragma unroll
-        for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(geo[gw_col + q]);
-        int soff_next = __builtin_amdgcn_readfirstlane(geo[min(1, last) * kGeomInts]);
-        __syncthreads();
-        for (int i = 0; i < A.n; ++i) {
-            const float* buf = lds + (i & 1) * kLdsBuf + lane;
-            // staging of frame i + 1 (the last iteration reloads frame n - 1
-            // into the idle buffer, which nobody reads)
-            const int inext = min(i + 1, last);
-            stage_load(frame_rsrc(inext), voff, soff_next, A.Wp, act, st);
-            // the next frame's geometry (a few broadcast reads), then this
-            // frame's samples
-            const int* gn = geo + (inext - f0) * kGeomInts;
-            const int* gs = geo + (min(i + 2, last) - f0) * kGeomInts;
-            const int nrow0 = gn[gw_row], nrow1 = gn[gw_row + 1];
-            int ncol[kVPW];
-#pragma unroll
-            for (int q = 0; q < kVPW; ++q) ncol[q] = gn[gw_col + q];
-            const int nsoff = gs[0];
-            const int d = (row1 - row0) / kLdsPitch;
-            const float* pb = buf + min(row0, row1) + hoff;
-            // one block per read pattern, each updating the sums in place
-            // (a chain of two-way branches keeps every sum in one register)
-            if (d == 0) accum_pair<0, 0>(pb, col, acc);
-            if (d == 1) accum_pair<1, 0>(pb, col, acc);
-            if (d == 2) accum_pair<2, 0>(pb, col, acc);
-            if (d == 3) accum_pair<3, 0>(pb, col, acc);
-            if (d == 4) accum_pair<4, 0>(pb, col, acc);
-            if (d == -1) accum_pair<1, 1>(pb, col, acc);
-            if (d == -2) accum_pair<2, 1>(pb, col, acc);
-            if (d == -3) accum_pair<3, 1>(pb, col, acc);
-            if (d == -4) accum_pair<4, 1>(pb, col, acc);
-            if (d < -kDMax || d > kDMax) accum_sep(buf + row0 + hoff, buf + row1 + hoff, col, acc);
-            static_assert(kDMax == 4, "one case per shared-read distance");
-            row0 = __builtin_amdgcn_readfirstlane(nrow0);
-            row1 = __builtin_amdgcn_readfirstlane(nrow1);
-#pragma unroll
-            for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(ncol[q]);
-            soff_next = __builtin_amdgcn_readfirstlane(nsoff);
-            stage_store(lds + ((i + 1) & 1) * kLdsBuf, loff, act, st);
+        for (int f0 = 0; f0 < A.n; f0 += A.gchunk) {
+            const int cnt = min(A.gchunk, A.n - f0);
+            // (the previous chunk's last barrier has retired every read of
+            // the table and the staging buffers)
+            fill_geometry(A, geo, f0, cnt, a0, b0, X0, Y0);
+            const long long rem = (long long)(A.n - f0) * A.fstride * 4;
+            const auto rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)(A.pad + (long long)f0 * A.fstride), 0,
+                                                                (int)min(rem, 0x7FFFFFFFll), 0x00020000);
             __syncthreads();
-            // next geometry chunk: iteration i + 1 reads frames i + 2 and i + 3
-            // (frame i + 1's geometry and frame i + 2's origin are in registers)
-            if (i + 3 <= last && i + 3 == f0 + kGeomChunk) {
-                f0 = i + 2;
-                fill_geometry(A, geo, f0, min(A.n - f0, kGeomChunk), a0, b0, X0, Y0);
+            stage_load(rsrc, voff, __builtin_amdgcn_readfirstlane(geo[0]), A.Wp, act, st);
+            stage_store(lds, loff, act, st);
+            int row0 = __builtin_amdgcn_readfirstlane(geo[gw_row]);
+            int row1 = __builtin_amdgcn_readfirstlane(geo[gw_row + 1]);
+            int col[kVPW];
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(geo[gw_col + q]);
+            int soff_next = __builtin_amdgcn_readfirstlane(geo[kGeomInts]);
+            __syncthreads();
+            for (int j = 0; j < cnt; ++j) {
+                const float* buf = lds + (j & 1) * kLdsBuf + lane;
+                // staging of frame j + 1 (at the chunk's end a repeat of its
+                // last frame into the idle buffer, which nobody reads)
+                stage_load(rsrc, voff, soff_next, A.Wp, act, st);
+                // the next frame's geometry (a few broadcast reads), then
+                // this frame's samples
+                const int* gn = geo + (j + 1) * kGeomInts;
+                const int nrow0 = gn[gw_row], nrow1 = gn[gw_row + 1];
+                int ncol[kVPW];
+#pragma unroll
+                for (int q = 0; q < kVPW; ++q) ncol[q] = gn[gw_col + q];
+                const int nsoff = gn[kGeomInts];
+                const int d = (row1 - row0) / kLdsPitch;
+                const float* pb = buf + min(row0, row1) + hoff;
+                // one block per read pattern, each updating the sums in place
+                // (a chain of two-way branches keeps every sum in one register)
+                if (d == 0) accum_pair<0, 0>(pb, col, acc);
+                if (d == 1) accum_pair<1, 0>(pb, col, acc);
+                if (d == 2) accum_pair<2, 0>(pb, col, acc);
+                if (d == 3) accum_pair<3, 0>(pb, col, acc);
+                if (d == 4) accum_pair<4, 0>(pb, col, acc);
+                if (d == -1) accum_pair<1, 1>(pb, col, acc);
+                if (d == -2) accum_pair<2, 1>(pb, col, acc);
+                if (d == -3) accum_pair<3, 1>(pb, col, acc);
+                if (d == -4) accum_pair<4, 1>(pb, col, acc);
+                if (d < -kDMax || d > kDMax) accum_sep(buf + row0 + hoff, buf + row1 + hoff, col, acc);
+                static_assert(kDMax == 4, "one case per shared-read distance");
+                row0 = __builtin_amdgcn_readfirstlane(nrow0);
+                row1 = __builtin_amdgcn_readfirstlane(nrow1);
+#pragma unroll
+                for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(ncol[q]);
+                soff_next = __builtin_amdgcn_readfirstlane(nsoff);
+                stage_store(lds + ((j + 1) & 1) * kLdsBuf, loff, act, st);
                 __syncthreads();
             }
         }
