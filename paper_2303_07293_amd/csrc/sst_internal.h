@@ -16,22 +16,22 @@ namespace sst {
 typedef int i4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// Work decomposition of the stack kernels.  A workgroup is kWaves wave64s;
-// it owns a tile of 64 columns (one per lane) by kRows rows and a block of
-// kVBX x kVBY trial velocities, so every staged frame tile is reused by all
-// kVBX * kVBY velocities of the block.  Wave w handles kRowsW = kRows / 2
-// rows (half w % 2) of kVPW x velocities (group w / 4) and kVYW = 2
-// neighbouring y velocities (pair (w / 2) % 2): kVPW * kVYW * kRowsW float
-// accumulators per lane.  For one frame the two y velocities of a pair sample
-// rows a small uniform distance d apart, so one read of kRowsW + |d| staged
-// rows feeds both sets of accumulators.
+// Work decomposition of the stack kernels.  A workgroup is kWaves wave64s
+// (three per SIMD); it owns a tile of 64 columns (one per lane) by kRows
+// rows and a block of kVBX x kVBY trial velocities, so every staged frame
+// tile is reused by all kVBX * kVBY velocities of the block.  Wave w
+// handles kRowsW = kRows / 2 rows (half w % 2) of kVPW x velocities (group
+// w / 4) and kVYW = 2 neighbouring y velocities (pair (w / 2) % 2):
+// kVPW * kVYW * kRowsW float accumulators per lane.  For one frame the two
+// y velocities of a pair sample rows a small uniform distance d apart, so
+// one read of kRowsW + |d| staged rows feeds both sets of accumulators.
 constexpr int kWave = 64;
-constexpr int kWaves = 8;
+constexpr int kWaves = 12;
 constexpr int kThreads = kWave * kWaves;
 constexpr int kTileW = 64;
 constexpr int kRows = 32;
 constexpr int kRowsW = kRows / 2;  // rows per wave
-constexpr int kVBX = 6;
+constexpr int kVBX = 9;
 constexpr int kVBY = 4;
 constexpr int kVPW = 3;  // x velocities per wave
 constexpr int kVYW = 2;  // y velocities per wave
@@ -43,7 +43,7 @@ static_assert(kVBX * kVBY * 2 == kVPW * kVYW * kWaves, "every (velocity, row hal
 // kStageW x kLdsRows floats is staged per frame; LDS rows are kLdsPitch = 128
 // floats apart so that every row of a column is reachable from one base
 // address (row offsets are multiples of 64 dwords).
-constexpr int kSMaxX = 32;
+constexpr int kSMaxX = 40;
 constexpr int kSMaxY = 16;
 constexpr int kStageW = kTileW + kSMaxX + 4;
 constexpr int kLdsPitch = 128;

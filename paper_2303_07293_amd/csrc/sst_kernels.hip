@@ -302,8 +302,8 @@ __device__ __forceinline__ int coverage(int xlo, int xhi, int ylo, int yhi, int&
 // block) and the row Y0 + (smallest y shift).  Entry k holds frame f0 + k
 // for k < cnt and repeats the chunk's last frame for k = cnt, cnt + 1, so
 // that the frame loop reads entries j + 1 and j + 2 without bounds tests.
-constexpr int kGeomInts = 12;  // window byte offset, col[2][3], row[4], 1 spare
-static_assert(kVBX == 2 * kVPW && kVBY == 2 * kVYW && kWaves == 8, "geometry layout assumed below");
+constexpr int kGeomInts = 1 + kVBX + kVBY + ((kVBX + kVBY + 1) & 1);  // window byte offset, columns, rows (even)
+static_assert(kVBX == kVPW * (kWaves / 4) && kVBY == 2 * kVYW && kWaves % 4 == 0, "geometry layout assumed below");
 
 // Fill the geometry of frames [f0, f0 + cnt) (one thread per entry).
 __device__ __forceinline__ void fill_geometry(const StackArgs& A, int* geo, int f0, int cnt, int a0, int b0, int X0,
@@ -343,25 +343,27 @@ constexpr int kC4 = kStageW / 4;  // float4 chunks per staged row
 static_assert(kC4 <= 32 && kLdsRows % (2 * kWaves) == 0, "two staged rows per wave instruction");
 constexpr int kStage = kLdsRows / (2 * kWaves);  // staging loads per thread and frame
 
-// Staging: wave w, load j covers staged row 2*(w + kWaves*j) + (lane >> 5),
-// float4 column lane & 31 (lanes with column >= kC4 idle).  The per-lane part
-// of the address is constant; the frame and j parts are scalar byte offsets.
-__device__ __forceinline__ void stage_load(__amdgpu_buffer_rsrc_t rsrc, int voff, int sbyte, int Wp, bool act,
-                                           f4 (&st)[kStage]) {
+// Staging: wave w, load j covers staged rows 2*(w + kWaves*j) and the next
+// one: lane l reads float4 column l & 31 of row 2*(w + kWaves*j) + (l >> 5),
+// lanes with column >= kC4 idle.  The LDS layout is lane-contiguous (32
+// float4 per 128-float row), so each load writes LDS directly (buffer load
+// with LDS destination: lane l's 16 bytes land at the wave's row base + 16 l)
+// and no register holds the window.  The per-lane part of the address is
+// constant; the frame and j parts are scalar byte offsets.
+__device__ __forceinline__ void stage_frame(__amdgpu_buffer_rsrc_t rsrc, int voff, int sbyte, int Wp, bool act,
+                                            float* buf, int wave) {
 #pragma unroll
     for (int j = 0; j < kStage; ++j) {
-        if (act)
-            st[j] = __builtin_bit_cast(
-                f4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, sbyte + j * 2 * kWaves * Wp * 4, 0));
+        if (act) {
+            auto* dst = (__attribute__((address_space(3))) void*)(buf + 2 * (wave + kWaves * j) * kLdsPitch);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, dst, 16, voff, sbyte + j * 2 * kWaves * Wp * 4, 0, 0);
+        }
     }
 }
 
-__device__ __forceinline__ void stage_store(float* buf, int loff, bool act, const f4 (&st)[kStage]) {
-#pragma unroll
-    for (int j = 0; j < kStage; ++j) {
-        if (act) *reinterpret_cast<f4*>(buf + loff + j * 2 * kWaves * kLdsPitch) = st[j];
-    }
-}
+// Wait until this wave's loads into LDS have landed (vmcnt 0; expcnt and
+// lgkmcnt not waited for); a barrier after it publishes them to the group.
+__device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // S/N, peak test and candidate output of one (tile, velocity) for one wave.
 // The wave holds rows 16h .. 16h + 15 (h = row half) of the tile, one column
@@ -621,13 +623,11 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
         const int scol = lane & 31;               // float4 column
         const bool act = scol < kC4;
         const int voff = (srow * A.Wp + 4 * scol) * 4;  // bytes, per lane
-        const int loff = srow * kLdsPitch + 4 * scol;   // floats, per lane
         // this wave's geometry of frame j: the LDS row offsets of its two y
         // velocities and the kVPW column offsets, plus the staging window
         // of frame j + 1
         const int gw_row = 1 + kVBX + kVYW * yp, gw_col = 1 + kVPW * xg;
         const int hoff = h * kRowsW * kLdsPitch;
-        f4 st[kStage];
         for (int f0 = 0; f0 < A.n; f0 += A.gchunk) {
             const int cnt = min(A.gchunk, A.n - f0);
             // (the previous chunk's last barrier has retired every read of
@@ -637,20 +637,21 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
             const auto rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)(A.pad + (long long)f0 * A.fstride), 0,
                                                                 (int)min(rem, 0x7FFFFFFFll), 0x00020000);
             __syncthreads();
-            stage_load(rsrc, voff, __builtin_amdgcn_readfirstlane(geo[0]), A.Wp, act, st);
-            stage_store(lds, loff, act, st);
+            stage_frame(rsrc, voff, __builtin_amdgcn_readfirstlane(geo[0]), A.Wp, act, lds, wave);
             int row0 = __builtin_amdgcn_readfirstlane(geo[gw_row]);
             int row1 = __builtin_amdgcn_readfirstlane(geo[gw_row + 1]);
             int col[kVPW];
 #pragma unroll
             for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(geo[gw_col + q]);
             int soff_next = __builtin_amdgcn_readfirstlane(geo[kGeomInts]);
+            stage_wait();
             __syncthreads();
             for (int j = 0; j < cnt; ++j) {
                 const float* buf = lds + (j & 1) * kLdsBuf + lane;
-                // staging of frame j + 1 (at the chunk's end a repeat of its
-                // last frame into the idle buffer, which nobody reads)
-                stage_load(rsrc, voff, soff_next, A.Wp, act, st);
+                // staging of frame j + 1 into the idle buffer, whose reads
+                // retired at the last barrier (at the chunk's end a repeat of
+                // its last frame, which nobody reads)
+                stage_frame(rsrc, voff, soff_next, A.Wp, act, lds + ((j + 1) & 1) * kLdsBuf, wave);
                 // the next frame's geometry (a few broadcast reads), then
                 // this frame's samples
                 const int* gn = geo + (j + 1) * kGeomInts;
@@ -679,7 +680,7 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
 #pragma unroll
                 for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(ncol[q]);
                 soff_next = __builtin_amdgcn_readfirstlane(nsoff);
-                stage_store(lds + ((j + 1) & 1) * kLdsBuf, loff, act, st);
+                stage_wait();
                 __syncthreads();
             }
         }
