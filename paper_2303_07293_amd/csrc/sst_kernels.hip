@@ -300,16 +300,19 @@ __device__ __forceinline__ int coverage(int xlo, int xhi, int ylo, int yhi, int&
 // window is the kStageW x kLdsRows region of the padded copy whose origin is
 // the 16-byte aligned column at or left of X0 + (smallest x shift of the
 // block) and the row Y0 + (smallest y shift).  Entry k holds frame f0 + k
-// for k < cnt and repeats the chunk's last frame for k = cnt, cnt + 1, so
-// that the frame loop reads entries j + 1 and j + 2 without bounds tests.
+// for k < cnt and repeats the chunk's last frame for the kGeomPad entries
+// after it, so that the frame loop reads entries up to j + 3 without bounds
+// tests.
 constexpr int kGeomInts = 1 + kVBX + kVBY + ((kVBX + kVBY + 1) & 1);  // window byte offset, columns, rows (even)
+constexpr int kGeomPad = 3;  // entries past a chunk's end (repeats of its last frame)
+constexpr int kNBuf = 3;     // staging buffers: frames j and j + 1 readable, j + 2 loading
 static_assert(kVBX == kVPW * (kWaves / 4) && kVBY == 2 * kVYW && kWaves % 4 == 0, "geometry layout assumed below");
 
 // Fill the geometry of frames [f0, f0 + cnt) (one thread per entry).
 __device__ __forceinline__ void fill_geometry(const StackArgs& A, int* geo, int f0, int cnt, int a0, int b0, int X0,
                                               int Y0) {
     const int t = threadIdx.x;
-    if (t < cnt + 2) {
+    if (t < cnt + kGeomPad) {
         const int k = min(t, cnt - 1);
         const int i = f0 + k;
         const int* rx = A.DX + (long long)i * A.ldx + a0;
@@ -580,6 +583,45 @@ __device__ __forceinline__ void accum_sep(const float* p0, const float* p1, cons
     }
 }
 
+// Pipelined form of the above: all kRowsW + kDMax staged rows of each x
+// velocity from the lower of the pair's two row offsets are read into v
+// one frame ahead, whatever d that frame has (for |d| > kDMax the values
+// are not used); the adds of a frame then only pick v[.][r] and v[.][r + D].
+constexpr int kRowsR = kRowsW + kDMax;
+
+__device__ __forceinline__ void read_rows(const float* p, const int (&col)[kVPW], float (&v)[kVPW][kRowsR]) {
+#pragma unroll
+    for (int q = 0; q < kVPW; ++q)
+#pragma unroll
+        for (int j = 0; j < kRowsR; ++j) v[q][j] = p[col[q] + j * kLdsPitch];
+}
+
+// Adds of one frame with read distance D (S0: which y velocity is upper),
+// interleaved with the reads of the next frame: as soon as the samples of
+// x velocity q are added, its registers receive the next frame's rows from
+// pn, so those reads are served while the wave adds the remaining sets.
+template <int D, int S0>
+__device__ __forceinline__ void add_pair_then_read(float (&v)[kVPW][kRowsR], float (&acc)[kVPW][kVYW][kRowsW],
+                                                   const float* pn, const int (&coln)[kVPW]) {
+#pragma unroll
+    for (int q = 0; q < kVPW; ++q) {
+#pragma unroll
+        for (int r = 0; r < kRowsW; ++r) {
+            acc[q][S0][r] += v[q][r];
+            acc[q][1 - S0][r] += v[q][r + D];
+        }
+#pragma unroll
+        for (int j = 0; j < kRowsR; ++j) v[q][j] = pn[coln[q] + j * kLdsPitch];
+    }
+}
+
+// Workgroup barrier that leaves LDS reads in flight.  Ordering is the
+// caller's: every wave waits for its own loads into LDS before it, and a
+// staging buffer is only refilled two frames after the adds that consumed
+// its reads.  The memory clobber keeps the compiler from moving memory
+// accesses across it.
+__device__ __forceinline__ void barrier_keep_reads() { asm volatile("s_barrier" ::: "memory"); }
+
 template <int V>
 using ic = std::integral_constant<int, V>;
 
@@ -589,9 +631,12 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
     // candidate column and the published boundary rows of every wave
     constexpr int kColFloats = kWaves * kColRows * kWave;
     constexpr int kXchFloats = kWaves * kVPW * kVYW * kWave;
-    constexpr int kLdsFloats = (2 * kLdsBuf > kColFloats + kXchFloats) ? 2 * kLdsBuf : kColFloats + kXchFloats;
+    // three staging buffers, plus the rows the unconditional read of the
+    // last buffer may run past its end
+    constexpr int kStageFloats = kNBuf * kLdsBuf + kDMax * kLdsPitch;
+    constexpr int kLdsFloats = (kStageFloats > kColFloats + kXchFloats) ? kStageFloats : kColFloats + kXchFloats;
     __shared__ __attribute__((aligned(16))) float lds[kLdsFloats];
-    __shared__ int geo[STAGED ? (kGeomChunk + 2) * kGeomInts : 1];
+    __shared__ int geo[STAGED ? (kGeomChunk + kGeomPad) * kGeomInts : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -630,58 +675,83 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
         const int hoff = h * kRowsW * kLdsPitch;
         for (int f0 = 0; f0 < A.n; f0 += A.gchunk) {
             const int cnt = min(A.gchunk, A.n - f0);
-            // (the previous chunk's last barrier has retired every read of
-            // the table and the staging buffers)
+            // (the previous chunk's last barrier follows every wave's last
+            // use of the table; its reads still in flight target staging
+            // rows whose values are never used)
             fill_geometry(A, geo, f0, cnt, a0, b0, X0, Y0);
             const long long rem = (long long)(A.n - f0) * A.fstride * 4;
             const auto rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)(A.pad + (long long)f0 * A.fstride), 0,
                                                                 (int)min(rem, 0x7FFFFFFFll), 0x00020000);
             __syncthreads();
+            // prologue: frames 0 and 1 of the chunk into buffers 0 and 1
             stage_frame(rsrc, voff, __builtin_amdgcn_readfirstlane(geo[0]), A.Wp, act, lds, wave);
-            int row0 = __builtin_amdgcn_readfirstlane(geo[gw_row]);
-            int row1 = __builtin_amdgcn_readfirstlane(geo[gw_row + 1]);
-            int col[kVPW];
+            stage_frame(rsrc, voff, __builtin_amdgcn_readfirstlane(geo[kGeomInts]), A.Wp, act, lds + kLdsBuf, wave);
+            // geometry of the frame being added (c), of the frame being read
+            // (n), and the window of the frame loaded next
+            int r0c = __builtin_amdgcn_readfirstlane(geo[gw_row]);
+            int r1c = __builtin_amdgcn_readfirstlane(geo[gw_row + 1]);
+            int colc[kVPW];
 #pragma unroll
-            for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(geo[gw_col + q]);
-            int soff_next = __builtin_amdgcn_readfirstlane(geo[kGeomInts]);
+            for (int q = 0; q < kVPW; ++q) colc[q] = __builtin_amdgcn_readfirstlane(geo[gw_col + q]);
+            int r0n = __builtin_amdgcn_readfirstlane(geo[kGeomInts + gw_row]);
+            int r1n = __builtin_amdgcn_readfirstlane(geo[kGeomInts + gw_row + 1]);
+            int coln[kVPW];
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q) coln[q] = __builtin_amdgcn_readfirstlane(geo[kGeomInts + gw_col + q]);
+            int soff2 = __builtin_amdgcn_readfirstlane(geo[2 * kGeomInts]);
             stage_wait();
             __syncthreads();
+            float v[kVPW][kRowsR];
+            read_rows(lds + min(r0c, r1c) + hoff + lane, colc, v);
+            int bc = 0;  // buffer of frame j; frame j + 1 is in (bc + 1) % 3, frame j + 2 goes to (bc + 2) % 3
             for (int j = 0; j < cnt; ++j) {
-                const float* buf = lds + (j & 1) * kLdsBuf + lane;
-                // staging of frame j + 1 into the idle buffer, whose reads
-                // retired at the last barrier (at the chunk's end a repeat of
-                // its last frame, which nobody reads)
-                stage_frame(rsrc, voff, soff_next, A.Wp, act, lds + ((j + 1) & 1) * kLdsBuf, wave);
-                // the next frame's geometry (a few broadcast reads), then
-                // this frame's samples
-                const int* gn = geo + (j + 1) * kGeomInts;
-                const int nrow0 = gn[gw_row], nrow1 = gn[gw_row + 1];
+                const int bn = bc == kNBuf - 1 ? 0 : bc + 1;
+                const int bl = bn == kNBuf - 1 ? 0 : bn + 1;
+                // load frame j + 2 into the buffer whose frame (j - 1) was
+                // consumed before the last barrier (past the chunk's end: a
+                // repeat of its last frame, never read)
+                stage_frame(rsrc, voff, soff2, A.Wp, act, lds + bl * kLdsBuf, wave);
+                // geometry of frame j + 2 and the window of frame j + 3
+                const int* g2 = geo + (j + 2) * kGeomInts;
+                const int nr0 = g2[gw_row], nr1 = g2[gw_row + 1];
                 int ncol[kVPW];
 #pragma unroll
-                for (int q = 0; q < kVPW; ++q) ncol[q] = gn[gw_col + q];
-                const int nsoff = gn[kGeomInts];
-                const int d = (row1 - row0) / kLdsPitch;
-                const float* pb = buf + min(row0, row1) + hoff;
-                // one block per read pattern, each updating the sums in place
-                // (a chain of two-way branches keeps every sum in one register)
-                if (d == 0) accum_pair<0, 0>(pb, col, acc);
-                if (d == 1) accum_pair<1, 0>(pb, col, acc);
-                if (d == 2) accum_pair<2, 0>(pb, col, acc);
-                if (d == 3) accum_pair<3, 0>(pb, col, acc);
-                if (d == 4) accum_pair<4, 0>(pb, col, acc);
-                if (d == -1) accum_pair<1, 1>(pb, col, acc);
-                if (d == -2) accum_pair<2, 1>(pb, col, acc);
-                if (d == -3) accum_pair<3, 1>(pb, col, acc);
-                if (d == -4) accum_pair<4, 1>(pb, col, acc);
-                if (d < -kDMax || d > kDMax) accum_sep(buf + row0 + hoff, buf + row1 + hoff, col, acc);
+                for (int q = 0; q < kVPW; ++q) ncol[q] = g2[gw_col + q];
+                const int nsoff = g2[kGeomInts];
+                // adds of frame j: one block per read pattern, each updating
+                // the sums in place (a chain of two-way branches keeps every
+                // sum in one register)
+                const int d = (r1c - r0c) / kLdsPitch;
+                const float* pn = lds + bn * kLdsBuf + min(r0n, r1n) + hoff + lane;
+                if (d == 0) add_pair_then_read<0, 0>(v, acc, pn, coln);
+                if (d == 1) add_pair_then_read<1, 0>(v, acc, pn, coln);
+                if (d == 2) add_pair_then_read<2, 0>(v, acc, pn, coln);
+                if (d == 3) add_pair_then_read<3, 0>(v, acc, pn, coln);
+                if (d == 4) add_pair_then_read<4, 0>(v, acc, pn, coln);
+                if (d == -1) add_pair_then_read<1, 1>(v, acc, pn, coln);
+                if (d == -2) add_pair_then_read<2, 1>(v, acc, pn, coln);
+                if (d == -3) add_pair_then_read<3, 1>(v, acc, pn, coln);
+                if (d == -4) add_pair_then_read<4, 1>(v, acc, pn, coln);
+                if (d < -kDMax || d > kDMax) {
+                    // rows too far apart to share: read both sets now (frame
+                    // j's buffer is still intact), then the next frame's rows
+                    const float* buf = lds + bc * kLdsBuf + lane;
+                    accum_sep(buf + r0c + hoff, buf + r1c + hoff, colc, acc);
+                    read_rows(pn, coln, v);
+                }
                 static_assert(kDMax == 4, "one case per shared-read distance");
-                row0 = __builtin_amdgcn_readfirstlane(nrow0);
-                row1 = __builtin_amdgcn_readfirstlane(nrow1);
+                r0c = r0n;
+                r1c = r1n;
 #pragma unroll
-                for (int q = 0; q < kVPW; ++q) col[q] = __builtin_amdgcn_readfirstlane(ncol[q]);
-                soff_next = __builtin_amdgcn_readfirstlane(nsoff);
+                for (int q = 0; q < kVPW; ++q) colc[q] = coln[q];
+                r0n = __builtin_amdgcn_readfirstlane(nr0);
+                r1n = __builtin_amdgcn_readfirstlane(nr1);
+#pragma unroll
+                for (int q = 0; q < kVPW; ++q) coln[q] = __builtin_amdgcn_readfirstlane(ncol[q]);
+                soff2 = __builtin_amdgcn_readfirstlane(nsoff);
+                bc = bn;
                 stage_wait();
-                __syncthreads();
+                barrier_keep_reads();
             }
         }
     } else {
