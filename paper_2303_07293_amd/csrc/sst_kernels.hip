@@ -583,36 +583,40 @@ __device__ __forceinline__ void accum_sep(const float* p0, const float* p1, cons
     }
 }
 
-// Pipelined form of the above: all kRowsW + kDMax staged rows of each x
-// velocity from the lower of the pair's two row offsets are read into v
-// one frame ahead, whatever d that frame has (for |d| > kDMax the values
-// are not used); the adds of a frame then only pick v[.][r] and v[.][r + D].
+// Pipelined form of the above.  For each x velocity all kRowsW + kDMax
+// staged rows from the lower of the pair's two row offsets are read,
+// whatever d the frame has (for |d| > kDMax the values are not used); the
+// adds of a frame then only pick v[.][r] and v[.][r + D].  The reads of a
+// frame are staggered: those of its first x velocity are issued before the
+// previous barrier, the second's before its adds start and the third's
+// after the first velocity's adds, so that a wave has at most about 14 LDS
+// operations in flight and each wait covers one velocity's rows.
 constexpr int kRowsR = kRowsW + kDMax;
 
-__device__ __forceinline__ void read_rows(const float* p, const int (&col)[kVPW], float (&v)[kVPW][kRowsR]) {
+__device__ __forceinline__ void read_rows_q(const float* p, int col, float (&vq)[kRowsR]) {
 #pragma unroll
-    for (int q = 0; q < kVPW; ++q)
-#pragma unroll
-        for (int j = 0; j < kRowsR; ++j) v[q][j] = p[col[q] + j * kLdsPitch];
+    for (int j = 0; j < kRowsR; ++j) vq[j] = p[col + j * kLdsPitch];
 }
 
-// Adds of one frame with read distance D (S0: which y velocity is upper),
-// interleaved with the reads of the next frame: as soon as the samples of
-// x velocity q are added, its registers receive the next frame's rows from
-// pn, so those reads are served while the wave adds the remaining sets.
 template <int D, int S0>
-__device__ __forceinline__ void add_pair_then_read(float (&v)[kVPW][kRowsR], float (&acc)[kVPW][kVYW][kRowsW],
-                                                   const float* pn, const int (&coln)[kVPW]) {
+__device__ __forceinline__ void add_rows_q(const float (&vq)[kRowsR], float (&aq)[kVYW][kRowsW]) {
 #pragma unroll
-    for (int q = 0; q < kVPW; ++q) {
-#pragma unroll
-        for (int r = 0; r < kRowsW; ++r) {
-            acc[q][S0][r] += v[q][r];
-            acc[q][1 - S0][r] += v[q][r + D];
-        }
-#pragma unroll
-        for (int j = 0; j < kRowsR; ++j) v[q][j] = pn[coln[q] + j * kLdsPitch];
+    for (int r = 0; r < kRowsW; ++r) {
+        aq[S0][r] += vq[r];
+        aq[1 - S0][r] += vq[r + D];
     }
+}
+
+// The adds of one frame (read distance D, S0 the upper y velocity), with
+// the third x velocity's rows read from p after the first one's adds.
+template <int D, int S0>
+__device__ __forceinline__ void add_frame(float (&v)[kVPW][kRowsR], float (&acc)[kVPW][kVYW][kRowsW],
+                                          const float* p, int col2) {
+    static_assert(kVPW == 3, "three x velocities per wave");
+    add_rows_q<D, S0>(v[0], acc[0]);
+    read_rows_q(p, col2, v[2]);
+    add_rows_q<D, S0>(v[1], acc[1]);
+    add_rows_q<D, S0>(v[2], acc[2]);
 }
 
 // Workgroup barrier that leaves LDS reads in flight.  Ordering is the
@@ -702,7 +706,7 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
             stage_wait();
             __syncthreads();
             float v[kVPW][kRowsR];
-            read_rows(lds + min(r0c, r1c) + hoff + lane, colc, v);
+            read_rows_q(lds + min(r0c, r1c) + hoff + lane, colc[0], v[0]);
             int bc = 0;  // buffer of frame j; frame j + 1 is in (bc + 1) % 3, frame j + 2 goes to (bc + 2) % 3
             for (int j = 0; j < cnt; ++j) {
                 const int bn = bc == kNBuf - 1 ? 0 : bc + 1;
@@ -718,28 +722,31 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
 #pragma unroll
                 for (int q = 0; q < kVPW; ++q) ncol[q] = g2[gw_col + q];
                 const int nsoff = g2[kGeomInts];
-                // adds of frame j: one block per read pattern, each updating
-                // the sums in place (a chain of two-way branches keeps every
-                // sum in one register)
+                // frame j: the second x velocity's rows, then the adds, one
+                // block per read pattern, each updating the sums in place (a
+                // chain of two-way branches keeps every sum in one register)
+                const float* pc = lds + bc * kLdsBuf + min(r0c, r1c) + hoff + lane;
+                read_rows_q(pc, colc[1], v[1]);
                 const int d = (r1c - r0c) / kLdsPitch;
-                const float* pn = lds + bn * kLdsBuf + min(r0n, r1n) + hoff + lane;
-                if (d == 0) add_pair_then_read<0, 0>(v, acc, pn, coln);
-                if (d == 1) add_pair_then_read<1, 0>(v, acc, pn, coln);
-                if (d == 2) add_pair_then_read<2, 0>(v, acc, pn, coln);
-                if (d == 3) add_pair_then_read<3, 0>(v, acc, pn, coln);
-                if (d == 4) add_pair_then_read<4, 0>(v, acc, pn, coln);
-                if (d == -1) add_pair_then_read<1, 1>(v, acc, pn, coln);
-                if (d == -2) add_pair_then_read<2, 1>(v, acc, pn, coln);
-                if (d == -3) add_pair_then_read<3, 1>(v, acc, pn, coln);
-                if (d == -4) add_pair_then_read<4, 1>(v, acc, pn, coln);
+                if (d == 0) add_frame<0, 0>(v, acc, pc, colc[2]);
+                if (d == 1) add_frame<1, 0>(v, acc, pc, colc[2]);
+                if (d == 2) add_frame<2, 0>(v, acc, pc, colc[2]);
+                if (d == 3) add_frame<3, 0>(v, acc, pc, colc[2]);
+                if (d == 4) add_frame<4, 0>(v, acc, pc, colc[2]);
+                if (d == -1) add_frame<1, 1>(v, acc, pc, colc[2]);
+                if (d == -2) add_frame<2, 1>(v, acc, pc, colc[2]);
+                if (d == -3) add_frame<3, 1>(v, acc, pc, colc[2]);
+                if (d == -4) add_frame<4, 1>(v, acc, pc, colc[2]);
                 if (d < -kDMax || d > kDMax) {
-                    // rows too far apart to share: read both sets now (frame
-                    // j's buffer is still intact), then the next frame's rows
+                    // rows too far apart to share: read both sets (frame j's
+                    // buffer stays intact until frame j + 3 loads into it)
                     const float* buf = lds + bc * kLdsBuf + lane;
                     accum_sep(buf + r0c + hoff, buf + r1c + hoff, colc, acc);
-                    read_rows(pn, coln, v);
                 }
                 static_assert(kDMax == 4, "one case per shared-read distance");
+                // the first x velocity's rows of frame j + 1, in flight
+                // across the barrier
+                read_rows_q(lds + bn * kLdsBuf + min(r0n, r1n) + hoff + lane, coln[0], v[0]);
                 r0c = r0n;
                 r1c = r1n;
 #pragma unroll
