@@ -103,7 +103,7 @@ struct Plan {
     int op = 0;
     int n = 0, h = 0, w = 0;
     int nvx = 0, nvy = 0, ldx = 0, ldy = 0, nvbx = 0, nvby = 0;
-    int halo = 0, step_x = 0, step_y = 0, tiles_x = 0, tiles_y = 0, ntiles = 0, nslot = 0;
+    int step_x = 0, step_y = 0, tiles_x = 0, tiles_y = 0, ntiles = 0, nslot = 0;
     int padL = 0, padT = 0, Wp = 0, Hp = 0;
     bool staged = true;
     int kt = 0, rows_per_chunk = 0, nchunk = 0;
@@ -156,9 +156,10 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
     if ((rc = build_table(t, n, t_ref, vx, nvx, p.ldx, w, p.DX, "vx"))) return rc;
     if ((rc = build_table(t, n, t_ref, vy, nvy, p.ldy, h, p.DY, "vy"))) return rc;
 
-    p.halo = detect ? 1 : 0;
-    p.step_x = kTileW - 2 * p.halo;
-    p.step_y = kRows - 2 * p.halo;
+    // tiles do not overlap (the peak test of a tile's border pixels
+    // evaluates their outside neighbours directly)
+    p.step_x = kTileW;
+    p.step_y = kRows;
     p.tiles_x = ceil_div(w, p.step_x);
     p.tiles_y = ceil_div(h, p.step_y);
     p.ntiles = p.tiles_x * p.tiles_y;
@@ -183,10 +184,10 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
     }
     p.staged = sx <= kSMaxX && sy <= kSMaxY;
     // zero padding so that every staged or direct read stays inside the copy
-    const int X0max = (p.tiles_x - 1) * p.step_x - p.halo;
-    const int Y0max = (p.tiles_y - 1) * p.step_y - p.halo;
-    p.padL = (int)align_up((size_t)std::max(0, p.halo - dxmin), 4);
-    p.padT = std::max(0, p.halo - dymin);
+    const int X0max = (p.tiles_x - 1) * p.step_x;
+    const int Y0max = (p.tiles_y - 1) * p.step_y;
+    p.padL = (int)align_up((size_t)std::max(0, -dxmin), 4);
+    p.padT = std::max(0, -dymin);
     // the staged window is kLdsPitch x kLdsRows from the block's smallest
     // shift (aligned down by up to 3 columns), the direct path reads up to the
     // largest shift plus the tile
@@ -284,7 +285,6 @@ StackArgs stack_args(const Plan& p, void* ws) {
     a.tiles_y = p.tiles_y;
     a.step_x = p.step_x;
     a.step_y = p.step_y;
-    a.halo = p.halo;
     a.nvbx = p.nvbx;
     a.vby0 = 0;
     a.nvby = p.nvby;

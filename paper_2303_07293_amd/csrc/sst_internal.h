@@ -95,7 +95,7 @@ struct StackArgs {
     const int* IY;    // [nvy][h][2]
     const double* P;  // [n+1] prefix sums of the frame variances
     int gchunk;     // frames per geometry chunk (their padded frames span < 2^31 bytes)
-    int tiles_x, tiles_y, step_x, step_y, halo;
+    int tiles_x, tiles_y, step_x, step_y;
     int nvbx;        // velocity blocks along x
     int vby0, nvby;  // velocity-block rows handled by this launch
     // plain stack

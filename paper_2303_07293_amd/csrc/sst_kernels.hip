@@ -369,17 +369,23 @@ __device__ __forceinline__ void stage_frame(__amdgpu_buffer_rsrc_t rsrc, int vof
 __device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // S/N, peak test and candidate output of one (tile, velocity) for one wave.
-// The wave holds rows 16h .. 16h + 15 (h = row half) of the tile, one column
-// per lane.  Tile rows 0 and kRows - 1 and lanes 0 and 63 are the 1-pixel
-// halo: their S/N is only compared with.  The peak test of the wave's rows
-// next to the other half needs that half's boundary row, which every wave
-// publishes in LDS after the frame loop.  The candidate search works on a
-// column of kColRows rows, tile rows R0 .. R0 + 16 with R0 = 15h: the wave's
-// own 16 rows and the neighbouring half's boundary row; its rows 1 .. 15 are
-// the ones it may emit.  The S/N of a row is recomputed where it is needed
-// rather than stored, to keep the register footprint of this epilogue below
-// the main loop's.
-constexpr int kColRows = kRowsW + 1;
+// Tiles do not overlap: the wave holds rows 16h .. 16h + 15 (h = row half)
+// of the tile, one column per lane, and may emit any of them.  The peak test
+// of the wave's rows next to the other half needs that half's boundary row,
+// which every wave publishes in LDS after the frame loop.  The candidate
+// search works on a column of kColRows rows, tile rows R0 .. R0 + 17 with
+// R0 = 16h - 1: the wave's own 16 rows (column rows 1 .. 16), the other
+// half's boundary row and, on the tile's outer side, the row of the next
+// tile, which this workgroup does not hold.  Neighbours outside the tile
+// (that row, and the columns left of lane 0 and right of lane 63) first
+// count as -infinity; a pixel that passes the test against everything
+// inside the tile then has its outside neighbours' S/N evaluated directly,
+// a sum over the frames of the padded copy in frame order: the same float32
+// adds of the same values as the workgroup that owns that pixel, hence the
+// same S/N.  The S/N of a row is recomputed where it is needed rather than
+// stored, to keep the register footprint of this epilogue below the main
+// loop's.
+constexpr int kColRows = kRowsW + 2;
 constexpr unsigned kEmitRows = ((1u << (kColRows - 1)) - 1u) & ~1u;  // column rows 1 .. kColRows - 2
 
 struct SnCtx {
@@ -388,6 +394,11 @@ struct SnCtx {
     const double* P;   // prefix sums of the frame variances
     int n, xlo, xhi;
     bool xfull;        // this lane's column sees every frame in x
+    // direct evaluation of pixels outside the tile
+    const float* pad;
+    const int *DX, *DY, *IX, *IY;
+    long long fstride;
+    int Wp, padL, padT, ldx, ldy, w, h, a, b;
 };
 
 // S/N of column row r of this lane (and its coverage).  A lane whose x
@@ -407,6 +418,24 @@ __device__ __forceinline__ float sn_row(const SnCtx& c, float acc, int r, int& c
     return V > 0.0 ? acc * rsqrtf((float)V) : 0.f;
 }
 
+// S/N of pixel (x, y) evaluated on its own: the frame-ordered sum of its
+// shifted samples of the padded copy, then the same normalisation as sn_row.
+__device__ __noinline__ float sn_direct(const SnCtx& c, int x, int y) {
+    if (x < 0 || x >= c.w || y < 0 || y >= c.h) return -INFINITY;
+    int xlo, xhi, ylo, yhi, lo, hi;
+    load_iv(c.IX, (long long)c.a * c.w + x, xlo, xhi);
+    load_iv(c.IY, (long long)c.b * c.h + y, ylo, yhi);
+    if (coverage(xlo, xhi, ylo, yhi, lo, hi) <= 0) return -INFINITY;
+    float acc = 0.f;
+#pragma unroll 1
+    for (int i = 0; i < c.n; ++i) {
+        const int dx = c.DX[(long long)i * c.ldx + c.a], dy = c.DY[(long long)i * c.ldy + c.b];
+        acc += c.pad[(long long)i * c.fstride + (long long)(y + dy + c.padT) * c.Wp + (x + dx + c.padL)];
+    }
+    const double V = c.P[hi + 1] - c.P[lo];
+    return V > 0.0 ? acc * rsqrtf((float)V) : 0.f;
+}
+
 // Where a (tile, velocity) writes its kept candidates.
 struct CandOut {
     int32_t* tcount;
@@ -417,21 +446,34 @@ struct CandOut {
 
 // Peak test and candidate output for one (tile, velocity, row half) whose
 // column sums are parked in LDS: col[r * 64 + lane] = S' of column row r.
-// fl marks the rows (1 .. kColRows - 2) that pass threshold and coverage.
+// fl marks the rows (1 .. kColRows - 2) that pass threshold and coverage;
+// orow is the column row outside the tile (0 or kColRows - 1).
 __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut o, const float* col, unsigned fl,
-                                                    int lane, int x, int Yc) {
+                                                    int lane, int x, int Yc, int orow) {
     const int kt = o.kt;
     // 8-neighbour test with the raster tie rule: neighbours earlier in raster
-    // order must be strictly smaller, later ones may tie.
+    // order must be strictly smaller, later ones may tie.  Outside the tile:
+    // -infinity for now.
+    auto sn_col = [&](int r) __attribute__((always_inline)) {
+        int cv;
+        return r == orow ? -INFINITY : sn_row(c, col[r * kWave + lane], r, cv);
+    };
+    auto left = [&](float v) __attribute__((always_inline)) {
+        const float t = __shfl_up(v, 1);
+        return lane == 0 ? -INFINITY : t;
+    };
+    auto right = [&](float v) __attribute__((always_inline)) {
+        const float t = __shfl_down(v, 1);
+        return lane == kWave - 1 ? -INFINITY : t;
+    };
     unsigned cm = 0;
-    int cv;
-    float Sm = sn_row(c, col[lane], 0, cv), S0 = sn_row(c, col[kWave + lane], 1, cv);
-    float Lm = __shfl_up(Sm, 1), Rm = __shfl_down(Sm, 1);
-    float L0 = __shfl_up(S0, 1), R0 = __shfl_down(S0, 1);
+    float Sm = sn_col(0), S0 = sn_col(1);
+    float Lm = left(Sm), Rm = right(Sm);
+    float L0 = left(S0), R0 = right(S0);
 #pragma unroll 1
     for (int r = 1; r <= kColRows - 2; ++r) {
-        const float Sp = sn_row(c, col[(r + 1) * kWave + lane], r + 1, cv);
-        const float Lp = __shfl_up(Sp, 1), Rp = __shfl_down(Sp, 1);
+        const float Sp = sn_col(r + 1);
+        const float Lp = left(Sp), Rp = right(Sp);
         if ((fl >> r) & 1u) {
             const float s = S0;
             const bool ok = s > Lm && s > Sm && s > Rm && s > L0 && s >= R0 && s >= Lp && s >= Sp && s >= Rp;
@@ -443,6 +485,27 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut
         Rm = R0;
         L0 = Lp;
         R0 = Rp;
+    }
+    // pixels next to the tile's border: test the outside neighbours
+    const int erow = orow == 0 ? 1 : kColRows - 2;  // the own row next to the outside row
+    unsigned todo = cm & ((lane == 0 || lane == kWave - 1) ? kEmitRows : (1u << erow));
+#pragma unroll 1
+    while (todo != 0) {
+        const int r = __builtin_ctz(todo);
+        todo &= todo - 1;
+        int cv;
+        const float s = sn_row(c, col[r * kWave + lane], r, cv);
+        bool ok = true;
+#pragma unroll 1
+        for (int k = 0; k < 9 && ok; ++k) {
+            const int dy = k / 3 - 1, dx = k % 3 - 1;
+            const bool outside = lane + dx < 0 || lane + dx >= kWave || r + dy == orow;
+            if (k == 4 || !outside) continue;
+            const float sq = sn_direct(c, x + dx, Yc + r + dy);
+            const bool earlier = dy < 0 || (dy == 0 && dx < 0);
+            ok = earlier ? s > sq : s >= sq;
+        }
+        if (!ok) cm &= ~(1u << r);
     }
     const int total = wave_sum_i32(__popc(cm));
     if (lane == 0) o.tcount[o.slot] = total;
@@ -462,14 +525,14 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut
         return;
     }
     // more candidates than kept entries: keep the kt best keys
-    unsigned left = cm;
+    unsigned left_rows = cm;
 #pragma unroll 1
     for (int k = 0; k < kt; ++k) {
         unsigned long long best = 0;
         int bestr = -1;
 #pragma unroll 1
         for (int r = 1; r <= kColRows - 2; ++r) {
-            if ((left >> r) & 1u) {
+            if ((left_rows >> r) & 1u) {
                 int cov;
                 const unsigned long long key = cand_key(sn_row(c, col[r * kWave + lane], r, cov), (Yc + r) * o.w + x);
                 if (key > best) {
@@ -483,7 +546,7 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut
             int cov;
             const float v = col[bestr * kWave + lane];
             E[k] = Entry{sn_row(c, v, bestr, cov), v, (Yc + bestr) * o.w + x, cov};
-            left &= ~(1u << bestr);
+            left_rows &= ~(1u << bestr);
         }
     }
 }
@@ -497,7 +560,6 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
                                                 const float (&rsm)[kRowsW], int a, int b, int x, bool xin, int lane,
                                                 int h, int Y0, int tile, float* col, const float* xrow,
                                                 const int* IYr, const float* RSr, const double* P, int xlo, int xhi) {
-    const bool lane_emit = lane >= 1 && lane <= kWave - 2 && xin;
     const long long kc = (long long)(b - A.vby0 * kVBY) * A.nvx + a;
     SnCtx c;
     c.IYr = IYr;
@@ -508,23 +570,23 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
     c.xhi = xhi;
     c.xfull = xlo == 0 && xhi == A.n - 1;
     unsigned fl = 0;  // bit r: the wave's row r passes threshold and coverage
-    if (c.xfull && lane_emit) {
+    if (c.xfull && xin) {
 #pragma unroll
         for (int r = 0; r < kRowsW; ++r)
             if (acc[r] * rsm[r] > A.thr) fl |= 1u << r;
     }
-    if (__ballot(!c.xfull && lane_emit) != 0) {
+    if (__ballot(!c.xfull && xin) != 0) {
         // lanes near the frame's x edges: combine both coverage intervals
-        if (!c.xfull && lane_emit) {
+        if (!c.xfull && xin) {
 #pragma unroll
             for (int r = 0; r < kRowsW; ++r) {
                 int cov;
-                const float s = sn_row(c, acc[r], r + h, cov);
+                const float s = sn_row(c, acc[r], r + 1, cov);
                 if (cov >= A.cmin && s > A.thr) fl |= 1u << r;
             }
         }
     }
-    fl = (fl << h) & kEmitRows;  // the wave's row r is column row r + h
+    fl <<= 1;  // the wave's row r is column row r + 1
     CandOut o;
     o.tcount = A.tcount;
     o.ent = A.ent;
@@ -538,11 +600,26 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
     // Rare path (some pixel of this wave's column block clears the
     // threshold): park the sums in this wave's LDS slot and work from there
     // with runtime row loops, which keeps this code's register use small.
-    float* own = col + h * kWave;
+    float* own = col + kWave;
 #pragma unroll
     for (int r = 0; r < kRowsW; ++r) own[r * kWave + lane] = acc[r];
     col[(h ? 0 : kColRows - 1) * kWave + lane] = xrow[lane];
-    candidates_from_column(c, o, col, fl, lane, x, Y0 + (kRowsW - 1) * h);
+    c.pad = A.pad;
+    c.DX = A.DX;
+    c.DY = A.DY;
+    c.IX = A.IX;
+    c.IY = A.IY;
+    c.fstride = A.fstride;
+    c.Wp = A.Wp;
+    c.padL = A.padL;
+    c.padT = A.padT;
+    c.ldx = A.ldx;
+    c.ldy = A.ldy;
+    c.w = A.w;
+    c.h = A.h;
+    c.a = a;
+    c.b = b;
+    candidates_from_column(c, o, col, fl, lane, x, Y0 + kRowsW * h - 1, h ? kColRows - 1 : 0);
 }
 
 // One frame's samples for a wave whose two y velocities sample rows D apart
@@ -656,8 +733,8 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
     const int h = wave % 2;           // row half
     const int aw = a0 + kVPW * xg;    // this wave's first x velocity
     const int bw = b0 + kVYW * yp;    // this wave's first y velocity
-    const int X0 = tx * A.step_x - A.halo;
-    const int Y0 = ty * A.step_y - A.halo;
+    const int X0 = tx * kTileW;
+    const int Y0 = ty * kRows;
 
     float acc[kVPW][kVYW][kRowsW];
 #pragma unroll
@@ -788,8 +865,12 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
     // Coverage tables for the epilogue, staged once per workgroup: the y
     // intervals of the block's velocity rows over the tile's rows, the
     // variance prefix (when it fits) and each lane's x intervals.
-    __shared__ int sIY[kVBY * kRows * 2];
-    __shared__ float sRS[DETECT ? kVBY * kRows : 1];
+    // (sIY and sRS have one row before tile row 0 of the first velocity
+    // row, so that a column starting at tile row -1 has a valid base)
+    __shared__ int sIYa[(kVBY * kRows + 1) * 2];
+    __shared__ float sRSa[DETECT ? kVBY * kRows + 1 : 2];
+    int* const sIY = sIYa + 2;
+    float* const sRS = sRSa + 1;
     __shared__ __attribute__((aligned(16))) float sRM[DETECT ? kVBY * kRows : 4];
     __shared__ double sP[DETECT ? kPLds : 1];
     const bool need_c = DETECT || A.mean || A.cov != nullptr;
@@ -874,7 +955,7 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
         // registers: the epilogue is too large for the unroller to replicate
         float* col = lds + wave * (kColRows * kWave);
         const float* xin_rows = lds + kColFloats + (wave ^ 1) * (kVPW * kVYW * kWave);
-        const int R0 = (kRowsW - 1) * h;
+        const int R0 = kRowsW * h - 1;
         auto one = [&](auto qc, auto sc, const double* P) __attribute__((always_inline)) {
             constexpr int q = decltype(qc)::value, s = decltype(sc)::value;
             const int bb = bw + s;

@@ -19,5 +19,8 @@ from .fields import (  # noqa: F401
     pure_noise,
     render_movers,
     small_case,
+    tile_border_case,
+    BORDER_PEAKS,
+    BORDER_TIES,
     SEED_BASE,
 )

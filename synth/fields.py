@@ -254,3 +254,29 @@ def small_case(seed: int, n: int, h: int, w: int, nvx: int, nvy: int,
     frames = _frames(rng, t, t_ref, h, w, sky, sigma, movers)
     return Field(f"small{seed} {n}x{h}x{w} grid{nvx}x{nvy}", frames, t, float(t_ref), vx, vy,
                  threshold=3.0, min_coverage=0, k_max=8, movers=movers, sky=sky, sigma=sigma)
+
+
+# Pixels of the tile-border case: single bright pixels on the borders between
+# 64 x 32 pixel tiles, and pairs of neighbours across a border given equal
+# values in every frame (the first of each pair is the earlier in raster
+# order).
+BORDER_PEAKS = [(63, 10), (64, 20), (10, 31), (20, 32), (64, 32), (127, 5), (128, 64), (0, 0), (139, 69),
+                (0, 45)]
+BORDER_TIES = [((63, 40), (64, 40)), ((50, 31), (50, 32)), ((127, 31), (128, 32)), ((100, 63), (99, 64))]
+
+
+def tile_border_case(seed: int = 0) -> Field:
+    """6 frames of 70 x 140 N(0, 1) noise with stationary bright pixels
+    (amplitude 40) at BORDER_PEAKS and equal-valued pairs at BORDER_TIES;
+    velocities (0, 1.5, -2) x (0, 1) px/h, timestamps 0.5 h apart."""
+    rng = np.random.default_rng(SEED_BASE + 500 + seed)
+    n, h, w = 6, 70, 140
+    t = np.arange(n, dtype=np.float64) * 0.5
+    frames = rng.normal(0.0, 1.0, size=(n, h, w)).astype(np.float32)
+    for x, y in BORDER_PEAKS:
+        frames[:, y, x] += np.float32(40.0)
+    for (x1, y1), (x2, y2) in BORDER_TIES:
+        frames[:, y1, x1] += np.float32(40.0)
+        frames[:, y2, x2] = frames[:, y1, x1]
+    return Field(f"tile-borders{seed} {n}x{h}x{w}", frames, t, 0.0, np.array([0.0, 1.5, -2.0]),
+                 np.array([0.0, 1.0]), threshold=5.0, min_coverage=0, k_max=32)

@@ -193,6 +193,24 @@ def test_detect_constant_frames(sst):
     assert int(count.cpu()[0]) == 1 and (g["x"][0], g["y"][0]) == (0, 0) and g["snr"][0] == 0.0
 
 
+def test_detect_tile_borders(sst):
+    """Peaks on the borders between tiles and in the image corners, and
+    equal-valued neighbours across a border: the border pixels' outside
+    neighbours are evaluated directly, and the raster tie rule must keep
+    exactly the earlier pixel of each pair."""
+    f = synth.tile_border_case()
+    _say(f"case {f.name}")
+    # each exact tie makes both pixels' decisions marginal for the
+    # tolerance-based comparison; the exact check follows
+    got, cnt = _check_detect(sst, f, f.threshold, f.min_coverage, f.k_max, max_marginal=2 * len(synth.BORDER_TIES) + 2)
+    g = got[0][: int(cnt[0])]  # velocity (0, 0)
+    found = set(zip(g["x"].tolist(), g["y"].tolist()))
+    for p in synth.BORDER_PEAKS:
+        assert p in found, p
+    for first, second in synth.BORDER_TIES:
+        assert first in found and second not in found, (first, second)
+
+
 def test_detect_repeatable_bitwise(sst):
     f = synth.small_case(30, 10, 90, 150, 6, 4, vmax=3.0, sky=10.0)
     fr = _dev(f.frames)

@@ -219,6 +219,22 @@ def test_brute_force_covers_exact_ties():
             assert np.array_equal(cov[b, a], np.array(bf[b][a][1]))
 
 
+def test_raster_tie_rule_on_planted_pairs():
+    """Isolated bright pixels are candidates; of two equal neighbours (equal
+    values in every frame) only the one earlier in raster order is (Sec. 2.1
+    peak rule as read here: earlier neighbours strictly smaller, later ones
+    may tie).  The pairs sit across tile borders so that the GPU test of the
+    same case covers the border evaluation."""
+    f = synth.tile_border_case()
+    ref = oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, velocities=[0])
+    c, n = ref[0]["cand"], int(ref[0]["count"])
+    found = set(zip(np.asarray(c["x"])[:n].tolist(), np.asarray(c["y"])[:n].tolist()))
+    for p in synth.BORDER_PEAKS:
+        assert p in found, p
+    for first, second in synth.BORDER_TIES:
+        assert first in found and second not in found, (first, second)
+
+
 # ------------------------------------------------------ O3 zero velocity --
 def pin_zero_velocity():
     rng = np.random.default_rng(11)
