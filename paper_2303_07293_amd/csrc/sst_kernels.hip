@@ -735,6 +735,9 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
     const int bw = b0 + kVYW * yp;    // this wave's first y velocity
     const int X0 = tx * kTileW;
     const int Y0 = ty * kRows;
+    // waves whose velocities all lie past the grid (in a partial last block)
+    // only help stage the frames
+    const bool busy = aw < A.nvx && bw < A.nvy;
 
     float acc[kVPW][kVYW][kRowsW];
 #pragma unroll
@@ -782,6 +785,18 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
             int soff2 = __builtin_amdgcn_readfirstlane(geo[2 * kGeomInts]);
             stage_wait();
             __syncthreads();
+            if (!busy) {
+                // the same staging loads and barriers as below, no adds
+                int bl = 2;
+                for (int j = 0; j < cnt; ++j) {
+                    stage_frame(rsrc, voff, soff2, A.Wp, act, lds + bl * kLdsBuf, wave);
+                    soff2 = __builtin_amdgcn_readfirstlane(geo[(j + 3) * kGeomInts]);
+                    bl = bl == kNBuf - 1 ? 0 : bl + 1;
+                    stage_wait();
+                    barrier_keep_reads();
+                }
+                continue;
+            }
             float v[kVPW][kRowsR];
             read_rows_q(lds + min(r0c, r1c) + hoff + lane, colc[0], v[0]);
             int bc = 0;  // buffer of frame j; frame j + 1 is in (bc + 1) % 3, frame j + 2 goes to (bc + 2) % 3
