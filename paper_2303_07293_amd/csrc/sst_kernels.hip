@@ -394,12 +394,11 @@ struct SnCtx {
     const double* P;   // prefix sums of the frame variances
     int n, xlo, xhi;
     bool xfull;        // this lane's column sees every frame in x
-    // direct evaluation of pixels outside the tile
-    const float* pad;
-    const int *DX, *DY, *IX, *IY;
-    long long fstride;
-    int Wp, padL, padT, ldx, ldy, w, h, a, b;
 };
+
+// The kernel's arguments where they were passed (the kernel argument
+// segment): a callee reads them there instead of from a copy.
+typedef const __attribute__((address_space(4))) StackArgs* KArgs;
 
 // S/N of column row r of this lane (and its coverage).  A lane whose x
 // samples are all inside has coverage = the row's y interval, whose 1/sqrt(V)
@@ -418,39 +417,49 @@ __device__ __forceinline__ float sn_row(const SnCtx& c, float acc, int r, int& c
     return V > 0.0 ? acc * rsqrtf((float)V) : 0.f;
 }
 
-// S/N of pixel (x, y) evaluated on its own: the frame-ordered sum of its
-// shifted samples of the padded copy, then the same normalisation as sn_row.
-__device__ __noinline__ float sn_direct(const SnCtx& c, int x, int y) {
-    if (x < 0 || x >= c.w || y < 0 || y >= c.h) return -INFINITY;
+// S/N of pixel (x, y) at velocity (a, b) evaluated on its own: the
+// frame-ordered sum of its shifted samples of the padded copy, then the same
+// normalisation as sn_row.
+__device__ __forceinline__ float sn_direct(KArgs A, const double* P, int a, int b, int x, int y) {
+    if (x < 0 || x >= A->w || y < 0 || y >= A->h) return -INFINITY;
     int xlo, xhi, ylo, yhi, lo, hi;
-    load_iv(c.IX, (long long)c.a * c.w + x, xlo, xhi);
-    load_iv(c.IY, (long long)c.b * c.h + y, ylo, yhi);
+    load_iv(A->IX, (long long)a * A->w + x, xlo, xhi);
+    load_iv(A->IY, (long long)b * A->h + y, ylo, yhi);
     if (coverage(xlo, xhi, ylo, yhi, lo, hi) <= 0) return -INFINITY;
+    const float* pad = A->pad;
+    const int* DX = A->DX;
+    const int* DY = A->DY;
+    const long long fstride = A->fstride;
+    const int Wp = A->Wp, ldx = A->ldx, ldy = A->ldy, n = A->n;
+    const int x0 = x + A->padL, y0 = y + A->padT;
     float acc = 0.f;
 #pragma unroll 1
-    for (int i = 0; i < c.n; ++i) {
-        const int dx = c.DX[(long long)i * c.ldx + c.a], dy = c.DY[(long long)i * c.ldy + c.b];
-        acc += c.pad[(long long)i * c.fstride + (long long)(y + dy + c.padT) * c.Wp + (x + dx + c.padL)];
+    for (int i = 0; i < n; ++i) {
+        const int dx = DX[(long long)i * ldx + a], dy = DY[(long long)i * ldy + b];
+        acc += pad[(long long)i * fstride + (long long)(y0 + dy) * Wp + (x0 + dx)];
     }
-    const double V = c.P[hi + 1] - c.P[lo];
+    const double V = P[hi + 1] - P[lo];
     return V > 0.0 ? acc * rsqrtf((float)V) : 0.f;
 }
-
-// Where a (tile, velocity) writes its kept candidates.
-struct CandOut {
-    int32_t* tcount;
-    Entry* ent;
-    long long slot;  // (velocity of this launch) * nslot + 2 * tile + row half
-    int kt, w;
-};
 
 // Peak test and candidate output for one (tile, velocity, row half) whose
 // column sums are parked in LDS: col[r * 64 + lane] = S' of column row r.
 // fl marks the rows (1 .. kColRows - 2) that pass threshold and coverage;
-// orow is the column row outside the tile (0 or kColRows - 1).
-__device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut o, const float* col, unsigned fl,
-                                                    int lane, int x, int Yc, int orow) {
-    const int kt = o.kt;
+// orow is the column row outside the tile (0 or kColRows - 1).  The
+// (tile, velocity, row half) writes its count and kept entries to slot.
+__device__ __noinline__ void candidates_from_column(KArgs A, const int* IYr, const float* RSr, const double* P,
+                                                    int xlo, int xhi, int a, int b, long long slot,
+                                                    const float* col, unsigned fl, int lane, int x, int Yc,
+                                                    int orow) {
+    SnCtx c;
+    c.IYr = IYr;
+    c.RSr = RSr;
+    c.P = P;
+    c.n = A->n;
+    c.xlo = xlo;
+    c.xhi = xhi;
+    c.xfull = xlo == 0 && xhi == c.n - 1;
+    const int kt = A->kt, w = A->w;
     // 8-neighbour test with the raster tie rule: neighbours earlier in raster
     // order must be strictly smaller, later ones may tie.  Outside the tile:
     // -infinity for now.
@@ -501,25 +510,25 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut
             const int dy = k / 3 - 1, dx = k % 3 - 1;
             const bool outside = lane + dx < 0 || lane + dx >= kWave || r + dy == orow;
             if (k == 4 || !outside) continue;
-            const float sq = sn_direct(c, x + dx, Yc + r + dy);
+            const float sq = sn_direct(A, P, a, b, x + dx, Yc + r + dy);
             const bool earlier = dy < 0 || (dy == 0 && dx < 0);
             ok = earlier ? s > sq : s >= sq;
         }
         if (!ok) cm &= ~(1u << r);
     }
     const int total = wave_sum_i32(__popc(cm));
-    if (lane == 0) o.tcount[o.slot] = total;
+    if (lane == 0) A->tcount[slot] = total;
     if (total == 0) return;
-    Entry* E = o.ent + o.slot * (long long)kt;
+    Entry* E = A->ent + slot * (long long)kt;
     if (total <= kt) {
-        int slot = wave_excl_scan(__popc(cm), lane);
+        int k = wave_excl_scan(__popc(cm), lane);
 #pragma unroll 1
         for (int r = 1; r <= kColRows - 2; ++r) {
             if ((cm >> r) & 1u) {
                 int cov;
                 const float v = col[r * kWave + lane];
                 const float s = sn_row(c, v, r, cov);
-                E[slot++] = Entry{s, v, (Yc + r) * o.w + x, cov};
+                E[k++] = Entry{s, v, (Yc + r) * w + x, cov};
             }
         }
         return;
@@ -534,7 +543,7 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut
         for (int r = 1; r <= kColRows - 2; ++r) {
             if ((left_rows >> r) & 1u) {
                 int cov;
-                const unsigned long long key = cand_key(sn_row(c, col[r * kWave + lane], r, cov), (Yc + r) * o.w + x);
+                const unsigned long long key = cand_key(sn_row(c, col[r * kWave + lane], r, cov), (Yc + r) * w + x);
                 if (key > best) {
                     best = key;
                     bestr = r;
@@ -545,7 +554,7 @@ __device__ __noinline__ void candidates_from_column(const SnCtx c, const CandOut
         if (bestr >= 0 && best == wb) {
             int cov;
             const float v = col[bestr * kWave + lane];
-            E[k] = Entry{sn_row(c, v, bestr, cov), v, (Yc + bestr) * o.w + x, cov};
+            E[k] = Entry{sn_row(c, v, bestr, cov), v, (Yc + bestr) * w + x, cov};
             left_rows &= ~(1u << bestr);
         }
     }
@@ -561,6 +570,7 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
                                                 int h, int Y0, int tile, float* col, const float* xrow,
                                                 const int* IYr, const float* RSr, const double* P, int xlo, int xhi) {
     const long long kc = (long long)(b - A.vby0 * kVBY) * A.nvx + a;
+    const long long slot = kc * A.nslot + 2 * tile + h;
     SnCtx c;
     c.IYr = IYr;
     c.RSr = RSr;
@@ -571,9 +581,16 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
     c.xfull = xlo == 0 && xhi == A.n - 1;
     unsigned fl = 0;  // bit r: the wave's row r passes threshold and coverage
     if (c.xfull && xin) {
+        // the largest product first (fmaxf skips NaN, so m is one of the
+        // rows that can hold a candidate, or NaN); rows only when it passes
+        float m = acc[0] * rsm[0];
 #pragma unroll
-        for (int r = 0; r < kRowsW; ++r)
-            if (acc[r] * rsm[r] > A.thr) fl |= 1u << r;
+        for (int r = 1; r < kRowsW; ++r) m = fmaxf(m, acc[r] * rsm[r]);
+        if (m > A.thr) {
+#pragma unroll
+            for (int r = 0; r < kRowsW; ++r)
+                if (acc[r] * rsm[r] > A.thr) fl |= 1u << r;
+        }
     }
     if (__ballot(!c.xfull && xin) != 0) {
         // lanes near the frame's x edges: combine both coverage intervals
@@ -587,14 +604,8 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
         }
     }
     fl <<= 1;  // the wave's row r is column row r + 1
-    CandOut o;
-    o.tcount = A.tcount;
-    o.ent = A.ent;
-    o.slot = kc * A.nslot + 2 * tile + h;
-    o.kt = A.kt;
-    o.w = A.w;
     if (__ballot(fl != 0) == 0) {
-        if (lane == 0) o.tcount[o.slot] = 0;
+        if (lane == 0) A.tcount[slot] = 0;
         return;
     }
     // Rare path (some pixel of this wave's column block clears the
@@ -604,22 +615,8 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
 #pragma unroll
     for (int r = 0; r < kRowsW; ++r) own[r * kWave + lane] = acc[r];
     col[(h ? 0 : kColRows - 1) * kWave + lane] = xrow[lane];
-    c.pad = A.pad;
-    c.DX = A.DX;
-    c.DY = A.DY;
-    c.IX = A.IX;
-    c.IY = A.IY;
-    c.fstride = A.fstride;
-    c.Wp = A.Wp;
-    c.padL = A.padL;
-    c.padT = A.padT;
-    c.ldx = A.ldx;
-    c.ldy = A.ldy;
-    c.w = A.w;
-    c.h = A.h;
-    c.a = a;
-    c.b = b;
-    candidates_from_column(c, o, col, fl, lane, x, Y0 + kRowsW * h - 1, h ? kColRows - 1 : 0);
+    candidates_from_column((KArgs)__builtin_amdgcn_kernarg_segment_ptr(), IYr, RSr, P, xlo, xhi, a, b, slot, col, fl,
+                           lane, x, Y0 + kRowsW * h - 1, h ? kColRows - 1 : 0);
 }
 
 // One frame's samples for a wave whose two y velocities sample rows D apart
