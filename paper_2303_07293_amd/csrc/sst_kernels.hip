@@ -467,13 +467,15 @@ __device__ __noinline__ void candidates_from_column(KArgs A, const int* IYr, con
         int cv;
         return r == orow ? -INFINITY : sn_row(c, col[r * kWave + lane], r, cv);
     };
+    // the left and right neighbours' values by whole-wave DPP shifts (lane 0
+    // and lane 63 have none: -infinity)
     auto left = [&](float v) __attribute__((always_inline)) {
-        const float t = __shfl_up(v, 1);
-        return lane == 0 ? -INFINITY : t;
+        return __int_as_float(
+            __builtin_amdgcn_update_dpp(__float_as_int(-INFINITY), __float_as_int(v), 0x138, 0xf, 0xf, false));
     };
     auto right = [&](float v) __attribute__((always_inline)) {
-        const float t = __shfl_down(v, 1);
-        return lane == kWave - 1 ? -INFINITY : t;
+        return __int_as_float(
+            __builtin_amdgcn_update_dpp(__float_as_int(-INFINITY), __float_as_int(v), 0x130, 0xf, 0xf, false));
     };
     unsigned cm = 0;
     float Sm = sn_col(0), S0 = sn_col(1);
