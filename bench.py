@@ -254,17 +254,67 @@ def batch_bench(torch, sst, args):
                       "ms_graph_replay_4_streams": t_graph4 * 1e3}), flush=True)
 
 
+def stack_bench(torch, sst, args):
+    """The plain float32 stack (`sst_stack`, SUM, every [vy][vx][h][w] stack
+    written to HBM) on the full field's grid: 32 frames (the diagnostic shape,
+    where the written stacks make HBM a co-binding roof) or all 64.  Reported
+    as updates/s, and as compulsory HBM bytes (frames read once, stacks
+    written once) per step time against the HBM peak."""
+    import synth
+    f = synth.config_diagnostic() if args.workload == "stack" else synth.config2()
+    dev = torch.device("cuda:0")
+    frames = torch.from_numpy(f.frames).to(dev)
+    n, h, w = f.frames.shape
+    nvx, nvy = len(f.vx), len(f.vy)
+    nb = sst.sst_workspace_bytes(sst.SST_OP_STACK, n, h, w, f.t, f.t_ref, f.vx, f.vy)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    out = torch.empty((nvy, nvx, h, w), dtype=torch.float32, device=dev)
+
+    def step():
+        sst.sst_stack(frames, f.t, f.t_ref, f.vx, f.vy, out=out, ws=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sst.sst_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    kern_ms, launches = sst.sst_profile_end()
+    kern_ms /= args.steps
+    updates = n * h * w * nvx * nvy
+    nbytes = 4 * n * h * w + 4 * nvx * nvy * h * w
+    gbs = nbytes / dt / 1e9
+    achieved = updates / (kern_ms * 1e-3) / 1e12
+    print(json.dumps({
+        "metric": "frame*pixel*velocity updates/s", "value": updates / dt, "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"plain stack {n}x{h}x{w} grid{nvx}x{nvy}, SUM, stacks written",
+                   "output_bytes": 4 * nvx * nvy * h * w},
+        "hbm": {"compulsory_bytes": nbytes, "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_ADD_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_ADD_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_stack<stack>", "kernel_ms_per_step": round(kern_ms, 4),
+                     "launches_per_step": launches / args.steps},
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["full", "tiny", "prep", "refine", "batch", "tinybatch"], default="full",
+    ap.add_argument("--workload", choices=["full", "tiny", "prep", "refine", "batch", "tinybatch", "stack", "stackfull"],
+                    default="full",
                     help="full: the search on the full field; tiny: the small field; prep: the steps before the "
                          "search (2x2 binning, median removal, co-adding) timed on their own; refine: sub-pixel "
                          "refinement of 4096 full-field detections (33x33 cutouts, 20 ascent steps); batch: 16 "
                          "uneven fields as prepared runs, back to back and as one graph; tinybatch: 64 small "
-                         "fields likewise")
+                         "fields likewise; stack / stackfull: the plain float32 stacks written to HBM, 32 or 64 "
+                         "frames of the full field")
     ap.add_argument("--storage", choices=["f32", "bf16", "f16"], default="f32",
                     help="frame storage: 16-bit frames with per-frame scales (quantised on the GPU before the "
                          "timed region); arithmetic stays float32")
@@ -293,6 +343,9 @@ def main():
         return
     if args.workload in ("batch", "tinybatch"):
         batch_bench(torch, sst, args)
+        return
+    if args.workload in ("stack", "stackfull"):
+        stack_bench(torch, sst, args)
         return
 
     f = synth.config2() if args.workload == "full" else synth.config1()

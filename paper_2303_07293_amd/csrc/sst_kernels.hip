@@ -955,8 +955,10 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
                             }
                             if (A.mean) v = c > 0 ? v / (float)c : 0.f;
                             const long long o = (kk * A.h + y) * A.w + x;
-                            A.out[o] = v;
-                            if (A.cov) A.cov[o] = c;
+                            // streaming stores: the stacks are not read
+                            // again by this kernel, the staged frames are
+                            __builtin_nontemporal_store(v, A.out + o);
+                            if (A.cov) __builtin_nontemporal_store(c, A.cov + o);
                         }
                     }
                 }
