@@ -324,8 +324,8 @@ def main():
                          "the reference point that scales the HBM byte counters of a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the search shards by field or velocity block with no exchange; see the design notes)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the search shards by field or velocity block with no exchange between GPUs)",
               file=sys.stderr)
         sys.exit(2)
 

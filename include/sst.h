@@ -53,7 +53,7 @@ extern "C" {
 #define SST_E_RANGE (-3)       /* a shift or size beyond the supported range */
 #define SST_E_WORKSPACE (-4)   /* workspace missing or too small */
 #define SST_E_DEVICE (-5)      /* a HIP runtime call failed */
-#define SST_E_UNSUPPORTED (-6) /* valid request this build does not handle */
+#define SST_E_UNSUPPORTED (-6) /* valid request the library does not handle */
 
 /* frame storage types.  16-bit frames carry a per-frame float32 scale s_i:
  * the frame value is the float32 product s_i * (stored value), and every

@@ -23,14 +23,14 @@ O5  Candidates.  p is a candidate iff c >= c_min, SN > threshold and p's key
 O6  Lists.  Per velocity, candidates sorted by key, descending; the first
     k_max are kept, `count` is the number before truncation.
 
-Readings where the paper is silent (each is a choice, documented in the
-design notes as well):
+Readings where the paper is silent (each is a choice):
   R1 frames are sampled at p + d (the stacked grid is the sky at t_ref);
   R2 t_ref is an explicit argument;
   R3 rounding is half away from zero (C llround);
   R4 the velocity grid is the outer product vx x vy, index k = b*nvx + a;
   R5 out-of-frame samples contribute nothing; c_min defaults to ceil(N/2),
-     from the paper's "at least half of the images" rule;
+     following the paper's requirement that an object show in no fewer than
+     half of the frames (Sec. 2.1);
   R6 background = frame mean, noise = population variance;
   R7 per-pixel S/N, no PSF matched filter;
   R8 strict comparison SN > threshold;
