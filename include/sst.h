@@ -187,6 +187,43 @@ int sst_plan_run(const sst_plan* plan, const void* frames, int dtype, const floa
 /* Free a plan (NULL is ignored).  The workspace is the caller's again. */
 void sst_plan_destroy(sst_plan* plan);
 
+/* ---- batches of prepared searches: one persistent launch per round ----
+ * Many fields of uneven frame count, size and velocity grid (the paper's
+ * image groups of a night, Sec. 2.1 and 2.3) searched together: the
+ * stacking work of all plans runs as persistent launches whose workgroups
+ * take (tile, velocity block) items of any plan from work queues, one
+ * launch per round (round r: chunk r of the velocity-block rows of every
+ * plan that has one), each followed by the plans' merges.  Results are
+ * those of sst_plan_run for each plan, bit for bit.  Plans whose velocity
+ * blocks are too spread for LDS staging run on their own within the run. */
+typedef struct sst_batch sst_batch;
+
+/* Device workspace bytes of a batch's tables (0 and an error if a plan
+ * pointer is NULL or nplans <= 0). */
+size_t sst_batch_workspace_bytes(const sst_plan* const* plans, int nplans);
+
+/* Build a batch of nplans plans (host array of plan pointers; the plans
+ * must outlive the batch).  ws: dev, >= sst_batch_workspace_bytes, 256-byte
+ * aligned; it holds the work tables, written here (waits for `stream`
+ * once), and belongs to the batch until sst_batch_destroy.  *batch receives
+ * a host object.  Errors: SST_E_ARG, SST_E_WORKSPACE, SST_E_RANGE (more
+ * than 2^31 - 1 items in a round), SST_E_DEVICE. */
+int sst_batch_create(const sst_plan* const* plans, int nplans, void* ws, size_t ws_bytes, void* stream,
+                     sst_batch** batch);
+
+/* Run every plan of the batch on its frames: host arrays of nplans entries
+ * (frames[j], dtypes[j], scales[j] or scales == NULL for float32 frames,
+ * cand[j], count[j], each as for sst_plan_run with plan j).  Enqueues
+ * kernels only (no host synchronisation, allocation or memset; the queue
+ * counters are cleared by a kernel), so a run may be captured into a
+ * graph.  Runs of one batch, or of batches sharing plans, must not overlap
+ * in time.  Errors: SST_E_ARG, SST_E_DEVICE. */
+int sst_batch_run(const sst_batch* batch, const void* const* frames, const int* dtypes, const float* const* scales,
+                  sst_candidate* const* cand, int32_t* const* count, void* stream);
+
+/* Free a batch (NULL is ignored).  Its workspace is the caller's again. */
+void sst_batch_destroy(sst_batch* batch);
+
 /* Sub-pixel refinement of detections by gradient ascent on a differentiable
  * stacked S/N.  The search returns tracks on its integer grid (paper Sec.
  * 2.1); here theta = (x0, y0, vx, vy) is continuous.  For each candidate a

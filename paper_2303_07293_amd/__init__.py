@@ -19,6 +19,7 @@ from .binding import (  # noqa: F401
     SST_OP_STATS,
     SST_SUM,
     SstError,
+    SstBatch,
     SstPlan,
     candidates_to_numpy,
     load,

@@ -37,7 +37,7 @@ CANDIDATE_DTYPE = np.dtype([
 
 EXPORTS = ("sst_shift_table", "sst_workspace_bytes", "sst_quantize", "sst_median_subtract", "sst_coadd", "sst_bin2x2",
            "sst_frame_stats", "sst_stack", "sst_detect", "sst_refine", "sst_plan_detect", "sst_plan_run",
-           "sst_plan_destroy",
+           "sst_plan_destroy", "sst_batch_workspace_bytes", "sst_batch_create", "sst_batch_run", "sst_batch_destroy",
            "sst_profile_begin", "sst_profile_end", "sst_last_error", "sst_version")
 
 
@@ -93,6 +93,14 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.sst_plan_run.restype = _i
     lib.sst_plan_destroy.argtypes = [_p]
     lib.sst_plan_destroy.restype = None
+    lib.sst_batch_workspace_bytes.argtypes = [_p, _i]
+    lib.sst_batch_workspace_bytes.restype = _sz
+    lib.sst_batch_create.argtypes = [_p, _i, _p, _sz, _p, _p]
+    lib.sst_batch_create.restype = _i
+    lib.sst_batch_run.argtypes = [_p, _p, _p, _p, _p, _p, _p]
+    lib.sst_batch_run.restype = _i
+    lib.sst_batch_destroy.argtypes = [_p]
+    lib.sst_batch_destroy.restype = None
     lib.sst_profile_begin.argtypes = []
     lib.sst_profile_begin.restype = _i
     lib.sst_profile_end.argtypes = [_p, _p]
@@ -397,6 +405,70 @@ def sst_plan_detect(n: int, h: int, w: int, t, t_ref: float, vx, vy, threshold: 
                                   float(threshold), int(min_coverage), int(k_max), _dev(ws), ws.numel(),
                                   _stream(torch.device(device)), ctypes.byref(handle)))
     return SstPlan(handle, ws, n, h, w, len(vx) * len(vy), k_max)
+
+
+class SstBatch:
+    """Prepared plans searched together (sst_batch_create): `run` enqueues the
+    plans' preparation kernels, one persistent stacking launch per round and
+    the merges; kernels only, so it may be captured in a graph.  The plans
+    must stay open while the batch is used."""
+
+    def __init__(self, plans, device="cuda:0"):
+        import torch
+        self.plans = list(plans)
+        if not self.plans:
+            raise ValueError("a batch needs at least one plan")
+        if any(p._h is None for p in self.plans):
+            raise RuntimeError("plan was destroyed")
+        handles = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        self._handles = handles
+        nb = load().sst_batch_workspace_bytes(handles, len(self.plans))
+        if nb == 0:
+            _check(-1)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(load().sst_batch_create(handles, len(self.plans), _dev(self.ws), self.ws.numel(),
+                                       _stream(torch.device(device)), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, frames, scales=None, cands=None, counts=None):
+        """frames: list of [n][h][w] tensors, one per plan (scales likewise
+        for 16-bit frames).  Returns (cands, counts), lists as SstPlan.run."""
+        import torch
+        k = len(self.plans)
+        if len(frames) != k:
+            raise ValueError(f"{len(frames)} frame tensors for {k} plans")
+        if self._h is None:
+            raise RuntimeError("batch was destroyed")
+        if cands is None:
+            cands = [torch.empty((p.nk, p.k_max, 8), dtype=torch.int32, device=f.device)
+                     for p, f in zip(self.plans, frames)]
+        if counts is None:
+            counts = [torch.empty((p.nk,), dtype=torch.int32, device=f.device) for p, f in zip(self.plans, frames)]
+        fr, dt, sc = [], [], []
+        for j, (p, f) in enumerate(zip(self.plans, frames)):
+            _check_frames(f)
+            if tuple(f.shape) != (p.n, p.h, p.w):
+                raise ValueError(f"frames {j} {tuple(f.shape)} do not match plan {(p.n, p.h, p.w)}")
+            fr.append(_dev(f))
+            dt.append(_frames_dtype(f))
+            sc.append(_check_scale(f, None if scales is None else scales[j]))
+        arr = lambda vals: (ctypes.c_void_p * k)(*vals)
+        _check(load().sst_batch_run(self._h, arr(fr), (ctypes.c_int * k)(*dt), arr(sc),
+                                    arr([_dev(c) for c in cands]), arr([_dev(c) for c in counts]),
+                                    _stream(frames[0].device)))
+        return cands, counts
+
+    def close(self):
+        if self._h is not None:
+            load().sst_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sst_profile_begin() -> None:

@@ -345,34 +345,71 @@ hipError_t launch_stack_profiled(const StackArgs& a, bool detect, bool staged, h
     return e;
 }
 
-// Everything a detect call enqueues after the shift tables are in the
-// workspace: kernels only (no host synchronisation, no allocation, no
-// memset), so the sequence can be captured into a graph.
-int detect_enqueue(const Plan& p, void* ws, const void* frames, int dtype, const float* scale, float threshold,
-                   int min_coverage, int k_max, sst_candidate* cand, int32_t* count, bool stats_out, hipStream_t s) {
-    hipError_t e = launch_stats(frames, dtype, scale, p.n, p.h, p.w, at<double>(ws, p.o_part), p.nchunk,
-                                at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
-                                at<double>(ws, p.o_P), stats_out ? at<double>(ws, p.o_sdev) : nullptr, s);
-    if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
-    int rc;
-    if ((rc = prep_and_cov(p, frames, dtype, scale, at<float>(ws, p.o_b32), ws, s))) return rc;
+hipError_t launch_batch_profiled(const BatchArgs& b, int groups, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (!g_prof.on) return launch_stack_batch(b, groups, s);
+    if (g_prof.used >= kProfMax) {
+        g_prof.on = false;
+        return hipErrorLaunchOutOfResources;
+    }
+    hipEvent_t e0 = g_prof.ev[2 * g_prof.used], e1 = g_prof.ev[2 * g_prof.used + 1];
+    hipError_t e = hipEventRecord(e0, s);
+    if (e != hipSuccess) return e;
+    e = launch_stack_batch(b, groups, s);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(e1, s);
+    if (e == hipSuccess) ++g_prof.used;
+    return e;
+}
+
+// The detect launch arguments of a plan for the velocity-block rows
+// [r0, r0 + rows).
+StackArgs detect_args(const Plan& p, void* ws, float threshold, int min_coverage, int r0, int rows) {
     StackArgs a = stack_args(p, ws);
     a.thr = threshold;
     a.cmin = min_coverage > 0 ? min_coverage : (p.n + 1) / 2;
     a.kt = p.kt;
     a.tcount = at<int32_t>(ws, p.o_tcount);
     a.ent = at<Entry>(ws, p.o_ent);
+    a.vby0 = r0;
+    a.nvby = rows;
+    return a;
+}
+
+// Frame statistics, padded copy and coverage intervals of a detect call.
+int detect_prepare(const Plan& p, void* ws, const void* frames, int dtype, const float* scale, bool stats_out,
+                   hipStream_t s) {
+    hipError_t e = launch_stats(frames, dtype, scale, p.n, p.h, p.w, at<double>(ws, p.o_part), p.nchunk,
+                                at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
+                                at<double>(ws, p.o_P), stats_out ? at<double>(ws, p.o_sdev) : nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
+    return prep_and_cov(p, frames, dtype, scale, at<float>(ws, p.o_b32), ws, s);
+}
+
+// Merge of the slots of velocity-block rows [r0, r0 + rows) into the lists.
+int detect_merge(const Plan& p, void* ws, int k_max, int r0, int rows, sst_candidate* cand, int32_t* count,
+                 hipStream_t s) {
+    const int b_first = r0 * kVBY;
+    const int b_last = std::min(p.nvy, (r0 + rows) * kVBY);
+    const int nk = (b_last - b_first) * p.nvx;
+    const hipError_t e = launch_merge(at<int32_t>(ws, p.o_tcount), at<Entry>(ws, p.o_ent), p.nslot, p.kt, k_max,
+                                      p.nvx, p.w, b_first * p.nvx, nk, cand, count, s);
+    return e != hipSuccess ? hip_fail(e, "merge kernel") : SST_OK;
+}
+
+// Everything a detect call enqueues after the shift tables are in the
+// workspace: kernels only (no host synchronisation, no allocation, no
+// memset), so the sequence can be captured into a graph.
+int detect_enqueue(const Plan& p, void* ws, const void* frames, int dtype, const float* scale, float threshold,
+                   int min_coverage, int k_max, sst_candidate* cand, int32_t* count, bool stats_out, hipStream_t s) {
+    int rc;
+    if ((rc = detect_prepare(p, ws, frames, dtype, scale, stats_out, s))) return rc;
     for (int r0 = 0; r0 < p.nvby; r0 += p.rows_per_chunk) {
         const int rows = std::min(p.rows_per_chunk, p.nvby - r0);
-        a.vby0 = r0;
-        a.nvby = rows;
-        if ((e = launch_stack_profiled(a, true, p.staged, s)) != hipSuccess) return hip_fail(e, "detect kernel");
-        const int b_first = r0 * kVBY;
-        const int b_last = std::min(p.nvy, (r0 + rows) * kVBY);
-        const int nk = (b_last - b_first) * p.nvx;
-        if ((e = launch_merge(a.tcount, a.ent, p.nslot, p.kt, k_max, p.nvx, p.w, b_first * p.nvx, nk, cand, count,
-                              s)) != hipSuccess)
-            return hip_fail(e, "merge kernel");
+        const StackArgs a = detect_args(p, ws, threshold, min_coverage, r0, rows);
+        const hipError_t e = launch_stack_profiled(a, true, p.staged, s);
+        if (e != hipSuccess) return hip_fail(e, "detect kernel");
+        if ((rc = detect_merge(p, ws, k_max, r0, rows, cand, count, s))) return rc;
     }
     return SST_OK;
 }
@@ -389,7 +426,182 @@ struct sst_plan {
     int k_max = 0;
 };
 
+// A batch of prepared detect plans whose stacking runs as persistent
+// launches: round r covers chunk r (velocity-block rows) of every staged
+// plan that has one.  Plans whose blocks are not staged run on their own.
+struct sst_batch {
+    struct Round {
+        std::vector<int> prob;  // plan index of each problem of the round
+        BatchArgs args{};
+        int groups = 0;
+    };
+    std::vector<const sst_plan*> plans;
+    std::vector<char> solo;
+    std::vector<Round> rounds;
+};
+
+namespace {
+
+// Layout of a batch's device tables: per round the problems' arguments, the
+// first items and the queue counters.
+struct BatchLayout {
+    std::vector<size_t> o_tab, o_start, o_cnt;
+    size_t total = 0;
+};
+
+int plan_chunks(const Plan& p) { return (p.nvby + p.rows_per_chunk - 1) / p.rows_per_chunk; }
+
+int batch_layout(const sst_plan* const* plans, int nplans, BatchLayout& L) {
+    if (!plans || nplans <= 0) return fail(SST_E_ARG, "no plans");
+    int rounds = 0;
+    for (int j = 0; j < nplans; ++j) {
+        if (!plans[j]) return fail(SST_E_ARG, "plan %d is NULL", j);
+        if (plans[j]->p.staged) rounds = std::max(rounds, plan_chunks(plans[j]->p));
+    }
+    size_t cur = 0;
+    L = BatchLayout{};
+    for (int r = 0; r < rounds; ++r) {
+        int np = 0;
+        for (int j = 0; j < nplans; ++j)
+            if (plans[j]->p.staged && r < plan_chunks(plans[j]->p)) ++np;
+        L.o_tab.push_back(take(cur, (size_t)np * sizeof(StackArgs)));
+        L.o_start.push_back(take(cur, (size_t)(np + 1) * sizeof(int)));
+        L.o_cnt.push_back(take(cur, kBatchQueues * sizeof(int)));
+    }
+    L.total = std::max<size_t>(cur, 256);
+    return SST_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+size_t sst_batch_workspace_bytes(const sst_plan* const* plans, int nplans) {
+    g_err.clear();
+    BatchLayout L;
+    return batch_layout(plans, nplans, L) ? 0 : L.total;
+}
+
+int sst_batch_create(const sst_plan* const* plans, int nplans, void* ws, size_t ws_bytes, void* stream,
+                     sst_batch** batch) {
+    g_err.clear();
+    if (!batch) return fail(SST_E_ARG, "batch is NULL");
+    *batch = nullptr;
+    BatchLayout L;
+    int rc = batch_layout(plans, nplans, L);
+    if (rc) return rc;
+    if (!ws || ws_bytes < L.total)
+        return fail(SST_E_WORKSPACE, "batch workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(SST_E_ARG, "workspace not 256-byte aligned");
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device attributes");
+    sst_batch* b = new (std::nothrow) sst_batch;
+    if (!b) return fail(SST_E_DEVICE, "out of host memory");
+    b->plans.assign(plans, plans + nplans);
+    b->solo.resize(nplans);
+    for (int j = 0; j < nplans; ++j) b->solo[j] = !plans[j]->p.staged;
+    std::vector<char> host(L.total, 0);
+    b->rounds.resize(L.o_tab.size());
+    for (size_t r = 0; r < b->rounds.size(); ++r) {
+        auto& R = b->rounds[r];
+        std::vector<StackArgs> tab;
+        std::vector<int> start(1, 0);
+        std::vector<double> cost;  // per item of each problem: frames to add
+        for (int j = 0; j < nplans; ++j) {
+            const Plan& p = plans[j]->p;
+            if (!p.staged || (int)r >= plan_chunks(p)) continue;
+            const int r0 = (int)r * p.rows_per_chunk, rows = std::min(p.rows_per_chunk, p.nvby - r0);
+            tab.push_back(detect_args(p, plans[j]->ws, plans[j]->threshold, plans[j]->min_coverage, r0, rows));
+            const long long items = (long long)p.tiles_x * p.tiles_y * p.nvbx * rows;
+            if (start.back() + items > 0x7FFFFFFFll) {
+                delete b;
+                return fail(SST_E_RANGE, "too many work items in one batch round");
+            }
+            start.push_back(start.back() + (int)items);
+            cost.push_back((double)p.n);
+            R.prob.push_back(j);
+        }
+        const int np = (int)R.prob.size();
+        // queues of equal cost: problem j's items cost n_j each
+        double total = 0.0;
+        for (int k = 0; k < np; ++k) total += cost[k] * (start[k + 1] - start[k]);
+        R.args.qbegin[0] = 0;
+        for (int q = 1; q < kBatchQueues; ++q) {
+            const double target = total * q / kBatchQueues;
+            double acc = 0.0;
+            int item = start[np];
+            for (int k = 0; k < np; ++k) {
+                const double c = cost[k] * (start[k + 1] - start[k]);
+                if (acc + c >= target) {
+                    item = start[k] + (int)std::ceil((target - acc) / cost[k]);
+                    break;
+                }
+                acc += c;
+            }
+            R.args.qbegin[q] = std::max(R.args.qbegin[q - 1], std::min(item, start[np]));
+        }
+        R.args.qbegin[kBatchQueues] = start[np];
+        R.args.tab = at<StackArgs>(ws, L.o_tab[r]);
+        R.args.start = at<int>(ws, L.o_start[r]);
+        R.args.nprob = np;
+        R.args.counter = at<int>(ws, L.o_cnt[r]);
+        // one workgroup per CU (the stacking kernel's occupancy), at least
+        // one per queue, the same number per queue
+        const int want = std::max(1, std::min(start[np], std::max(ncu, kBatchQueues)));
+        R.groups = (want + kBatchQueues - 1) / kBatchQueues * kBatchQueues;
+        std::memcpy(host.data() + L.o_tab[r], tab.data(), tab.size() * sizeof(StackArgs));
+        std::memcpy(host.data() + L.o_start[r], start.data(), start.size() * sizeof(int));
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    e = hipMemcpyAsync(ws, host.data(), L.total, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch table upload");
+    }
+    *batch = b;
+    return SST_OK;
+}
+
+int sst_batch_run(const sst_batch* batch, const void* const* frames, const int* dtypes, const float* const* scales,
+                  sst_candidate* const* cand, int32_t* const* count, void* stream) {
+    g_err.clear();
+    if (!batch) return fail(SST_E_ARG, "batch is NULL");
+    if (!frames || !dtypes || !cand || !count) return fail(SST_E_ARG, "frames/dtypes/cand/count array is NULL");
+    const int np = (int)batch->plans.size();
+    int rc;
+    for (int j = 0; j < np; ++j) {
+        if ((rc = check_frames(frames[j], dtypes[j], scales ? scales[j] : nullptr))) return rc;
+        if (!cand[j] || !count[j]) return fail(SST_E_ARG, "cand/count %d is NULL", j);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int j = 0; j < np; ++j) {
+        const sst_plan* pl = batch->plans[j];
+        const float* sc = scales ? scales[j] : nullptr;
+        if (batch->solo[j])
+            rc = detect_enqueue(pl->p, pl->ws, frames[j], dtypes[j], sc, pl->threshold, pl->min_coverage, pl->k_max,
+                                cand[j], count[j], false, s);
+        else
+            rc = detect_prepare(pl->p, pl->ws, frames[j], dtypes[j], sc, false, s);
+        if (rc) return rc;
+    }
+    for (size_t r = 0; r < batch->rounds.size(); ++r) {
+        const auto& R = batch->rounds[r];
+        hipError_t e = launch_zero_i32(R.args.counter, kBatchQueues, s);
+        if (e != hipSuccess) return hip_fail(e, "queue reset kernel");
+        if ((e = launch_batch_profiled(R.args, R.groups, s)) != hipSuccess) return hip_fail(e, "batch detect kernel");
+        for (int j : R.prob) {
+            const sst_plan* pl = batch->plans[j];
+            const int r0 = (int)r * pl->p.rows_per_chunk, rows = std::min(pl->p.rows_per_chunk, pl->p.nvby - r0);
+            if ((rc = detect_merge(pl->p, pl->ws, pl->k_max, r0, rows, cand[j], count[j], s))) return rc;
+        }
+    }
+    return SST_OK;
+}
+
+void sst_batch_destroy(sst_batch* batch) { delete batch; }
 
 int sst_profile_begin(void) {
     g_err.clear();

@@ -111,6 +111,20 @@ struct StackArgs {
     Entry* ent;       // [velocities of this launch][nslot][kt]
 };
 
+// One round of a batch of detect problems, run by one persistent launch:
+// the arguments of each problem's share of the round, the first global work
+// item of each problem, and kBatchQueues queues of consecutive items (one
+// per XCD: workgroup g serves queue g mod kBatchQueues, whose items it takes
+// one at a time through an atomic counter).
+constexpr int kBatchQueues = 8;
+struct BatchArgs {
+    const StackArgs* tab;  // [nprob]
+    const int* start;      // [nprob + 1], start[nprob] = items in the round
+    int nprob;
+    int* counter;          // [kBatchQueues] items taken, zero before the launch
+    int qbegin[kBatchQueues + 1];
+};
+
 struct PrepArgs {
     const void* frames;  // [n][h][w] of dtype
     int dtype;           // SST_F32, SST_BF16, SST_F16
@@ -129,6 +143,8 @@ hipError_t launch_quantize(const float* frames, int n, int h, int w, int dtype, 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_cov(const int* D, int ld, int n, int nv, int size, int* I, hipStream_t s);
 hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, hipStream_t s);
+hipError_t launch_stack_batch(const BatchArgs& b, int groups, hipStream_t s);
+hipError_t launch_zero_i32(int* p, int count, hipStream_t s);
 hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int nslot, int kt, int k_max,
                         int nvx, int w, int k_first, int nk, void* cand, int32_t* count,
                         hipStream_t s);

@@ -396,9 +396,9 @@ struct SnCtx {
     bool xfull;        // this lane's column sees every frame in x
 };
 
-// The kernel's arguments where they were passed (the kernel argument
-// segment): a callee reads them there instead of from a copy.
-typedef const __attribute__((address_space(4))) StackArgs* KArgs;
+// Where a callee reads the arguments of the work item: the kernel argument
+// segment, or the entry of a batch's argument table (never a copy).
+typedef const StackArgs* KArgs;
 
 // S/N of column row r of this lane (and its coverage).  A lane whose x
 // samples are all inside has coverage = the row's y interval, whose 1/sqrt(V)
@@ -567,7 +567,7 @@ __device__ __noinline__ void candidates_from_column(KArgs A, const int* IYr, con
 // else NaN, so that acc * rsm[r] > threshold is exactly the threshold and
 // coverage test (NaN compares false).  xrow is the other row half's boundary
 // row of the same velocity; IYr and RSr start at column row 0 (tile row R0).
-__device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float (&acc)[kRowsW],
+__device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, const float (&acc)[kRowsW],
                                                 const float (&rsm)[kRowsW], int a, int b, int x, bool xin, int lane,
                                                 int h, int Y0, int tile, float* col, const float* xrow,
                                                 const int* IYr, const float* RSr, const double* P, int xlo, int xhi) {
@@ -617,7 +617,7 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, const float 
 #pragma unroll
     for (int r = 0; r < kRowsW; ++r) own[r * kWave + lane] = acc[r];
     col[(h ? 0 : kColRows - 1) * kWave + lane] = xrow[lane];
-    candidates_from_column((KArgs)__builtin_amdgcn_kernarg_segment_ptr(), IYr, RSr, P, xlo, xhi, a, b, slot, col, fl,
+    candidates_from_column(Ap, IYr, RSr, P, xlo, xhi, a, b, slot, col, fl,
                            lane, x, Y0 + kRowsW * h - 1, h ? kColRows - 1 : 0);
 }
 
@@ -705,8 +705,10 @@ __device__ __forceinline__ void barrier_keep_reads() { asm volatile("s_barrier" 
 template <int V>
 using ic = std::integral_constant<int, V>;
 
+// One work item of the stacking kernels: tile and velocity block number
+// `logical` of the problem A describes (Ap: where a callee reads A).
 template <bool DETECT, bool STAGED>
-__global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
+__device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int logical) {
     // LDS: two staging buffers during the frame loop; afterwards each wave's
     // candidate column and the published boundary rows of every wave
     constexpr int kColFloats = kWaves * kColRows * kWave;
@@ -721,7 +723,6 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nvb = A.nvbx * A.nvby;
-    const int logical = xcd_remap(blockIdx.x, gridDim.x);
     const int tile = logical / nvb;
     const int vb = logical - tile * nvb;
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
@@ -987,7 +988,7 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
                     rsm[4 * k + 2] = t.z;
                     rsm[4 * k + 3] = t.w;
                 }
-                detect_epilogue(A, acc[q][s], rsm, aw + q, bb, x, xin, lane, h, Y0, tile, col,
+                detect_epilogue(A, Ap, acc[q][s], rsm, aw + q, bb, x, xin, lane, h, Y0, tile, col,
                                 xin_rows + (q * kVYW + s) * kWave, sIY + (vr * kRows + R0) * 2, sRS + vr * kRows + R0,
                                 P, xlo[q], xhi[q]);
             }
@@ -1008,6 +1009,49 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
         else
             epi(A.P);
     }
+}
+
+template <bool DETECT, bool STAGED>
+__global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
+    stack_item<DETECT, STAGED>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(), xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Persistent form for a batch of detect problems (all staged): each
+// workgroup takes work items from its queue until the queue is empty; an
+// item is a (tile, velocity block) of one problem, found by binary search of
+// the problems' first items.
+__global__ __launch_bounds__(kThreads) void k_stack_batch(const BatchArgs B) {
+    __shared__ int s_item;
+    const int q = blockIdx.x % kBatchQueues;
+    const int begin = B.qbegin[q], end = B.qbegin[q + 1];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = begin + atomicAdd(B.counter + q, 1);
+        __syncthreads();
+        const int g = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (g >= end) break;
+        int lo = 0, hi = B.nprob - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (B.start[mid] <= g)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        // the table is read-only during the launch: read it through the
+        // constant address space, so that the (uniform) loads are scalar
+        typedef const __attribute__((address_space(4))) StackArgs CArgs;
+        const StackArgs* Ap = (const StackArgs*)((CArgs*)B.tab + lo);
+        stack_item<true, true>(*Ap, Ap, g - B.start[lo]);
+        // (the item's last barrier precedes every wave's reuse of LDS in the
+        // next item, whose first writes come after its own barriers)
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kAux) void k_zero_i32(int* __restrict__ p, int count) {
+    const int i = blockIdx.x * kAux + threadIdx.x;
+    if (i < count) p[i] = 0;
 }
 
 // ------------------------------------------------------------------ merge
@@ -1189,6 +1233,18 @@ hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, hipStream_
         else
             hipLaunchKernelGGL((k_stack<false, false>), grid, block, 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_stack_batch(const BatchArgs& b, int groups, hipStream_t s) {
+    if (groups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stack_batch, dim3((unsigned)groups), dim3(kThreads), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int* p, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((count + kAux - 1) / kAux)), dim3(kAux), 0, s, p, count);
     return hipGetLastError();
 }
 

@@ -276,3 +276,18 @@ def test_plan_argument_errors(lib):
                                ctypes.byref(h)) == B.SST_E_WORKSPACE
     assert lib.sst_plan_run(None, FAKE, 0, None, FAKE, FAKE, None) == B.SST_E_ARG
     lib.sst_plan_destroy(None)
+
+
+def test_batch_argument_errors(lib):
+    """Batch entry points reject missing plans and handles before any device
+    work."""
+    assert lib.sst_batch_workspace_bytes(None, 0) == 0
+    nulls = (ctypes.c_void_p * 2)(None, None)
+    assert lib.sst_batch_workspace_bytes(nulls, 2) == 0
+    h = ctypes.c_void_p()
+    assert lib.sst_batch_create(None, 1, FAKE, 1 << 20, None, ctypes.byref(h)) == B.SST_E_ARG
+    assert lib.sst_batch_create(nulls, 2, FAKE, 1 << 20, None, ctypes.byref(h)) == B.SST_E_ARG
+    assert h.value is None
+    assert lib.sst_batch_create(nulls, 2, FAKE, 1 << 20, None, None) == B.SST_E_ARG
+    assert lib.sst_batch_run(None, FAKE, FAKE, None, FAKE, FAKE, None) == B.SST_E_ARG
+    lib.sst_batch_destroy(None)

@@ -121,3 +121,82 @@ def test_graph_capture_of_many_fields(sst, n_streams):
     assert marg <= 4
     for p in plans:
         p.close()
+
+
+# --------------------------------------------------------------- batches
+def _multi_chunk_case(seed_shift=0):
+    """512^2 noise frames with a 61 x 61 grid at 0.5 px/h over 2 h and
+    k_max 1024: the slot budget splits the velocity-block rows into 8 chunks,
+    so a batch runs several rounds."""
+    t = np.linspace(0.0, 2.0, 8)
+    f = synth.pure_noise(60 + 1000 * seed_shift, 8, 512, 512, sigma=5.0, sky=50.0, t=t)
+    f.vx = np.arange(-30, 31, dtype=np.float64) * 0.5
+    f.vy = f.vx.copy()
+    return f
+
+
+def _batch_cases(seed_shift=0):
+    return [_case(s, seed_shift) for s in FIELDS] + [_multi_chunk_case(seed_shift)]
+
+
+def _settings(f):
+    return (2.5, 0, 1024) if f.w == 512 else (2.5, 0, 8)
+
+
+def test_batch_matches_plan_runs(sst):
+    cases = _batch_cases()
+    plans = [sst.sst_plan_detect(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, *_settings(f)) for f in cases]
+    batch = sst.SstBatch(plans)
+    _say(f"case batch of {len(cases)} fields (one with several rounds)")
+    for shift in (0, 1):
+        new = _batch_cases(shift)
+        frames = [torch.from_numpy(g.frames).to("cuda:0") for g in new]
+        cands, counts = batch.run(frames)
+        torch.cuda.synchronize()
+        for k, (p, fr) in enumerate(zip(plans, frames)):
+            c, n = p.run(fr)
+            torch.cuda.synchronize()
+            assert torch.equal(cands[k], c) and torch.equal(counts[k], n), (shift, k)
+        _say(f"  run {shift}: {len(new)} fields match their plan runs, "
+              f"{sum(int(n.sum()) for n in counts)} candidates")
+    batch.close()
+    for p in plans:
+        p.close()
+
+
+def test_batch_graph_replays(sst):
+    cases = _batch_cases()
+    plans = [sst.sst_plan_detect(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, *_settings(f)) for f in cases]
+    batch = sst.SstBatch(plans)
+    frames = [torch.from_numpy(f.frames).to("cuda:0") for f in cases]
+    cands = [torch.empty((p.nk, p.k_max, 8), dtype=torch.int32, device="cuda:0") for p in plans]
+    counts = [torch.empty((p.nk,), dtype=torch.int32, device="cuda:0") for p in plans]
+    _say(f"case graph of a batch of {len(cases)} fields")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch.run(frames, cands=cands, counts=counts)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.run(frames, cands=cands, counts=counts)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        new = _batch_cases(rep + 2)
+        for fr, g in zip(frames, new):
+            fr.copy_(torch.from_numpy(g.frames))
+        for c, n in zip(cands, counts):
+            c.fill_(-7)
+            n.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k, g in enumerate(new):
+            ce, ne = sst.sst_detect(frames[k], g.t, g.t_ref, g.vx, g.vy, *_settings(g))
+            torch.cuda.synchronize()
+            assert torch.equal(cands[k], ce) and torch.equal(counts[k], ne), (rep, k)
+        _say(f"  replay {rep}: {len(new)} fields match eager runs")
+    batch.close()
+    for p in plans:
+        p.close()
