@@ -175,7 +175,9 @@ def batch_bench(torch, sst, args):
     prepared once (sst_plan_detect); timed are (a) plain sst_detect calls, one
     per field, (b) the prepared runs enqueued back to back, (c) the same runs
     captured in one graph and replayed, (d) the runs spread over 4 streams,
-    (e) (d) captured in one graph.  Value: updates/s of (e)."""
+    (e) (d) captured in one graph, (f) one persistent stacking launch per
+    round for all fields (SstBatch), (g) (f) captured in one graph.  Value:
+    updates/s of the faster of (e) and (g)."""
     import synth
     dev = torch.device("cuda:0")
     if args.workload == "batch":
@@ -242,16 +244,33 @@ def batch_bench(torch, sst, args):
         runs_parallel()
     torch.cuda.synchronize()
     t_graph4 = timed(graph4.replay, reps)
+    # (f) one persistent stacking launch per round for all fields, (g) (f)
+    # captured in one graph
+    batch = sst.SstBatch([x[9] for x in fields])
+    bframes = [x[8] for x in fields]
+    bc, bn = [x[10][0] for x in fields], [x[10][1] for x in fields]
+
+    def batched():
+        batch.run(bframes, cands=bc, counts=bn)
+
+    t_batch = timed(batched, reps)
+    graphb = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graphb):
+        batched()
+    torch.cuda.synchronize()
+    t_graphb = timed(graphb.replay, reps)
     # the eager path re-uploads the tables into the plans' workspaces: last
     t_eager = timed(eager, reps)
-    print(json.dumps({"metric": "frame*pixel*velocity updates/s", "value": total / t_graph4, "unit": "updates/s",
-                      "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": t_graph4 * 1e3, "higher_is_better": True,
+    best = min(t_graph4, t_graphb)
+    print(json.dumps({"metric": "frame*pixel*velocity updates/s", "value": total / best, "unit": "updates/s",
+                      "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": best * 1e3, "higher_is_better": True,
                       "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": f"{args.workload}: {len(fields)} fields, {total:.3g} updates",
                                  "fields": [x[0] for x in fields]},
                       "ms_eager_calls": t_eager * 1e3, "ms_prepared_runs": t_runs * 1e3,
                       "ms_graph_replay": t_graph * 1e3, "ms_prepared_runs_4_streams": t_par * 1e3,
-                      "ms_graph_replay_4_streams": t_graph4 * 1e3}), flush=True)
+                      "ms_graph_replay_4_streams": t_graph4 * 1e3, "ms_persistent_batch": t_batch * 1e3,
+                      "ms_graph_replay_persistent_batch": t_graphb * 1e3}), flush=True)
 
 
 def stack_bench(torch, sst, args):

@@ -205,8 +205,9 @@ size_t sst_batch_workspace_bytes(const sst_plan* const* plans, int nplans);
 /* Build a batch of nplans plans (host array of plan pointers; the plans
  * must outlive the batch).  ws: dev, >= sst_batch_workspace_bytes, 256-byte
  * aligned; it holds the work tables, written here (waits for `stream`
- * once), and belongs to the batch until sst_batch_destroy.  *batch receives
- * a host object.  Errors: SST_E_ARG, SST_E_WORKSPACE, SST_E_RANGE (more
+ * once), and belongs to the batch until sst_batch_destroy.  The batch also
+ * creates three streams (default priority) and four events on the current
+ * device.  *batch receives a host object.  Errors: SST_E_ARG, SST_E_WORKSPACE, SST_E_RANGE (more
  * than 2^31 - 1 items in a round), SST_E_DEVICE. */
 int sst_batch_create(const sst_plan* const* plans, int nplans, void* ws, size_t ws_bytes, void* stream,
                      sst_batch** batch);
@@ -215,9 +216,11 @@ int sst_batch_create(const sst_plan* const* plans, int nplans, void* ws, size_t 
  * (frames[j], dtypes[j], scales[j] or scales == NULL for float32 frames,
  * cand[j], count[j], each as for sst_plan_run with plan j).  Enqueues
  * kernels only (no host synchronisation, allocation or memset; the queue
- * counters are cleared by a kernel), so a run may be captured into a
- * graph.  Runs of one batch, or of batches sharing plans, must not overlap
- * in time.  Errors: SST_E_ARG, SST_E_DEVICE. */
+ * counters are cleared by a kernel): the plans' preparation kernels and
+ * merges are spread over three streams of the batch, forked from `stream`
+ * and joined back to it with events, so a run may be captured into a graph
+ * from `stream`.  Runs of one batch, or of batches sharing plans, must not
+ * overlap in time.  Errors: SST_E_ARG, SST_E_DEVICE. */
 int sst_batch_run(const sst_batch* batch, const void* const* frames, const int* dtypes, const float* const* scales,
                   sst_candidate* const* cand, int32_t* const* count, void* stream);
 

@@ -438,6 +438,19 @@ struct sst_batch {
     std::vector<const sst_plan*> plans;
     std::vector<char> solo;
     std::vector<Round> rounds;
+    // side streams (default priority) over which a run spreads the plans'
+    // preparation kernels and merges, forked from and joined to the run's
+    // stream by events
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr, join[kSide] = {};
+    ~sst_batch() {
+        for (int i = 0; i < kSide; ++i) {
+            if (side[i]) (void)hipStreamDestroy(side[i]);
+            if (join[i]) (void)hipEventDestroy(join[i]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+    }
 };
 
 namespace {
@@ -499,6 +512,15 @@ int sst_batch_create(const sst_plan* const* plans, int nplans, void* ws, size_t 
     if (e != hipSuccess) return hip_fail(e, "device attributes");
     sst_batch* b = new (std::nothrow) sst_batch;
     if (!b) return fail(SST_E_DEVICE, "out of host memory");
+    e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int i = 0; i < sst_batch::kSide && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch streams and events");
+    }
     b->plans.assign(plans, plans + nplans);
     b->solo.resize(nplans);
     for (int j = 0; j < nplans; ++j) b->solo[j] = !plans[j]->p.staged;
@@ -577,26 +599,48 @@ int sst_batch_run(const sst_batch* batch, const void* const* frames, const int* 
         if (!cand[j] || !count[j]) return fail(SST_E_ARG, "cand/count %d is NULL", j);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
+    constexpr int kS = sst_batch::kSide;
+    // fork: work item k goes to stream k mod (kS + 1), stream 0 being s
+    auto fork = [&]() -> hipError_t {
+        hipError_t e = hipEventRecord(batch->fork, s);
+        for (int i = 0; i < kS && e == hipSuccess; ++i) e = hipStreamWaitEvent(batch->side[i], batch->fork, 0);
+        return e;
+    };
+    auto join = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < kS && e == hipSuccess; ++i) {
+            e = hipEventRecord(batch->join[i], batch->side[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, batch->join[i], 0);
+        }
+        return e;
+    };
+    auto on = [&](int k) { return k % (kS + 1) == 0 ? s : batch->side[k % (kS + 1) - 1]; };
+    hipError_t e = fork();
+    if (e != hipSuccess) return hip_fail(e, "batch fork");
     for (int j = 0; j < np; ++j) {
         const sst_plan* pl = batch->plans[j];
         const float* sc = scales ? scales[j] : nullptr;
         if (batch->solo[j])
             rc = detect_enqueue(pl->p, pl->ws, frames[j], dtypes[j], sc, pl->threshold, pl->min_coverage, pl->k_max,
-                                cand[j], count[j], false, s);
+                                cand[j], count[j], false, on(j));
         else
-            rc = detect_prepare(pl->p, pl->ws, frames[j], dtypes[j], sc, false, s);
+            rc = detect_prepare(pl->p, pl->ws, frames[j], dtypes[j], sc, false, on(j));
         if (rc) return rc;
     }
+    if ((e = join()) != hipSuccess) return hip_fail(e, "batch join");
     for (size_t r = 0; r < batch->rounds.size(); ++r) {
         const auto& R = batch->rounds[r];
-        hipError_t e = launch_zero_i32(R.args.counter, kBatchQueues, s);
-        if (e != hipSuccess) return hip_fail(e, "queue reset kernel");
+        if ((e = launch_zero_i32(R.args.counter, kBatchQueues, s)) != hipSuccess)
+            return hip_fail(e, "queue reset kernel");
         if ((e = launch_batch_profiled(R.args, R.groups, s)) != hipSuccess) return hip_fail(e, "batch detect kernel");
-        for (int j : R.prob) {
-            const sst_plan* pl = batch->plans[j];
+        if ((e = fork()) != hipSuccess) return hip_fail(e, "batch fork");
+        for (size_t k = 0; k < R.prob.size(); ++k) {
+            const sst_plan* pl = batch->plans[R.prob[k]];
+            const int j = R.prob[k];
             const int r0 = (int)r * pl->p.rows_per_chunk, rows = std::min(pl->p.rows_per_chunk, pl->p.nvby - r0);
-            if ((rc = detect_merge(pl->p, pl->ws, pl->k_max, r0, rows, cand[j], count[j], s))) return rc;
+            if ((rc = detect_merge(pl->p, pl->ws, pl->k_max, r0, rows, cand[j], count[j], on((int)k)))) return rc;
         }
+        if ((e = join()) != hipSuccess) return hip_fail(e, "batch join");
     }
     return SST_OK;
 }

@@ -1017,35 +1017,39 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
 }
 
 // Persistent form for a batch of detect problems (all staged): each
-// workgroup takes work items from its queue until the queue is empty; an
-// item is a (tile, velocity block) of one problem, found by binary search of
-// the problems' first items.
+// workgroup takes work items from its queue until the queue is empty, then
+// helps the other queues; an item is a (tile, velocity block) of one
+// problem, found by binary search of the problems' first items.
 __global__ __launch_bounds__(kThreads) void k_stack_batch(const BatchArgs B) {
+    // the table is read-only during the launch: read it through the constant
+    // address space, so that the (uniform) loads are scalar
+    typedef const __attribute__((address_space(4))) StackArgs CArgs;
     __shared__ int s_item;
-    const int q = blockIdx.x % kBatchQueues;
-    const int begin = B.qbegin[q], end = B.qbegin[q + 1];
-    for (;;) {
-        if (threadIdx.x == 0) s_item = begin + atomicAdd(B.counter + q, 1);
-        __syncthreads();
-        const int g = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (g >= end) break;
-        int lo = 0, hi = B.nprob - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (B.start[mid] <= g)
-                lo = mid;
-            else
-                hi = mid - 1;
+    const int q0 = blockIdx.x % kBatchQueues;
+    // the workgroup's own queue first, then (for the tail of the launch)
+    // the other queues in turn; every queue ends, so every workgroup exits
+    for (int k = 0; k < kBatchQueues; ++k) {
+        const int q = (q0 + k) % kBatchQueues;
+        const int begin = B.qbegin[q], end = B.qbegin[q + 1];
+        for (;;) {
+            if (threadIdx.x == 0) s_item = begin + atomicAdd(B.counter + q, 1);
+            __syncthreads();
+            const int g = __builtin_amdgcn_readfirstlane(s_item);
+            __syncthreads();
+            if (g >= end) break;
+            int lo = 0, hi = B.nprob - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (B.start[mid] <= g)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const StackArgs* Ap = (const StackArgs*)((CArgs*)B.tab + lo);
+            stack_item<true, true>(*Ap, Ap, g - B.start[lo]);
+            // every wave has finished the item before the next one reuses LDS
+            __syncthreads();
         }
-        // the table is read-only during the launch: read it through the
-        // constant address space, so that the (uniform) loads are scalar
-        typedef const __attribute__((address_space(4))) StackArgs CArgs;
-        const StackArgs* Ap = (const StackArgs*)((CArgs*)B.tab + lo);
-        stack_item<true, true>(*Ap, Ap, g - B.start[lo]);
-        // (the item's last barrier precedes every wave's reuse of LDS in the
-        // next item, whose first writes come after its own barriers)
-        __syncthreads();
     }
 }
 
