@@ -100,6 +100,23 @@ int sst_shift_table(const double* t, int n, double t_ref, const double* v, int n
 size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double t_ref,
                            const double* vx, int nvx, const double* vy, int nvy, int k_max);
 
+/* Velocity-block shapes.  The stacking kernels are compiled for several
+ * blocks of VBX x VBY trial velocities per workgroup (the velocity grid is
+ * padded to whole blocks; a block's frame window is widened by the spread
+ * of its shifts).  Shape 0 (9 x 4) is the default of every one-shot call;
+ * shape 1 (3 x 12) wastes less on small grids whose y shifts spread little.
+ * sst_shape_info writes the block size of `shape` (vbx/vby may be NULL) and
+ * returns the number of shapes, or SST_E_ARG for an unknown shape.  Which
+ * shape is faster for a problem is left to the caller (a tuner times
+ * plans of each). */
+int sst_shape_info(int shape, int* vbx, int* vby);
+
+/* sst_workspace_bytes for velocity-block shape `shape` (sst_workspace_bytes
+ * is shape 0): the shift tables are padded to whole blocks and the slots of
+ * a detect launch hold whole block rows. */
+size_t sst_workspace_bytes_shape(int op, int shape, int n, int h, int w, const double* t, double t_ref,
+                                 const double* vx, int nvx, const double* vy, int nvy, int k_max);
+
 /* 16-bit storage of float32 frames with a per-frame offset and scale (a
  * data-layout step before the search, not part of the paper's method):
  *   offset[i] = float32 of the float64 mean of frame i if center != 0, else 0
@@ -176,6 +193,20 @@ typedef struct sst_plan sst_plan;
 int sst_plan_detect(int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
                     const double* vy, int nvy, float threshold, int min_coverage, int k_max,
                     void* ws, size_t ws_bytes, void* stream, sst_plan** plan);
+
+/* sst_plan_detect with velocity-block shape `shape` (sst_plan_detect is
+ * shape 0; ws >= sst_workspace_bytes_shape(SST_OP_DETECT, shape, ...)).
+ * Every shape gives the same candidate lists bit for bit; only the time
+ * differs.  Errors: as sst_plan_detect, SST_E_ARG for an unknown shape. */
+int sst_plan_detect_shape(int shape, int n, int h, int w, const double* t, double t_ref, const double* vx,
+                          int nvx, const double* vy, int nvy, float threshold, int min_coverage, int k_max,
+                          void* ws, size_t ws_bytes, void* stream, sst_plan** plan);
+
+/* What a plan does: its shape, whether its velocity blocks are staged in
+ * LDS (1) or read through L2 (0, much slower: blocks too spread for the
+ * staging window), and its stacking launches per run (chunks of block
+ * rows).  Any pointer may be NULL.  Errors: SST_E_ARG (plan NULL). */
+int sst_plan_info(const sst_plan* plan, int* shape, int* staged, int* launches);
 
 /* The search of sst_detect for frames of the prepared geometry (same
  * results bit for bit).  frames/dtype/scale/cand/count as for sst_detect.

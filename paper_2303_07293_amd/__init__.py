@@ -34,8 +34,10 @@ from .binding import (  # noqa: F401
     sst_profile_end,
     sst_quantize,
     sst_refine,
+    sst_shapes,
     sst_shift_table,
     sst_stack,
     sst_workspace_bytes,
 )
 from .autograd import StackedSNR, stacked_snr  # noqa: F401,E402
+from .tune import tune_plan, tuned_shape, tuning_times  # noqa: F401,E402

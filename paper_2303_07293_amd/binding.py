@@ -38,6 +38,7 @@ CANDIDATE_DTYPE = np.dtype([
 EXPORTS = ("sst_shift_table", "sst_workspace_bytes", "sst_quantize", "sst_median_subtract", "sst_coadd", "sst_bin2x2",
            "sst_frame_stats", "sst_stack", "sst_detect", "sst_refine", "sst_plan_detect", "sst_plan_run",
            "sst_plan_destroy", "sst_batch_workspace_bytes", "sst_batch_create", "sst_batch_run", "sst_batch_destroy",
+           "sst_shape_info", "sst_workspace_bytes_shape", "sst_plan_detect_shape", "sst_plan_info",
            "sst_profile_begin", "sst_profile_end", "sst_last_error", "sst_version")
 
 
@@ -69,6 +70,14 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.sst_shift_table.restype = _i
     lib.sst_workspace_bytes.argtypes = [_i, _i, _i, _i, _p, _d, _p, _i, _p, _i, _i]
     lib.sst_workspace_bytes.restype = _sz
+    lib.sst_workspace_bytes_shape.argtypes = [_i, _i, _i, _i, _i, _p, _d, _p, _i, _p, _i, _i]
+    lib.sst_workspace_bytes_shape.restype = _sz
+    lib.sst_shape_info.argtypes = [_i, _p, _p]
+    lib.sst_shape_info.restype = _i
+    lib.sst_plan_detect_shape.argtypes = [_i, _i, _i, _i, _p, _d, _p, _i, _p, _i, _f, _i, _i, _p, _sz, _p, _p]
+    lib.sst_plan_detect_shape.restype = _i
+    lib.sst_plan_info.argtypes = [_p, _p, _p, _p]
+    lib.sst_plan_info.restype = _i
     lib.sst_quantize.argtypes = [_p, _i, _i, _i, _i, _i, _p, _p, _p, _p, _sz, _p]
     lib.sst_quantize.restype = _i
     lib.sst_median_subtract.argtypes = [_p, _i, _i, _i, _p, _p, _p]
@@ -166,15 +175,29 @@ def sst_shift_table(t, t_ref: float, v) -> np.ndarray:
 
 
 def sst_workspace_bytes(op: int, n: int, h: int, w: int, t=None, t_ref: float = 0.0, vx=None, vy=None,
-                        k_max: int = 0) -> int:
+                        k_max: int = 0, shape: int = 0) -> int:
     t = None if t is None else _f64(t)
     vx = None if vx is None else _f64(vx)
     vy = None if vy is None else _f64(vy)
-    nb = load().sst_workspace_bytes(op, n, h, w, _ptr(t), float(t_ref), _ptr(vx), 0 if vx is None else len(vx),
-                                    _ptr(vy), 0 if vy is None else len(vy), k_max)
+    nb = load().sst_workspace_bytes_shape(op, shape, n, h, w, _ptr(t), float(t_ref), _ptr(vx),
+                                          0 if vx is None else len(vx), _ptr(vy), 0 if vy is None else len(vy), k_max)
     if nb == 0:
         raise SstError(SST_E_ARG, sst_last_error())
     return int(nb)
+
+
+def sst_shapes():
+    """The compiled velocity-block shapes: list of (vbx, vby), index = shape."""
+    out = []
+    k = 0
+    while True:
+        vbx, vby = ctypes.c_int(0), ctypes.c_int(0)
+        nsh = load().sst_shape_info(k, ctypes.byref(vbx), ctypes.byref(vby))
+        _check(nsh)
+        out.append((vbx.value, vby.value))
+        k += 1
+        if k >= nsh:
+            return out
 
 
 def _workspace(nbytes: int, device, ws=None):
@@ -365,6 +388,9 @@ class SstPlan:
         self._h = handle
         self.ws = ws
         self.n, self.h, self.w, self.nk, self.k_max = n, h, w, nk, k_max
+        shape, staged, launches = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _check(load().sst_plan_info(handle, ctypes.byref(shape), ctypes.byref(staged), ctypes.byref(launches)))
+        self.shape, self.staged, self.launches = shape.value, bool(staged.value), launches.value
 
     def run(self, frames, scale=None, cand=None, count=None):
         import torch
@@ -394,16 +420,17 @@ class SstPlan:
 
 
 def sst_plan_detect(n: int, h: int, w: int, t, t_ref: float, vx, vy, threshold: float, min_coverage: int = 0,
-                    k_max: int = 64, device="cuda:0") -> SstPlan:
-    """Prepare sst_detect for one geometry (uploads the shift tables once)."""
+                    k_max: int = 64, device="cuda:0", shape: int = 0) -> SstPlan:
+    """Prepare sst_detect for one geometry (uploads the shift tables once),
+    with velocity-block shape `shape` (see sst_shapes)."""
     import torch
     t, vx, vy = _f64(t), _f64(vx), _f64(vy)
-    nb = sst_workspace_bytes(SST_OP_DETECT, n, h, w, t, t_ref, vx, vy, k_max)
+    nb = sst_workspace_bytes(SST_OP_DETECT, n, h, w, t, t_ref, vx, vy, k_max, shape=shape)
     ws = torch.empty(nb, dtype=torch.uint8, device=device)
     handle = ctypes.c_void_p()
-    _check(load().sst_plan_detect(n, h, w, _ptr(t), float(t_ref), _ptr(vx), len(vx), _ptr(vy), len(vy),
-                                  float(threshold), int(min_coverage), int(k_max), _dev(ws), ws.numel(),
-                                  _stream(torch.device(device)), ctypes.byref(handle)))
+    _check(load().sst_plan_detect_shape(int(shape), n, h, w, _ptr(t), float(t_ref), _ptr(vx), len(vx), _ptr(vy),
+                                        len(vy), float(threshold), int(min_coverage), int(k_max), _dev(ws),
+                                        ws.numel(), _stream(torch.device(device)), ctypes.byref(handle)))
     return SstPlan(handle, ws, n, h, w, len(vx) * len(vy), k_max)
 
 

@@ -106,6 +106,7 @@ struct Plan {
     int step_x = 0, step_y = 0, tiles_x = 0, tiles_y = 0, ntiles = 0, nslot = 0;
     int padL = 0, padT = 0, Wp = 0, Hp = 0;
     bool staged = true;
+    int shape = 0, vbx = 0, vby = 0;  // velocity-block shape
     int kt = 0, rows_per_chunk = 0, nchunk = 0;
     std::vector<int32_t> DX, DY;
     // workspace offsets (bytes)
@@ -120,10 +121,14 @@ size_t take(size_t& cur, size_t bytes) {
 }
 
 int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
-              const double* vy, int nvy, int k_max, Plan& p) {
+              const double* vy, int nvy, int k_max, Plan& p, int shape = 0) {
     int rc = check_dims(n, h, w);
     if (rc) return rc;
+    if (shape < 0 || shape >= kNShapes) return fail(SST_E_ARG, "velocity-block shape %d: need 0..%d", shape, kNShapes - 1);
     p.op = op;
+    p.shape = shape;
+    p.vbx = shape_vbx(shape);
+    p.vby = shape_vby(shape);
     p.n = n;
     p.h = h;
     p.w = w;
@@ -149,10 +154,10 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
     const bool detect = op == SST_OP_DETECT;
     p.nvx = nvx;
     p.nvy = nvy;
-    p.nvbx = ceil_div(nvx, kVBX);
-    p.nvby = ceil_div(nvy, kVBY);
-    p.ldx = p.nvbx * kVBX;
-    p.ldy = p.nvby * kVBY;
+    p.nvbx = ceil_div(nvx, p.vbx);
+    p.nvby = ceil_div(nvy, p.vby);
+    p.ldx = p.nvbx * p.vbx;
+    p.ldy = p.nvby * p.vby;
     if ((rc = build_table(t, n, t_ref, vx, nvx, p.ldx, w, p.DX, "vx"))) return rc;
     if ((rc = build_table(t, n, t_ref, vy, nvy, p.ldy, h, p.DY, "vy"))) return rc;
 
@@ -168,15 +173,15 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
     int dxmin = 0, dxmax = 0, dymin = 0, dymax = 0, sx = 0, sy = 0;
     for (int i = 0; i < n; ++i) {
         const int32_t* rx = &p.DX[(size_t)i * p.ldx];
-        for (int a0 = 0; a0 < p.ldx; a0 += kVBX) {
-            const auto mm = std::minmax_element(rx + a0, rx + a0 + kVBX);
+        for (int a0 = 0; a0 < p.ldx; a0 += p.vbx) {
+            const auto mm = std::minmax_element(rx + a0, rx + a0 + p.vbx);
             dxmin = std::min(dxmin, *mm.first);
             dxmax = std::max(dxmax, *mm.second);
             sx = std::max(sx, *mm.second - *mm.first);
         }
         const int32_t* ry = &p.DY[(size_t)i * p.ldy];
-        for (int b0 = 0; b0 < p.ldy; b0 += kVBY) {
-            const auto mm = std::minmax_element(ry + b0, ry + b0 + kVBY);
+        for (int b0 = 0; b0 < p.ldy; b0 += p.vby) {
+            const auto mm = std::minmax_element(ry + b0, ry + b0 + p.vby);
             dymin = std::min(dymin, *mm.first);
             dymax = std::max(dymax, *mm.second);
             sy = std::max(sy, *mm.second - *mm.first);
@@ -208,9 +213,9 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
         p.o_P = take(cur, (size_t)(n + 1) * sizeof(double));
         p.o_sdev = take(cur, (size_t)n * 2 * sizeof(double));
         p.kt = k_max;
-        const size_t per_row = (size_t)kVBY * nvx * p.nslot * ((size_t)p.kt * sizeof(Entry) + sizeof(int32_t));
+        const size_t per_row = (size_t)p.vby * nvx * p.nslot * ((size_t)p.kt * sizeof(Entry) + sizeof(int32_t));
         p.rows_per_chunk = (int)std::max<size_t>(1, std::min<size_t>(p.nvby, kEntryBudget / per_row));
-        const size_t nk = (size_t)p.rows_per_chunk * kVBY * nvx;
+        const size_t nk = (size_t)p.rows_per_chunk * p.vby * nvx;
         p.o_tcount = take(cur, nk * p.nslot * sizeof(int32_t));
         p.o_ent = take(cur, nk * p.nslot * p.kt * sizeof(Entry));
     }
@@ -328,9 +333,9 @@ struct Profiler {
 };
 Profiler g_prof;
 
-hipError_t launch_stack_profiled(const StackArgs& a, bool detect, bool staged, hipStream_t s) {
+hipError_t launch_stack_profiled(const StackArgs& a, bool detect, bool staged, int shape, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    if (!g_prof.on) return launch_stack(a, detect, staged, s);
+    if (!g_prof.on) return launch_stack(a, detect, staged, shape, s);
     if (g_prof.used >= kProfMax) {
         g_prof.on = false;
         return hipErrorLaunchOutOfResources;
@@ -338,16 +343,16 @@ hipError_t launch_stack_profiled(const StackArgs& a, bool detect, bool staged, h
     hipEvent_t e0 = g_prof.ev[2 * g_prof.used], e1 = g_prof.ev[2 * g_prof.used + 1];
     hipError_t e = hipEventRecord(e0, s);
     if (e != hipSuccess) return e;
-    e = launch_stack(a, detect, staged, s);
+    e = launch_stack(a, detect, staged, shape, s);
     if (e != hipSuccess) return e;
     e = hipEventRecord(e1, s);
     if (e == hipSuccess) ++g_prof.used;
     return e;
 }
 
-hipError_t launch_batch_profiled(const BatchArgs& b, int groups, hipStream_t s) {
+hipError_t launch_batch_profiled(const BatchArgs& b, int groups, int shape, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    if (!g_prof.on) return launch_stack_batch(b, groups, s);
+    if (!g_prof.on) return launch_stack_batch(b, groups, shape, s);
     if (g_prof.used >= kProfMax) {
         g_prof.on = false;
         return hipErrorLaunchOutOfResources;
@@ -355,7 +360,7 @@ hipError_t launch_batch_profiled(const BatchArgs& b, int groups, hipStream_t s) 
     hipEvent_t e0 = g_prof.ev[2 * g_prof.used], e1 = g_prof.ev[2 * g_prof.used + 1];
     hipError_t e = hipEventRecord(e0, s);
     if (e != hipSuccess) return e;
-    e = launch_stack_batch(b, groups, s);
+    e = launch_stack_batch(b, groups, shape, s);
     if (e != hipSuccess) return e;
     e = hipEventRecord(e1, s);
     if (e == hipSuccess) ++g_prof.used;
@@ -389,8 +394,8 @@ int detect_prepare(const Plan& p, void* ws, const void* frames, int dtype, const
 // Merge of the slots of velocity-block rows [r0, r0 + rows) into the lists.
 int detect_merge(const Plan& p, void* ws, int k_max, int r0, int rows, sst_candidate* cand, int32_t* count,
                  hipStream_t s) {
-    const int b_first = r0 * kVBY;
-    const int b_last = std::min(p.nvy, (r0 + rows) * kVBY);
+    const int b_first = r0 * p.vby;
+    const int b_last = std::min(p.nvy, (r0 + rows) * p.vby);
     const int nk = (b_last - b_first) * p.nvx;
     const hipError_t e = launch_merge(at<int32_t>(ws, p.o_tcount), at<Entry>(ws, p.o_ent), p.nslot, p.kt, k_max,
                                       p.nvx, p.w, b_first * p.nvx, nk, cand, count, s);
@@ -407,7 +412,7 @@ int detect_enqueue(const Plan& p, void* ws, const void* frames, int dtype, const
     for (int r0 = 0; r0 < p.nvby; r0 += p.rows_per_chunk) {
         const int rows = std::min(p.rows_per_chunk, p.nvby - r0);
         const StackArgs a = detect_args(p, ws, threshold, min_coverage, r0, rows);
-        const hipError_t e = launch_stack_profiled(a, true, p.staged, s);
+        const hipError_t e = launch_stack_profiled(a, true, p.staged, p.shape, s);
         if (e != hipSuccess) return hip_fail(e, "detect kernel");
         if ((rc = detect_merge(p, ws, k_max, r0, rows, cand, count, s))) return rc;
     }
@@ -434,6 +439,8 @@ struct sst_batch {
         std::vector<int> prob;  // plan index of each problem of the round
         BatchArgs args{};
         int groups = 0;
+        int shape = 0;  // velocity-block shape of every problem of the round
+        int chunk = 0;  // velocity-block-row chunk of every problem
     };
     std::vector<const sst_plan*> plans;
     std::vector<char> solo;
@@ -458,11 +465,15 @@ namespace {
 // Layout of a batch's device tables: per round the problems' arguments, the
 // first items and the queue counters.
 struct BatchLayout {
+    std::vector<int> chunk, shape;  // per launch
     std::vector<size_t> o_tab, o_start, o_cnt;
     size_t total = 0;
 };
 
 int plan_chunks(const Plan& p) { return (p.nvby + p.rows_per_chunk - 1) / p.rows_per_chunk; }
+
+// Whether plan p has work in the launch of chunk r and shape sh.
+bool in_round(const Plan& p, int r, int sh) { return p.staged && p.shape == sh && r < plan_chunks(p); }
 
 int batch_layout(const sst_plan* const* plans, int nplans, BatchLayout& L) {
     if (!plans || nplans <= 0) return fail(SST_E_ARG, "no plans");
@@ -473,14 +484,18 @@ int batch_layout(const sst_plan* const* plans, int nplans, BatchLayout& L) {
     }
     size_t cur = 0;
     L = BatchLayout{};
-    for (int r = 0; r < rounds; ++r) {
-        int np = 0;
-        for (int j = 0; j < nplans; ++j)
-            if (plans[j]->p.staged && r < plan_chunks(plans[j]->p)) ++np;
-        L.o_tab.push_back(take(cur, (size_t)np * sizeof(StackArgs)));
-        L.o_start.push_back(take(cur, (size_t)(np + 1) * sizeof(int)));
-        L.o_cnt.push_back(take(cur, kBatchQueues * sizeof(int)));
-    }
+    for (int r = 0; r < rounds; ++r)
+        for (int sh = 0; sh < kNShapes; ++sh) {
+            int np = 0;
+            for (int j = 0; j < nplans; ++j)
+                if (in_round(plans[j]->p, r, sh)) ++np;
+            if (np == 0) continue;
+            L.chunk.push_back(r);
+            L.shape.push_back(sh);
+            L.o_tab.push_back(take(cur, (size_t)np * sizeof(StackArgs)));
+            L.o_start.push_back(take(cur, (size_t)(np + 1) * sizeof(int)));
+            L.o_cnt.push_back(take(cur, kBatchQueues * sizeof(int)));
+        }
     L.total = std::max<size_t>(cur, 256);
     return SST_OK;
 }
@@ -528,13 +543,15 @@ int sst_batch_create(const sst_plan* const* plans, int nplans, void* ws, size_t 
     b->rounds.resize(L.o_tab.size());
     for (size_t r = 0; r < b->rounds.size(); ++r) {
         auto& R = b->rounds[r];
+        R.chunk = L.chunk[r];
+        R.shape = L.shape[r];
         std::vector<StackArgs> tab;
         std::vector<int> start(1, 0);
         std::vector<double> cost;  // per item of each problem: frames to add
         for (int j = 0; j < nplans; ++j) {
             const Plan& p = plans[j]->p;
-            if (!p.staged || (int)r >= plan_chunks(p)) continue;
-            const int r0 = (int)r * p.rows_per_chunk, rows = std::min(p.rows_per_chunk, p.nvby - r0);
+            if (!in_round(p, R.chunk, R.shape)) continue;
+            const int r0 = R.chunk * p.rows_per_chunk, rows = std::min(p.rows_per_chunk, p.nvby - r0);
             tab.push_back(detect_args(p, plans[j]->ws, plans[j]->threshold, plans[j]->min_coverage, r0, rows));
             const long long items = (long long)p.tiles_x * p.tiles_y * p.nvbx * rows;
             if (start.back() + items > 0x7FFFFFFFll) {
@@ -632,12 +649,13 @@ int sst_batch_run(const sst_batch* batch, const void* const* frames, const int* 
         const auto& R = batch->rounds[r];
         if ((e = launch_zero_i32(R.args.counter, kBatchQueues, s)) != hipSuccess)
             return hip_fail(e, "queue reset kernel");
-        if ((e = launch_batch_profiled(R.args, R.groups, s)) != hipSuccess) return hip_fail(e, "batch detect kernel");
+        if ((e = launch_batch_profiled(R.args, R.groups, R.shape, s)) != hipSuccess)
+            return hip_fail(e, "batch detect kernel");
         if ((e = fork()) != hipSuccess) return hip_fail(e, "batch fork");
         for (size_t k = 0; k < R.prob.size(); ++k) {
             const sst_plan* pl = batch->plans[R.prob[k]];
             const int j = R.prob[k];
-            const int r0 = (int)r * pl->p.rows_per_chunk, rows = std::min(pl->p.rows_per_chunk, pl->p.nvby - r0);
+            const int r0 = R.chunk * pl->p.rows_per_chunk, rows = std::min(pl->p.rows_per_chunk, pl->p.nvby - r0);
             if ((rc = detect_merge(pl->p, pl->ws, pl->k_max, r0, rows, cand[j], count[j], on((int)k)))) return rc;
         }
         if ((e = join()) != hipSuccess) return hip_fail(e, "batch join");
@@ -705,10 +723,23 @@ int sst_shift_table(const double* t, int n, double t_ref, const double* v, int n
 
 size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
                            const double* vy, int nvy, int k_max) {
+    return sst_workspace_bytes_shape(op, 0, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max);
+}
+
+size_t sst_workspace_bytes_shape(int op, int shape, int n, int h, int w, const double* t, double t_ref,
+                                 const double* vx, int nvx, const double* vy, int nvy, int k_max) {
     g_err.clear();
     Plan p;
-    if (make_plan(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p) != SST_OK) return 0;
+    if (make_plan(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p, shape) != SST_OK) return 0;
     return p.total;
+}
+
+int sst_shape_info(int shape, int* vbx, int* vby) {
+    g_err.clear();
+    if (shape < 0 || shape >= kNShapes) return fail(SST_E_ARG, "velocity-block shape %d: need 0..%d", shape, kNShapes - 1);
+    if (vbx) *vbx = shape_vbx(shape);
+    if (vby) *vby = shape_vby(shape);
+    return kNShapes;
 }
 
 int sst_quantize(const float* frames, int n, int h, int w, int dtype, int center, void* q, float* scale,
@@ -880,7 +911,7 @@ int sst_stack(const void* frames, int dtype, const float* scale, int n, int h, i
     a.out = out;
     a.cov = cov;
     a.mean = mode == SST_MEAN;
-    hipError_t e = launch_stack_profiled(a, false, p.staged, s);
+    hipError_t e = launch_stack_profiled(a, false, p.staged, p.shape, s);
     if (e != hipSuccess) return hip_fail(e, "stack kernel");
     return SST_OK;
 }
@@ -913,13 +944,20 @@ int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, 
 int sst_plan_detect(int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx, const double* vy,
                     int nvy, float threshold, int min_coverage, int k_max, void* ws, size_t ws_bytes, void* stream,
                     sst_plan** plan) {
+    return sst_plan_detect_shape(0, n, h, w, t, t_ref, vx, nvx, vy, nvy, threshold, min_coverage, k_max, ws, ws_bytes,
+                                 stream, plan);
+}
+
+int sst_plan_detect_shape(int shape, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
+                          const double* vy, int nvy, float threshold, int min_coverage, int k_max, void* ws,
+                          size_t ws_bytes, void* stream, sst_plan** plan) {
     g_err.clear();
     if (!plan) return fail(SST_E_ARG, "plan is NULL");
     *plan = nullptr;
     if (std::isnan(threshold)) return fail(SST_E_ARG, "threshold is NaN");
     sst_plan* pl = new (std::nothrow) sst_plan;
     if (!pl) return fail(SST_E_DEVICE, "out of host memory");
-    int rc = make_plan(SST_OP_DETECT, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, pl->p);
+    int rc = make_plan(SST_OP_DETECT, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, pl->p, shape);
     if (!rc) rc = check_ws(pl->p, ws, ws_bytes);
     if (!rc) rc = upload_tables(pl->p, nullptr, ws, static_cast<hipStream_t>(stream));
     if (rc) {
@@ -943,6 +981,15 @@ int sst_plan_run(const sst_plan* plan, const void* frames, int dtype, const floa
     if (!cand || !count) return fail(SST_E_ARG, "cand/count is NULL");
     return detect_enqueue(plan->p, plan->ws, frames, dtype, scale, plan->threshold, plan->min_coverage, plan->k_max,
                           cand, count, false, static_cast<hipStream_t>(stream));
+}
+
+int sst_plan_info(const sst_plan* plan, int* shape, int* staged, int* launches) {
+    g_err.clear();
+    if (!plan) return fail(SST_E_ARG, "plan is NULL");
+    if (shape) *shape = plan->p.shape;
+    if (staged) *staged = plan->p.staged ? 1 : 0;
+    if (launches) *launches = plan_chunks(plan->p);
+    return SST_OK;
 }
 
 void sst_plan_destroy(sst_plan* plan) { delete plan; }

@@ -18,10 +18,10 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Work decomposition of the stack kernels.  A workgroup is kWaves wave64s
 // (three per SIMD); it owns a tile of 64 columns (one per lane) by kRows
-// rows and a block of kVBX x kVBY trial velocities, so every staged frame
-// tile is reused by all kVBX * kVBY velocities of the block.  Wave w
-// handles kRowsW = kRows / 2 rows (half w % 2) of kVPW x velocities (group
-// w / 4) and kVYW = 2 neighbouring y velocities (pair (w / 2) % 2):
+// rows and a block of VBX x VBY trial velocities (a shape below), so every
+// staged frame tile is reused by all VBX * VBY velocities of the block.  Wave
+// w handles kRowsW = kRows / 2 rows (half w % 2) of kVPW x velocities and
+// kVYW = 2 neighbouring y velocities:
 // kVPW * kVYW * kRowsW float accumulators per lane.  For one frame the two
 // y velocities of a pair sample rows a small uniform distance d apart, so
 // one read of kRowsW + |d| staged rows feeds both sets of accumulators.
@@ -31,12 +31,19 @@ constexpr int kThreads = kWave * kWaves;
 constexpr int kTileW = 64;
 constexpr int kRows = 32;
 constexpr int kRowsW = kRows / 2;  // rows per wave
-constexpr int kVBX = 9;
-constexpr int kVBY = 4;
 constexpr int kVPW = 3;  // x velocities per wave
 constexpr int kVYW = 2;  // y velocities per wave
 constexpr int kDMax = 4; // largest |d| read once for both y velocities of a pair
-static_assert(kVBX * kVBY * 2 == kVPW * kVYW * kWaves, "every (velocity, row half) of a block has one wave");
+// Velocity-block shapes (chosen per plan): the kWaves / 2 waves of a row
+// half are NXG groups of kVPW x velocities times kWaves / 2 / NXG pairs of y
+// velocities.  Shape 0 is 9 x 4 (the default), shape 1 is 3 x 12 (for
+// small grids of small spread: less padding of the grid to whole blocks).
+constexpr int kNShapes = 2;
+__host__ __device__ constexpr int shape_nxg(int sh) { return sh == 0 ? 3 : 1; }
+__host__ __device__ constexpr int shape_vbx(int sh) { return kVPW * shape_nxg(sh); }
+__host__ __device__ constexpr int shape_vby(int sh) { return kVYW * (kWaves / 2 / shape_nxg(sh)); }
+static_assert(shape_vbx(0) * shape_vby(0) * 2 == kVPW * kVYW * kWaves, "every (velocity, row half) of a block has one wave");
+static_assert(shape_vbx(1) * shape_vby(1) * 2 == kVPW * kVYW * kWaves, "every (velocity, row half) of a block has one wave");
 // LDS staging: the frame region a velocity block needs is the tile widened by
 // the spread of the block's shifts (at most kSMaxX / kSMaxY px) plus 3
 // columns of alignment slack for 16-byte staging.  A fixed window of
@@ -142,8 +149,8 @@ hipError_t launch_quantize(const float* frames, int n, int h, int w, int dtype, 
                            float* part, int nchunk, float* scale, void* q, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_cov(const int* D, int ld, int n, int nv, int size, int* I, hipStream_t s);
-hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, hipStream_t s);
-hipError_t launch_stack_batch(const BatchArgs& b, int groups, hipStream_t s);
+hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, int shape, hipStream_t s);
+hipError_t launch_stack_batch(const BatchArgs& b, int groups, int shape, hipStream_t s);
 hipError_t launch_zero_i32(int* p, int count, hipStream_t s);
 hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int nslot, int kt, int k_max,
                         int nvx, int w, int k_first, int nk, void* cand, int32_t* count,

@@ -303,42 +303,44 @@ __device__ __forceinline__ int coverage(int xlo, int xhi, int ylo, int yhi, int&
 // for k < cnt and repeats the chunk's last frame for the kGeomPad entries
 // after it, so that the frame loop reads entries up to j + 3 without bounds
 // tests.
-constexpr int kGeomInts = 1 + kVBX + kVBY + ((kVBX + kVBY + 1) & 1);  // window byte offset, columns, rows (even)
+template <int SH>
+constexpr int kGeomInts = 1 + shape_vbx(SH) + shape_vby(SH) + ((shape_vbx(SH) + shape_vby(SH) + 1) & 1);  // window byte offset, columns, rows (even)
 constexpr int kGeomPad = 3;  // entries past a chunk's end (repeats of its last frame)
 constexpr int kNBuf = 3;     // staging buffers: frames j and j + 1 readable, j + 2 loading
-static_assert(kVBX == kVPW * (kWaves / 4) && kVBY == 2 * kVYW && kWaves % 4 == 0, "geometry layout assumed below");
 
 // Fill the geometry of frames [f0, f0 + cnt) (one thread per entry).
+template <int SH>
 __device__ __forceinline__ void fill_geometry(const StackArgs& A, int* geo, int f0, int cnt, int a0, int b0, int X0,
                                               int Y0) {
+    constexpr int VBX = shape_vbx(SH), VBY = shape_vby(SH), GI = kGeomInts<SH>;
     const int t = threadIdx.x;
     if (t < cnt + kGeomPad) {
         const int k = min(t, cnt - 1);
         const int i = f0 + k;
         const int* rx = A.DX + (long long)i * A.ldx + a0;
         const int* ry = A.DY + (long long)i * A.ldy + b0;
-        int dx[kVBX], dy[kVBY];
+        int dx[VBX], dy[VBY];
 #pragma unroll
-        for (int j = 0; j < kVBX; ++j) dx[j] = rx[j];
+        for (int j = 0; j < VBX; ++j) dx[j] = rx[j];
 #pragma unroll
-        for (int j = 0; j < kVBY; ++j) dy[j] = ry[j];
+        for (int j = 0; j < VBY; ++j) dy[j] = ry[j];
         int dxmin = dx[0], dymin = dy[0];
 #pragma unroll
-        for (int j = 1; j < kVBX; ++j) dxmin = min(dxmin, dx[j]);
+        for (int j = 1; j < VBX; ++j) dxmin = min(dxmin, dx[j]);
 #pragma unroll
-        for (int j = 1; j < kVBY; ++j) dymin = min(dymin, dy[j]);
+        for (int j = 1; j < VBY; ++j) dymin = min(dymin, dy[j]);
         const int gx0 = X0 + dxmin + A.padL;
         const int xa = gx0 & ~3;
         const int c0 = gx0 - xa;
         const int gy0 = Y0 + dymin + A.padT;
-        int* g = geo + t * kGeomInts;
+        int* g = geo + t * GI;
         // window origin: bytes from the chunk's first frame (< 2^31 by the
         // chunk size)
         g[0] = (int)(((long long)k * A.fstride + (long long)gy0 * A.Wp + xa) * 4);
 #pragma unroll
-        for (int j = 0; j < kVBX; ++j) g[1 + j] = c0 + dx[j] - dxmin;  // LDS column of velocity j
+        for (int j = 0; j < VBX; ++j) g[1 + j] = c0 + dx[j] - dxmin;  // LDS column of velocity j
 #pragma unroll
-        for (int j = 0; j < kVBY; ++j) g[1 + kVBX + j] = (dy[j] - dymin) * kLdsPitch;  // LDS row offset
+        for (int j = 0; j < VBY; ++j) g[1 + VBX + j] = (dy[j] - dymin) * kLdsPitch;  // LDS row offset
     }
 }
 
@@ -567,11 +569,11 @@ __device__ __noinline__ void candidates_from_column(KArgs A, const int* IYr, con
 // else NaN, so that acc * rsm[r] > threshold is exactly the threshold and
 // coverage test (NaN compares false).  xrow is the other row half's boundary
 // row of the same velocity; IYr and RSr start at column row 0 (tile row R0).
-__device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, const float (&acc)[kRowsW],
+__device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, int vby, const float (&acc)[kRowsW],
                                                 const float (&rsm)[kRowsW], int a, int b, int x, bool xin, int lane,
                                                 int h, int Y0, int tile, float* col, const float* xrow,
                                                 const int* IYr, const float* RSr, const double* P, int xlo, int xhi) {
-    const long long kc = (long long)(b - A.vby0 * kVBY) * A.nvx + a;
+    const long long kc = (long long)(b - A.vby0 * vby) * A.nvx + a;
     const long long slot = kc * A.nslot + 2 * tile + h;
     SnCtx c;
     c.IYr = IYr;
@@ -707,8 +709,9 @@ using ic = std::integral_constant<int, V>;
 
 // One work item of the stacking kernels: tile and velocity block number
 // `logical` of the problem A describes (Ap: where a callee reads A).
-template <bool DETECT, bool STAGED>
+template <bool DETECT, bool STAGED, int SH>
 __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int logical) {
+    constexpr int VBX = shape_vbx(SH), VBY = shape_vby(SH), NYP = VBY / kVYW, GI = kGeomInts<SH>;
     // LDS: two staging buffers during the frame loop; afterwards each wave's
     // candidate column and the published boundary rows of every wave
     constexpr int kColFloats = kWaves * kColRows * kWave;
@@ -718,7 +721,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     constexpr int kStageFloats = kNBuf * kLdsBuf + kDMax * kLdsPitch;
     constexpr int kLdsFloats = (kStageFloats > kColFloats + kXchFloats) ? kStageFloats : kColFloats + kXchFloats;
     __shared__ __attribute__((aligned(16))) float lds[kLdsFloats];
-    __shared__ int geo[STAGED ? (kGeomChunk + kGeomPad) * kGeomInts : 1];
+    __shared__ int geo[STAGED ? (kGeomChunk + kGeomPad) * GI : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -726,10 +729,10 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     const int tile = logical / nvb;
     const int vb = logical - tile * nvb;
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
-    const int a0 = (vb % A.nvbx) * kVBX;
-    const int b0 = (A.vby0 + vb / A.nvbx) * kVBY;
-    const int xg = wave / 4;          // which kVPW-group of the block's x velocities
-    const int yp = (wave / 2) % 2;    // which pair of the block's y velocities
+    const int a0 = (vb % A.nvbx) * VBX;
+    const int b0 = (A.vby0 + vb / A.nvbx) * VBY;
+    const int xg = wave / (2 * NYP);  // which kVPW-group of the block's x velocities
+    const int yp = (wave / 2) % NYP;  // which pair of the block's y velocities
     const int h = wave % 2;           // row half
     const int aw = a0 + kVPW * xg;    // this wave's first x velocity
     const int bw = b0 + kVYW * yp;    // this wave's first y velocity
@@ -755,21 +758,21 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         // this wave's geometry of frame j: the LDS row offsets of its two y
         // velocities and the kVPW column offsets, plus the staging window
         // of frame j + 1
-        const int gw_row = 1 + kVBX + kVYW * yp, gw_col = 1 + kVPW * xg;
+        const int gw_row = 1 + VBX + kVYW * yp, gw_col = 1 + kVPW * xg;
         const int hoff = h * kRowsW * kLdsPitch;
         for (int f0 = 0; f0 < A.n; f0 += A.gchunk) {
             const int cnt = min(A.gchunk, A.n - f0);
             // (the previous chunk's last barrier follows every wave's last
             // use of the table; its reads still in flight target staging
             // rows whose values are never used)
-            fill_geometry(A, geo, f0, cnt, a0, b0, X0, Y0);
+            fill_geometry<SH>(A, geo, f0, cnt, a0, b0, X0, Y0);
             const long long rem = (long long)(A.n - f0) * A.fstride * 4;
             const auto rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)(A.pad + (long long)f0 * A.fstride), 0,
                                                                 (int)min(rem, 0x7FFFFFFFll), 0x00020000);
             __syncthreads();
             // prologue: frames 0 and 1 of the chunk into buffers 0 and 1
             stage_frame(rsrc, voff, __builtin_amdgcn_readfirstlane(geo[0]), A.Wp, act, lds, wave);
-            stage_frame(rsrc, voff, __builtin_amdgcn_readfirstlane(geo[kGeomInts]), A.Wp, act, lds + kLdsBuf, wave);
+            stage_frame(rsrc, voff, __builtin_amdgcn_readfirstlane(geo[GI]), A.Wp, act, lds + kLdsBuf, wave);
             // geometry of the frame being added (c), of the frame being read
             // (n), and the window of the frame loaded next
             int r0c = __builtin_amdgcn_readfirstlane(geo[gw_row]);
@@ -777,12 +780,12 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             int colc[kVPW];
 #pragma unroll
             for (int q = 0; q < kVPW; ++q) colc[q] = __builtin_amdgcn_readfirstlane(geo[gw_col + q]);
-            int r0n = __builtin_amdgcn_readfirstlane(geo[kGeomInts + gw_row]);
-            int r1n = __builtin_amdgcn_readfirstlane(geo[kGeomInts + gw_row + 1]);
+            int r0n = __builtin_amdgcn_readfirstlane(geo[GI + gw_row]);
+            int r1n = __builtin_amdgcn_readfirstlane(geo[GI + gw_row + 1]);
             int coln[kVPW];
 #pragma unroll
-            for (int q = 0; q < kVPW; ++q) coln[q] = __builtin_amdgcn_readfirstlane(geo[kGeomInts + gw_col + q]);
-            int soff2 = __builtin_amdgcn_readfirstlane(geo[2 * kGeomInts]);
+            for (int q = 0; q < kVPW; ++q) coln[q] = __builtin_amdgcn_readfirstlane(geo[GI + gw_col + q]);
+            int soff2 = __builtin_amdgcn_readfirstlane(geo[2 * GI]);
             stage_wait();
             __syncthreads();
             if (!busy) {
@@ -790,7 +793,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
                 int bl = 2;
                 for (int j = 0; j < cnt; ++j) {
                     stage_frame(rsrc, voff, soff2, A.Wp, act, lds + bl * kLdsBuf, wave);
-                    soff2 = __builtin_amdgcn_readfirstlane(geo[(j + 3) * kGeomInts]);
+                    soff2 = __builtin_amdgcn_readfirstlane(geo[(j + 3) * GI]);
                     bl = bl == kNBuf - 1 ? 0 : bl + 1;
                     stage_wait();
                     barrier_keep_reads();
@@ -808,12 +811,12 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
                 // repeat of its last frame, never read)
                 stage_frame(rsrc, voff, soff2, A.Wp, act, lds + bl * kLdsBuf, wave);
                 // geometry of frame j + 2 and the window of frame j + 3
-                const int* g2 = geo + (j + 2) * kGeomInts;
+                const int* g2 = geo + (j + 2) * GI;
                 const int nr0 = g2[gw_row], nr1 = g2[gw_row + 1];
                 int ncol[kVPW];
 #pragma unroll
                 for (int q = 0; q < kVPW; ++q) ncol[q] = g2[gw_col + q];
-                const int nsoff = g2[kGeomInts];
+                const int nsoff = g2[GI];
                 // frame j: the second x velocity's rows, then the adds, one
                 // block per read pattern, each updating the sums in place (a
                 // chain of two-way branches keeps every sum in one register)
@@ -882,11 +885,11 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     // variance prefix (when it fits) and each lane's x intervals.
     // (sIY and sRS have one row before tile row 0 of the first velocity
     // row, so that a column starting at tile row -1 has a valid base)
-    __shared__ int sIYa[(kVBY * kRows + 1) * 2];
-    __shared__ float sRSa[DETECT ? kVBY * kRows + 1 : 2];
+    __shared__ int sIYa[(VBY * kRows + 1) * 2];
+    __shared__ float sRSa[DETECT ? VBY * kRows + 1 : 2];
     int* const sIY = sIYa + 2;
     float* const sRS = sRSa + 1;
-    __shared__ __attribute__((aligned(16))) float sRM[DETECT ? kVBY * kRows : 4];
+    __shared__ __attribute__((aligned(16))) float sRM[DETECT ? VBY * kRows : 4];
     __shared__ double sP[DETECT ? kPLds : 1];
     const bool need_c = DETECT || A.mean || A.cov != nullptr;
     int xlo[kVPW], xhi[kVPW];
@@ -897,7 +900,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         if (need_c && xin && aw + q < A.nvx) load_iv(A.IX, (long long)(aw + q) * A.w + x, xlo[q], xhi[q]);
     }
     if (need_c) {
-        for (int e = tid; e < kVBY * kRows; e += kThreads) {
+        for (int e = tid; e < VBY * kRows; e += kThreads) {
             const int bb = b0 + e / kRows, y = Y0 + e % kRows;
             int lo = A.n, hi = -1;
             if (bb < A.nvy && y >= 0 && y < A.h) load_iv(A.IY, (long long)bb * A.h + y, lo, hi);
@@ -910,7 +913,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         if (p_lds)
             for (int e = tid; e <= A.n; e += kThreads) sP[e] = A.P[e];
         // per (velocity row, tile row): 1/sqrt(V) over the row's y interval
-        for (int e = tid; e < kVBY * kRows; e += kThreads) {
+        for (int e = tid; e < VBY * kRows; e += kThreads) {
             const int bb = b0 + e / kRows, y = Y0 + e % kRows;
             int lo = A.n, hi = -1;
             if (bb < A.nvy && y >= 0 && y < A.h) load_iv(A.IY, (long long)bb * A.h + y, lo, hi);
@@ -988,7 +991,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
                     rsm[4 * k + 2] = t.z;
                     rsm[4 * k + 3] = t.w;
                 }
-                detect_epilogue(A, Ap, acc[q][s], rsm, aw + q, bb, x, xin, lane, h, Y0, tile, col,
+                detect_epilogue(A, Ap, VBY, acc[q][s], rsm, aw + q, bb, x, xin, lane, h, Y0, tile, col,
                                 xin_rows + (q * kVYW + s) * kWave, sIY + (vr * kRows + R0) * 2, sRS + vr * kRows + R0,
                                 P, xlo[q], xhi[q]);
             }
@@ -1011,15 +1014,16 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     }
 }
 
-template <bool DETECT, bool STAGED>
+template <bool DETECT, bool STAGED, int SH>
 __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
-    stack_item<DETECT, STAGED>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(), xcd_remap(blockIdx.x, gridDim.x));
+    stack_item<DETECT, STAGED, SH>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(), xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Persistent form for a batch of detect problems (all staged): each
 // workgroup takes work items from its queue until the queue is empty, then
 // helps the other queues; an item is a (tile, velocity block) of one
 // problem, found by binary search of the problems' first items.
+template <int SH>
 __global__ __launch_bounds__(kThreads) void k_stack_batch(const BatchArgs B) {
     // the table is read-only during the launch: read it through the constant
     // address space, so that the (uniform) loads are scalar
@@ -1046,7 +1050,7 @@ __global__ __launch_bounds__(kThreads) void k_stack_batch(const BatchArgs B) {
                     hi = mid - 1;
             }
             const StackArgs* Ap = (const StackArgs*)((CArgs*)B.tab + lo);
-            stack_item<true, true>(*Ap, Ap, g - B.start[lo]);
+            stack_item<true, true, SH>(*Ap, Ap, g - B.start[lo]);
             // every wave has finished the item before the next one reuses LDS
             __syncthreads();
         }
@@ -1223,26 +1227,39 @@ hipError_t launch_cov(const int* D, int ld, int n, int nv, int size, int* I, hip
     return hipGetLastError();
 }
 
-hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, hipStream_t s) {
-    const long long groups = (long long)a.tiles_x * a.tiles_y * a.nvbx * a.nvby;
-    const dim3 grid((unsigned)groups), block(kThreads);
+template <int SH>
+void launch_stack_shape(const StackArgs& a, bool detect, bool staged, dim3 grid, hipStream_t s) {
+    const dim3 block(kThreads);
     if (detect) {
         if (staged)
-            hipLaunchKernelGGL((k_stack<true, true>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_stack<true, true, SH>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((k_stack<true, false>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_stack<true, false, SH>), grid, block, 0, s, a);
     } else {
         if (staged)
-            hipLaunchKernelGGL((k_stack<false, true>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_stack<false, true, SH>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((k_stack<false, false>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_stack<false, false, SH>), grid, block, 0, s, a);
     }
+}
+
+hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, int shape, hipStream_t s) {
+    const long long groups = (long long)a.tiles_x * a.tiles_y * a.nvbx * a.nvby;
+    const dim3 grid((unsigned)groups);
+    static_assert(kNShapes == 2, "one instantiation per shape");
+    if (shape == 1)
+        launch_stack_shape<1>(a, detect, staged, grid, s);
+    else
+        launch_stack_shape<0>(a, detect, staged, grid, s);
     return hipGetLastError();
 }
 
-hipError_t launch_stack_batch(const BatchArgs& b, int groups, hipStream_t s) {
+hipError_t launch_stack_batch(const BatchArgs& b, int groups, int shape, hipStream_t s) {
     if (groups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stack_batch, dim3((unsigned)groups), dim3(kThreads), 0, s, b);
+    if (shape == 1)
+        hipLaunchKernelGGL(k_stack_batch<1>, dim3((unsigned)groups), dim3(kThreads), 0, s, b);
+    else
+        hipLaunchKernelGGL(k_stack_batch<0>, dim3((unsigned)groups), dim3(kThreads), 0, s, b);
     return hipGetLastError();
 }
 

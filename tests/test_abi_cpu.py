@@ -291,3 +291,19 @@ def test_batch_argument_errors(lib):
     assert lib.sst_batch_create(nulls, 2, FAKE, 1 << 20, None, None) == B.SST_E_ARG
     assert lib.sst_batch_run(None, FAKE, FAKE, None, FAKE, FAKE, None) == B.SST_E_ARG
     lib.sst_batch_destroy(None)
+
+
+def test_shape_argument_errors(lib):
+    vbx, vby = ctypes.c_int(0), ctypes.c_int(0)
+    nsh = lib.sst_shape_info(0, ctypes.byref(vbx), ctypes.byref(vby))
+    assert nsh >= 2 and (vbx.value, vby.value) == (9, 4)
+    assert lib.sst_shape_info(nsh, None, None) == B.SST_E_ARG
+    assert lib.sst_shape_info(-1, None, None) == B.SST_E_ARG
+    t = np.arange(4, dtype=np.float64)
+    v = np.array([0.0, 1.0])
+    assert lib.sst_workspace_bytes_shape(B.SST_OP_DETECT, nsh, 4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 4) == 0
+    assert lib.sst_workspace_bytes_shape(B.SST_OP_DETECT, 1, 4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 4) > 0
+    h = ctypes.c_void_p()
+    assert lib.sst_plan_detect_shape(nsh, 4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 5.0, 0, 4, FAKE, 1 << 40, None,
+                                     ctypes.byref(h)) == B.SST_E_ARG
+    assert lib.sst_plan_info(None, None, None, None) == B.SST_E_ARG
