@@ -172,7 +172,8 @@ def batch_bench(torch, sst, args):
     """Many fields per call.  batch: the 16 uneven fields of the batching
     workload (24-160 frames, 512^2-2048^2, grids 41^2-121^2); tinybatch: 64
     fields of the small field's shape (32 x 128^2, 21^2 grid).  Each field is
-    prepared once (sst_plan_detect); timed are (a) plain sst_detect calls, one
+    prepared once, with the velocity-block shape the tuner picks for its
+    geometry (tune_plan); timed are (a) plain sst_detect calls, one
     per field, (b) the prepared runs enqueued back to back, (c) the same runs
     captured in one graph and replayed, (d) the runs spread over 4 streams,
     (e) (d) captured in one graph, (f) one persistent stacking launch per
@@ -190,22 +191,26 @@ def batch_bench(torch, sst, args):
     for sp in sorted(specs, key=lambda s: -s.updates):  # largest first
         f = sp.make()
         fr = torch.from_numpy(f.frames).to(dev)
-        plan = sst.sst_plan_detect(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max)
+        # the velocity-block shape is picked per geometry by the tuner
+        plan = sst.tune_plan(fr, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max)
         out = (torch.empty((plan.nk, f.k_max, 8), dtype=torch.int32, device=dev),
                torch.empty((plan.nk,), dtype=torch.int32, device=dev))
+        # the one-shot calls use the default shape: a workspace of their own
+        ews = torch.empty(sst.sst_workspace_bytes(sst.SST_OP_DETECT, f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy,
+                                                  f.k_max), dtype=torch.uint8, device=dev)
         fields.append((f.name, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, fr, plan, out,
-                       sp.updates))
+                       ews, sp.updates))
         del f
         if args.workload == "batch":
             print(f"prepared {sp.name}", file=sys.stderr, flush=True)
     total = sum(x[-1] for x in fields)
 
     def eager():
-        for (_, t, t_ref, vx, vy, thr, cmin, kmax, fr, plan, (c, n), _) in fields:
-            sst.sst_detect(fr, t, t_ref, vx, vy, thr, cmin, kmax, ws=plan.ws, cand=c, count=n)
+        for (_, t, t_ref, vx, vy, thr, cmin, kmax, fr, plan, (c, n), ews, _) in fields:
+            sst.sst_detect(fr, t, t_ref, vx, vy, thr, cmin, kmax, ws=ews, cand=c, count=n)
 
     def runs():
-        for (*_, fr, plan, (c, n), _) in fields:
+        for (*_, fr, plan, (c, n), _ews, _) in fields:
             plan.run(fr, cand=c, count=n)
 
     # the same runs spread over 4 streams (fields round-robin, default
@@ -216,7 +221,7 @@ def batch_bench(torch, sst, args):
         cur = torch.cuda.current_stream()
         for st in streams:
             st.wait_stream(cur)
-        for k, (*_, fr, plan, (c, n), _) in enumerate(fields):
+        for k, (*_, fr, plan, (c, n), _ews, _) in enumerate(fields):
             with torch.cuda.stream(streams[k % len(streams)]):
                 plan.run(fr, cand=c, count=n)
         for st in streams:
@@ -266,7 +271,8 @@ def batch_bench(torch, sst, args):
                       "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": best * 1e3, "higher_is_better": True,
                       "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": f"{args.workload}: {len(fields)} fields, {total:.3g} updates",
-                                 "fields": [x[0] for x in fields]},
+                                 "fields": [x[0] for x in fields],
+                                 "shapes": [sst.sst_shapes()[x[9].shape] for x in fields]},
                       "ms_eager_calls": t_eager * 1e3, "ms_prepared_runs": t_runs * 1e3,
                       "ms_graph_replay": t_graph * 1e3, "ms_prepared_runs_4_streams": t_par * 1e3,
                       "ms_graph_replay_4_streams": t_graph4 * 1e3, "ms_persistent_batch": t_batch * 1e3,
