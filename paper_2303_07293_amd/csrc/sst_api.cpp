@@ -109,8 +109,9 @@ struct Plan {
     int shape = 0, vbx = 0, vby = 0;  // velocity-block shape
     int kt = 0, rows_per_chunk = 0, nchunk = 0;
     std::vector<int32_t> DX, DY;
+    std::vector<int32_t> G;  // per (velocity block, frame) staging geometry, kGeomRec ints
     // workspace offsets (bytes)
-    size_t o_tab = 0, o_part = 0, o_b = 0, o_s2 = 0, o_P = 0, o_b32 = 0, o_sdev = 0;
+    size_t o_geom = 0, o_tab = 0, o_part = 0, o_b = 0, o_s2 = 0, o_P = 0, o_b32 = 0, o_sdev = 0;
     size_t o_ix = 0, o_iy = 0, o_pad = 0, o_tcount = 0, o_ent = 0, o_qpart = 0, o_dt = 0, total = 0;
 };
 
@@ -200,8 +201,26 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
     const int need_h = std::max(Y0max + dymax + kRows, Y0max + dymax + kLdsRows) + p.padT;
     p.Wp = (int)align_up((size_t)std::max(4, need_w), 16);
     p.Hp = std::max(1, need_h);
+    // Staging geometry of every velocity block and frame, the same for all
+    // tiles (tile origins are multiples of 4 columns): the byte offset of the
+    // window from the tile's origin in the frame's padded copy, then the LDS
+    // column of each x velocity and the LDS row offset of each y velocity.
+    p.G.assign((size_t)p.nvbx * p.nvby * n * kGeomRec, 0);
+    for (int by = 0; by < p.nvby; ++by)
+        for (int bx = 0; bx < p.nvbx; ++bx)
+            for (int i = 0; i < n; ++i) {
+                const int32_t* rx = &p.DX[(size_t)i * p.ldx + (size_t)bx * p.vbx];
+                const int32_t* ry = &p.DY[(size_t)i * p.ldy + (size_t)by * p.vby];
+                const int mx = *std::min_element(rx, rx + p.vbx), my = *std::min_element(ry, ry + p.vby);
+                const int gx = mx + p.padL, xa = gx & ~3;
+                int32_t* g = &p.G[(((size_t)by * p.nvbx + bx) * n + i) * kGeomRec];
+                g[0] = (int32_t)((((long long)(my + p.padT)) * p.Wp + xa) * 4);
+                for (int j = 0; j < p.vbx; ++j) g[1 + j] = gx - xa + rx[j] - mx;
+                for (int j = 0; j < p.vby; ++j) g[1 + p.vbx + j] = (ry[j] - my) * kLdsPitch;
+            }
 
     p.o_tab = take(cur, ((size_t)n * p.ldx + (size_t)n * p.ldy) * sizeof(int32_t));
+    p.o_geom = take(cur, p.G.size() * sizeof(int32_t));
     p.o_b32 = take(cur, (size_t)n * sizeof(float));
     p.o_ix = take(cur, (size_t)nvx * w * 2 * sizeof(int32_t));
     p.o_iy = take(cur, (size_t)nvy * h * 2 * sizeof(int32_t));
@@ -251,7 +270,8 @@ int upload_tables(const Plan& p, const double* bg, void* ws, hipStream_t s) {
     std::vector<char> host(p.o_b32 - p.o_tab + (size_t)p.n * sizeof(float), 0);
     std::memcpy(host.data(), p.DX.data(), nx * sizeof(int32_t));
     std::memcpy(host.data() + nx * sizeof(int32_t), p.DY.data(), ny * sizeof(int32_t));
-    size_t bytes = (nx + ny) * sizeof(int32_t);
+    std::memcpy(host.data() + (p.o_geom - p.o_tab), p.G.data(), p.G.size() * sizeof(int32_t));
+    size_t bytes = p.o_geom - p.o_tab + p.G.size() * sizeof(int32_t);
     if (bg) {
         float* f = reinterpret_cast<float*>(host.data() + (p.o_b32 - p.o_tab));
         for (int i = 0; i < p.n; ++i) f[i] = (float)bg[i];
@@ -277,6 +297,7 @@ StackArgs stack_args(const Plan& p, void* ws) {
     a.Wp = p.Wp;
     a.padL = p.padL;
     a.padT = p.padT;
+    a.geom = at<int>(ws, p.o_geom);
     a.DX = at<int>(ws, p.o_tab);
     a.DY = at<int>(ws, p.o_tab + (size_t)p.n * p.ldx * sizeof(int32_t));
     a.ldx = p.ldx;

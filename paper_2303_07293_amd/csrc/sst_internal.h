@@ -63,7 +63,8 @@ constexpr int kStatChunk = 8192;  // pixels per frame-statistics workgroup
 constexpr int kMaxK = 1024;       // largest k_max accepted
 constexpr int kMergeLds = 2048;   // entries ranked in LDS by the merge kernel
 constexpr int kPLds = 1024;       // variance-prefix entries the stack kernel keeps in LDS
-constexpr int kGeomChunk = 256;   // frames whose block geometry the stack kernel keeps in LDS
+constexpr int kGeomChunk = 256;   // frames per buffer descriptor of the stack kernel (at most)
+constexpr int kGeomRec = 16;      // ints per (velocity block, frame) geometry record
 
 // One candidate kept by a (tile, velocity) before the per-velocity merge.
 struct Entry {
@@ -94,6 +95,7 @@ struct StackArgs {
     long long fstride;  // Hp * Wp
     int n, h, w;
     int Wp, padL, padT;
+    const int* geom;  // [nvby][nvbx][n][kGeomRec] staging geometry of each velocity block and frame
     const int* DX;  // [n][ldx] clamped x shifts, columns >= nvx repeat column nvx-1
     const int* DY;  // [n][ldy]
     int ldx, ldy;

@@ -293,56 +293,17 @@ __device__ __forceinline__ int coverage(int xlo, int xhi, int ylo, int yhi, int&
 }
 
 // -------------------------------------------------------------- stacking
-// Per-frame geometry of a workgroup's velocity block, kept in LDS for a
-// chunk of at most kGeomChunk frames (fewer when a chunk's frames would span
-// more than 2^31 bytes of the padded copy: every staging read of a chunk is
-// a 31-bit byte offset from one buffer descriptor).  For frame i the staged
-// window is the kStageW x kLdsRows region of the padded copy whose origin is
-// the 16-byte aligned column at or left of X0 + (smallest x shift of the
-// block) and the row Y0 + (smallest y shift).  Entry k holds frame f0 + k
-// for k < cnt and repeats the chunk's last frame for the kGeomPad entries
-// after it, so that the frame loop reads entries up to j + 3 without bounds
-// tests.
-template <int SH>
-constexpr int kGeomInts = 1 + shape_vbx(SH) + shape_vby(SH) + ((shape_vbx(SH) + shape_vby(SH) + 1) & 1);  // window byte offset, columns, rows (even)
-constexpr int kGeomPad = 3;  // entries past a chunk's end (repeats of its last frame)
-constexpr int kNBuf = 3;     // staging buffers: frames j and j + 1 readable, j + 2 loading
-
-// Fill the geometry of frames [f0, f0 + cnt) (one thread per entry).
-template <int SH>
-__device__ __forceinline__ void fill_geometry(const StackArgs& A, int* geo, int f0, int cnt, int a0, int b0, int X0,
-                                              int Y0) {
-    constexpr int VBX = shape_vbx(SH), VBY = shape_vby(SH), GI = kGeomInts<SH>;
-    const int t = threadIdx.x;
-    if (t < cnt + kGeomPad) {
-        const int k = min(t, cnt - 1);
-        const int i = f0 + k;
-        const int* rx = A.DX + (long long)i * A.ldx + a0;
-        const int* ry = A.DY + (long long)i * A.ldy + b0;
-        int dx[VBX], dy[VBY];
-#pragma unroll
-        for (int j = 0; j < VBX; ++j) dx[j] = rx[j];
-#pragma unroll
-        for (int j = 0; j < VBY; ++j) dy[j] = ry[j];
-        int dxmin = dx[0], dymin = dy[0];
-#pragma unroll
-        for (int j = 1; j < VBX; ++j) dxmin = min(dxmin, dx[j]);
-#pragma unroll
-        for (int j = 1; j < VBY; ++j) dymin = min(dymin, dy[j]);
-        const int gx0 = X0 + dxmin + A.padL;
-        const int xa = gx0 & ~3;
-        const int c0 = gx0 - xa;
-        const int gy0 = Y0 + dymin + A.padT;
-        int* g = geo + t * GI;
-        // window origin: bytes from the chunk's first frame (< 2^31 by the
-        // chunk size)
-        g[0] = (int)(((long long)k * A.fstride + (long long)gy0 * A.Wp + xa) * 4);
-#pragma unroll
-        for (int j = 0; j < VBX; ++j) g[1 + j] = c0 + dx[j] - dxmin;  // LDS column of velocity j
-#pragma unroll
-        for (int j = 0; j < VBY; ++j) g[1 + VBX + j] = (dy[j] - dymin) * kLdsPitch;  // LDS row offset
-    }
-}
+// Per-frame geometry of a velocity block comes from a table the host builds
+// with the shift tables (the same for every tile, whose origins are
+// multiples of 4 columns): for frame i the staged window is the kStageW x
+// kLdsRows region of the padded copy whose origin is the 16-byte aligned
+// column at or left of X0 + (smallest x shift of the block) and the row Y0 +
+// (smallest y shift); its record holds the window's byte offset from the
+// tile's origin, the LDS column of each x velocity and the LDS row offset of
+// each y velocity.  The frames of one buffer descriptor (a chunk of at most
+// kGeomChunk frames, fewer when they would span more than 2^31 bytes of the
+// padded copy) are addressed by 31-bit byte offsets.
+constexpr int kNBuf = 3;  // staging buffers: frames j and j + 1 readable, j + 2 loading
 
 constexpr int kC4 = kStageW / 4;  // float4 chunks per staged row
 static_assert(kC4 <= 32 && kLdsRows % (2 * kWaves) == 0, "two staged rows per wave instruction");
@@ -711,7 +672,8 @@ using ic = std::integral_constant<int, V>;
 // `logical` of the problem A describes (Ap: where a callee reads A).
 template <bool DETECT, bool STAGED, int SH>
 __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int logical) {
-    constexpr int VBX = shape_vbx(SH), VBY = shape_vby(SH), NYP = VBY / kVYW, GI = kGeomInts<SH>;
+    constexpr int VBX = shape_vbx(SH), VBY = shape_vby(SH), NYP = VBY / kVYW;
+    static_assert(1 + VBX + VBY <= kGeomRec, "geometry record");
     // LDS: two staging buffers during the frame loop; afterwards each wave's
     // candidate column and the published boundary rows of every wave
     constexpr int kColFloats = kWaves * kColRows * kWave;
@@ -721,7 +683,6 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     constexpr int kStageFloats = kNBuf * kLdsBuf + kDMax * kLdsPitch;
     constexpr int kLdsFloats = (kStageFloats > kColFloats + kXchFloats) ? kStageFloats : kColFloats + kXchFloats;
     __shared__ __attribute__((aligned(16))) float lds[kLdsFloats];
-    __shared__ int geo[STAGED ? (kGeomChunk + kGeomPad) * GI : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -755,45 +716,65 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         const int scol = lane & 31;               // float4 column
         const bool act = scol < kC4;
         const int voff = (srow * A.Wp + 4 * scol) * 4;  // bytes, per lane
-        // this wave's geometry of frame j: the LDS row offsets of its two y
-        // velocities and the kVPW column offsets, plus the staging window
-        // of frame j + 1
+        // this wave's geometry of a frame (its record in the block's table):
+        // the LDS row offsets of its two y velocities and the kVPW column
+        // offsets, read with buffer loads (counted by vmcnt, like the
+        // staging loads, so that LDS waits stay partial) and made scalar
         const int gw_row = 1 + VBX + kVYW * yp, gw_col = 1 + kVPW * xg;
         const int hoff = h * kRowsW * kLdsPitch;
+        const int tbase = (Y0 * A.Wp + X0) * 4;  // bytes of the tile's origin in a padded frame
+        const long long blk = (long long)((A.vby0 + vb / A.nvbx) * A.nvbx + vb % A.nvbx) * A.n;
         for (int f0 = 0; f0 < A.n; f0 += A.gchunk) {
             const int cnt = min(A.gchunk, A.n - f0);
-            // (the previous chunk's last barrier follows every wave's last
-            // use of the table; its reads still in flight target staging
-            // rows whose values are never used)
-            fill_geometry<SH>(A, geo, f0, cnt, a0, b0, X0, Y0);
+            const auto grs = __builtin_amdgcn_make_buffer_rsrc((void*)(A.geom + (blk + f0) * kGeomRec), 0,
+                                                               cnt * kGeomRec * 4, 0x00020000);
+            // record of frame k of the chunk: past the chunk's end its last
+            // frame (staged but never read)
+            auto recb = [&](int k) __attribute__((always_inline)) { return min(k, cnt - 1) * (kGeomRec * 4); };
+            auto ld_rows = [&](int k) __attribute__((always_inline)) {
+                return __builtin_amdgcn_raw_buffer_load_b64(grs, 0, recb(k) + gw_row * 4, 0);
+            };
+            auto ld_cols = [&](int k) __attribute__((always_inline)) {
+                return __builtin_amdgcn_raw_buffer_load_b128(grs, 0, recb(k) + gw_col * 4, 0);
+            };
+            auto ld_win = [&](int k) __attribute__((always_inline)) {
+                return __builtin_amdgcn_raw_buffer_load_b32(grs, 0, recb(k), 0);
+            };
+            // byte offset of frame k's window from the chunk's first frame
+            // (< 2^31 by the chunk size)
+            auto win = [&](int k, int rel) __attribute__((always_inline)) {
+                return (int)((long long)min(k, cnt - 1) * A.fstride * 4) + tbase + __builtin_amdgcn_readfirstlane((int)rel);
+            };
             const long long rem = (long long)(A.n - f0) * A.fstride * 4;
             const auto rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)(A.pad + (long long)f0 * A.fstride), 0,
                                                                 (int)min(rem, 0x7FFFFFFFll), 0x00020000);
-            __syncthreads();
+            // (the previous chunk's last barrier follows every wave's last
+            // use of its staged frames; its reads still in flight target
+            // staging rows whose values are never used)
             // prologue: frames 0 and 1 of the chunk into buffers 0 and 1
-            stage_frame(rsrc, voff, __builtin_amdgcn_readfirstlane(geo[0]), A.Wp, act, lds, wave);
-            stage_frame(rsrc, voff, __builtin_amdgcn_readfirstlane(geo[GI]), A.Wp, act, lds + kLdsBuf, wave);
+            stage_frame(rsrc, voff, win(0, ld_win(0)), A.Wp, act, lds, wave);
+            stage_frame(rsrc, voff, win(1, ld_win(1)), A.Wp, act, lds + kLdsBuf, wave);
             // geometry of the frame being added (c), of the frame being read
             // (n), and the window of the frame loaded next
-            int r0c = __builtin_amdgcn_readfirstlane(geo[gw_row]);
-            int r1c = __builtin_amdgcn_readfirstlane(geo[gw_row + 1]);
-            int colc[kVPW];
-#pragma unroll
-            for (int q = 0; q < kVPW; ++q) colc[q] = __builtin_amdgcn_readfirstlane(geo[gw_col + q]);
-            int r0n = __builtin_amdgcn_readfirstlane(geo[GI + gw_row]);
-            int r1n = __builtin_amdgcn_readfirstlane(geo[GI + gw_row + 1]);
-            int coln[kVPW];
-#pragma unroll
-            for (int q = 0; q < kVPW; ++q) coln[q] = __builtin_amdgcn_readfirstlane(geo[GI + gw_col + q]);
-            int soff2 = __builtin_amdgcn_readfirstlane(geo[2 * GI]);
+            const auto rw0 = ld_rows(0), rw1 = ld_rows(1);
+            const auto cl0 = ld_cols(0), cl1 = ld_cols(1);
+            int soff2 = win(2, ld_win(2));
+            int r0c = __builtin_amdgcn_readfirstlane((int)rw0[0]), r1c = __builtin_amdgcn_readfirstlane((int)rw0[1]);
+            int r0n = __builtin_amdgcn_readfirstlane((int)rw1[0]), r1n = __builtin_amdgcn_readfirstlane((int)rw1[1]);
+            int colc[kVPW] = {__builtin_amdgcn_readfirstlane((int)cl0[0]), __builtin_amdgcn_readfirstlane((int)cl0[1]),
+                              __builtin_amdgcn_readfirstlane((int)cl0[2])};
+            int coln[kVPW] = {__builtin_amdgcn_readfirstlane((int)cl1[0]), __builtin_amdgcn_readfirstlane((int)cl1[1]),
+                              __builtin_amdgcn_readfirstlane((int)cl1[2])};
+            static_assert(kVPW == 3, "three columns per record read");
             stage_wait();
             __syncthreads();
             if (!busy) {
                 // the same staging loads and barriers as below, no adds
                 int bl = 2;
                 for (int j = 0; j < cnt; ++j) {
+                    const int nw = ld_win(j + 3);
                     stage_frame(rsrc, voff, soff2, A.Wp, act, lds + bl * kLdsBuf, wave);
-                    soff2 = __builtin_amdgcn_readfirstlane(geo[(j + 3) * GI]);
+                    soff2 = win(j + 3, nw);
                     bl = bl == kNBuf - 1 ? 0 : bl + 1;
                     stage_wait();
                     barrier_keep_reads();
@@ -806,17 +787,16 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             for (int j = 0; j < cnt; ++j) {
                 const int bn = bc == kNBuf - 1 ? 0 : bc + 1;
                 const int bl = bn == kNBuf - 1 ? 0 : bn + 1;
+                // geometry of frame j + 2 and the window of frame j + 3
+                // (issued before the staging loads, so that waiting for them
+                // leaves those in flight)
+                const auto nrw = ld_rows(j + 2);
+                const auto ncl = ld_cols(j + 2);
+                const int nw = ld_win(j + 3);
                 // load frame j + 2 into the buffer whose frame (j - 1) was
                 // consumed before the last barrier (past the chunk's end: a
                 // repeat of its last frame, never read)
                 stage_frame(rsrc, voff, soff2, A.Wp, act, lds + bl * kLdsBuf, wave);
-                // geometry of frame j + 2 and the window of frame j + 3
-                const int* g2 = geo + (j + 2) * GI;
-                const int nr0 = g2[gw_row], nr1 = g2[gw_row + 1];
-                int ncol[kVPW];
-#pragma unroll
-                for (int q = 0; q < kVPW; ++q) ncol[q] = g2[gw_col + q];
-                const int nsoff = g2[GI];
                 // frame j: the second x velocity's rows, then the adds, one
                 // block per read pattern, each updating the sums in place (a
                 // chain of two-way branches keeps every sum in one register)
@@ -840,17 +820,18 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
                 }
                 static_assert(kDMax == 4, "one case per shared-read distance");
                 // the first x velocity's rows of frame j + 1, in flight
-                // across the barrier
+                // across the barrier, then the geometry moves on
                 read_rows_q(lds + bn * kLdsBuf + min(r0n, r1n) + hoff + lane, coln[0], v[0]);
                 r0c = r0n;
                 r1c = r1n;
 #pragma unroll
                 for (int q = 0; q < kVPW; ++q) colc[q] = coln[q];
-                r0n = __builtin_amdgcn_readfirstlane(nr0);
-                r1n = __builtin_amdgcn_readfirstlane(nr1);
-#pragma unroll
-                for (int q = 0; q < kVPW; ++q) coln[q] = __builtin_amdgcn_readfirstlane(ncol[q]);
-                soff2 = __builtin_amdgcn_readfirstlane(nsoff);
+                r0n = __builtin_amdgcn_readfirstlane((int)nrw[0]);
+                r1n = __builtin_amdgcn_readfirstlane((int)nrw[1]);
+                coln[0] = __builtin_amdgcn_readfirstlane((int)ncl[0]);
+                coln[1] = __builtin_amdgcn_readfirstlane((int)ncl[1]);
+                coln[2] = __builtin_amdgcn_readfirstlane((int)ncl[2]);
+                soff2 = win(j + 3, nw);
                 bc = bn;
                 stage_wait();
                 barrier_keep_reads();
