@@ -351,9 +351,14 @@ __device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70
 constexpr int kColRows = kRowsW + 2;
 constexpr unsigned kEmitRows = ((1u << (kColRows - 1)) - 1u) & ~1u;  // column rows 1 .. kColRows - 2
 
+// LDS and global pointers by address space, so that a function that is not
+// inlined still reads LDS with LDS instructions (not flat ones)
+typedef const __attribute__((address_space(3))) int LInt;
+typedef const __attribute__((address_space(3))) float LFloat;
+
 struct SnCtx {
-    const int* IYr;    // [kColRows][2] y coverage intervals of the column's rows
-    const float* RSr;  // [kColRows] 1/sqrt(V) of a pixel whose x samples are all inside
+    LInt* IYr;    // [kColRows][2] y coverage intervals of the column's rows
+    LFloat* RSr;  // [kColRows] 1/sqrt(V) of a pixel whose x samples are all inside
     const double* P;   // prefix sums of the frame variances
     int n, xlo, xhi;
     bool xfull;        // this lane's column sees every frame in x
@@ -389,9 +394,11 @@ __device__ __forceinline__ float sn_direct(KArgs A, const double* P, int a, int 
     load_iv(A->IX, (long long)a * A->w + x, xlo, xhi);
     load_iv(A->IY, (long long)b * A->h + y, ylo, yhi);
     if (coverage(xlo, xhi, ylo, yhi, lo, hi) <= 0) return -INFINITY;
-    const float* pad = A->pad;
-    const int* DX = A->DX;
-    const int* DY = A->DY;
+    typedef const __attribute__((address_space(1))) float GFloat;
+    typedef const __attribute__((address_space(1))) int GInt;
+    GFloat* pad = (GFloat*)A->pad;
+    GInt* DX = (GInt*)A->DX;
+    GInt* DY = (GInt*)A->DY;
     const long long fstride = A->fstride;
     const int Wp = A->Wp, ldx = A->ldx, ldy = A->ldy, n = A->n;
     const int x0 = x + A->padL, y0 = y + A->padT;
@@ -410,9 +417,9 @@ __device__ __forceinline__ float sn_direct(KArgs A, const double* P, int a, int 
 // fl marks the rows (1 .. kColRows - 2) that pass threshold and coverage;
 // orow is the column row outside the tile (0 or kColRows - 1).  The
 // (tile, velocity, row half) writes its count and kept entries to slot.
-__device__ __noinline__ void candidates_from_column(KArgs A, const int* IYr, const float* RSr, const double* P,
+__device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* RSr, const double* P,
                                                     int xlo, int xhi, int a, int b, long long slot,
-                                                    const float* col, unsigned fl, int lane, int x, int Yc,
+                                                    LFloat* col, unsigned fl, int lane, int x, int Yc,
                                                     int orow) {
     SnCtx c;
     c.IYr = IYr;
@@ -444,7 +451,8 @@ __device__ __noinline__ void candidates_from_column(KArgs A, const int* IYr, con
     float Sm = sn_col(0), S0 = sn_col(1);
     float Lm = left(Sm), Rm = right(Sm);
     float L0 = left(S0), R0 = right(S0);
-#pragma unroll 1
+    // (unrolled: the LDS reads of later rows are issued early)
+#pragma unroll
     for (int r = 1; r <= kColRows - 2; ++r) {
         const float Sp = sn_col(r + 1);
         const float Lp = left(Sp), Rp = right(Sp);
@@ -481,8 +489,9 @@ __device__ __noinline__ void candidates_from_column(KArgs A, const int* IYr, con
         }
         if (!ok) cm &= ~(1u << r);
     }
+    typedef __attribute__((address_space(1))) int32_t GInt;
     const int total = wave_sum_i32(__popc(cm));
-    if (lane == 0) A->tcount[slot] = total;
+    if (lane == 0) ((GInt*)A->tcount)[slot] = total;
     if (total == 0) return;
     Entry* E = A->ent + slot * (long long)kt;
     if (total <= kt) {
@@ -537,8 +546,8 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, in
     const long long kc = (long long)(b - A.vby0 * vby) * A.nvx + a;
     const long long slot = kc * A.nslot + 2 * tile + h;
     SnCtx c;
-    c.IYr = IYr;
-    c.RSr = RSr;
+    c.IYr = (LInt*)IYr;
+    c.RSr = (LFloat*)RSr;
     c.P = P;
     c.n = A.n;
     c.xlo = xlo;
@@ -580,7 +589,7 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, in
 #pragma unroll
     for (int r = 0; r < kRowsW; ++r) own[r * kWave + lane] = acc[r];
     col[(h ? 0 : kColRows - 1) * kWave + lane] = xrow[lane];
-    candidates_from_column(Ap, IYr, RSr, P, xlo, xhi, a, b, slot, col, fl,
+    candidates_from_column(Ap, (LInt*)IYr, (LFloat*)RSr, P, xlo, xhi, a, b, slot, (LFloat*)col, fl,
                            lane, x, Y0 + kRowsW * h - 1, h ? kColRows - 1 : 0);
 }
 
