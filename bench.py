@@ -343,7 +343,8 @@ def main():
     ap.add_argument("--storage", choices=["f32", "bf16", "f16"], default="f32",
                     help="frame storage: 16-bit frames with per-frame scales (quantised on the GPU before the "
                          "timed region); arithmetic stays float32")
-    ap.add_argument("--cpu-velocities", type=int, default=32, help="oracle sample size (0: skip)")
+    ap.add_argument("--cpu-velocities", type=int, default=96,
+                    help="oracle sample size in velocities (about 13 s of host time at the full field; 0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (three times) and exit: "
                          "the reference point that scales the HBM byte counters of a profiler run")
