@@ -170,6 +170,20 @@ def test_detect_small_cases(sst, seed, n, h, w, nvx, nvy, vmax, sky):
     _check_detect(sst, f, 2.5, 0, 6, max_marginal=4)
 
 
+@pytest.mark.parametrize("seed,n,h,w,nvx,nvy,vmax,ties", [
+    (40, 3, 2, 16384, 3, 2, 3.0, True),    # widest frame accepted, two rows
+    (41, 3, 16384, 2, 2, 3, 3.0, True),    # tallest frame accepted, two columns
+    (42, 300, 9, 13, 3, 2, 0.05, False),   # more frames than one staging chunk (256)
+])
+def test_extreme_frame_shapes(sst, seed, n, h, w, nvx, nvy, vmax, ties):
+    """The largest side the library accepts, and a frame count that makes the
+    stacking loop cross from one chunk of frames to the next."""
+    f = synth.small_case(seed, n, h, w, nvx, nvy, vmax=vmax, sky=5.0, sigma=2.0, ties=ties)
+    _say(f"case {f.name}")
+    _check_detect(sst, f, 2.5, 0, 6, max_marginal=4)
+    _check_stack(sst, f)
+
+
 def test_detect_many_candidates_truncation_and_merge(sst):
     """A threshold far below the noise makes almost every local maximum a
     candidate: tiles hold more candidates than they keep (kt), and each
@@ -180,6 +194,9 @@ def test_detect_many_candidates_truncation_and_merge(sst):
     _say("case many candidates")
     _check_detect(sst, f, -100.0, 0, 40, max_marginal=50)
     _check_detect(sst, f, -100.0, 0, 1, max_marginal=50)
+    # the largest k_max accepted: among 1024 listed entries of about 14000
+    # candidates, near-equal S/N pairs make about 60 order decisions marginal
+    _check_detect(sst, f, -100.0, 0, 1024, max_marginal=120)
 
 
 def test_detect_constant_frames(sst):
