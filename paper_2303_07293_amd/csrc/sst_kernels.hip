@@ -996,10 +996,11 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             one(ic<2>{}, ic<1>{}, P);
         };
         static_assert(kVPW == 3 && kVYW == 2, "one call per velocity of the wave");
-        // one instantiation (the prefix in LDS when it fits): the epilogue
-        // code is most of the kernel's, and a second copy costs instruction
-        // fetches more than the prefix reads of the rare lanes it serves
-        epi(p_lds ? (const double*)sP : A.P);
+        // two instantiations so that the common one reads the prefix from LDS
+        if (p_lds)
+            epi(sP);
+        else
+            epi(A.P);
     }
 }
 
