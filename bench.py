@@ -412,7 +412,9 @@ def main():
     achieved = updates / (kern_ms_step * 1e-3) / 1e12  # TFLOP/s at one FP32 add per update
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_ADD_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_ADD_TFLOPS, 4),
-            "traffic": measured_traffic() if args.workload == "full" else None, "traffic_unit": "B/launch",
+            # the counters were taken on float32 frames of the full field
+            "traffic": measured_traffic() if args.workload == "full" and args.storage == "f32" else None,
+            "traffic_unit": "B/launch",
             "kernel": "k_stack<detect>", "kernel_ms_per_step": round(kern_ms_step, 4),
             "launches_per_step": launches / args.steps}
     out = {
