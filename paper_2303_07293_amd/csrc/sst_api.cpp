@@ -41,7 +41,9 @@ constexpr int kMaxFrames = 65535;
 constexpr int kMaxSide = 16384;
 constexpr int kMaxGrid = 65535;
 constexpr double kMaxShift = 1073741824.0;  // 2^30
-constexpr size_t kEntryBudget = size_t(2) << 30;
+// Device memory for the candidate slots of one stacking launch: velocity-
+// block rows beyond it run in further launches (one at the full field).
+constexpr size_t kEntryBudget = size_t(8) << 30;
 
 int check_dims(int n, int h, int w) {
     if (n < 1 || n > kMaxFrames) return fail(SST_E_ARG, "n = %d frames: need 1..%d", n, kMaxFrames);
@@ -233,7 +235,10 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
         p.o_sdev = take(cur, (size_t)n * 2 * sizeof(double));
         p.kt = k_max;
         const size_t per_row = (size_t)p.vby * nvx * p.nslot * ((size_t)p.kt * sizeof(Entry) + sizeof(int32_t));
-        p.rows_per_chunk = (int)std::max<size_t>(1, std::min<size_t>(p.nvby, kEntryBudget / per_row));
+        // as few launches as the budget allows, with their rows balanced
+        const int max_rows = (int)std::max<size_t>(1, std::min<size_t>(p.nvby, kEntryBudget / per_row));
+        const int nchunks = (p.nvby + max_rows - 1) / max_rows;
+        p.rows_per_chunk = (p.nvby + nchunks - 1) / nchunks;
         const size_t nk = (size_t)p.rows_per_chunk * p.vby * nvx;
         p.o_tcount = take(cur, nk * p.nslot * sizeof(int32_t));
         p.o_ent = take(cur, nk * p.nslot * p.kt * sizeof(Entry));

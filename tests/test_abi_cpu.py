@@ -177,12 +177,13 @@ def test_workspace_bytes(lib):
     # the padded frame copy grows with the largest shift
     big = sst.sst_workspace_bytes(sst.SST_OP_STACK, 8, 100, 120, t, 0.0, v * 10, v)
     assert big > s
-    # full-field config fits comfortably in one MI355X's HBM
+    # the full field (candidate slots of every velocity, one launch) takes a
+    # few percent of one MI355X's 288 GB
     rng = np.random.default_rng(synth.SEED_BASE + 2)
     t2 = synth.fields.config2_times(rng)
     g = np.arange(-40, 41, dtype=np.float64)
     nb = sst.sst_workspace_bytes(sst.SST_OP_DETECT, 64, 1024, 1024, t2, t2[0], g, g, 64)
-    assert nb < 4 << 30
+    assert nb < 10 << 30
     with pytest.raises(sst.SstError):
         sst.sst_workspace_bytes(sst.SST_OP_DETECT, 8, 100, 120, t[::-1], 0.0, v, v, 16)
     with pytest.raises(sst.SstError):

@@ -126,7 +126,7 @@ def test_graph_capture_of_many_fields(sst, n_streams):
 # --------------------------------------------------------------- batches
 def _multi_chunk_case(seed_shift=0):
     """512^2 noise frames with a 61 x 61 grid at 0.5 px/h over 2 h and
-    k_max 1024: the slot budget splits the velocity-block rows into 8 chunks,
+    k_max 1024: the slot budget splits the velocity-block rows into 2 chunks,
     so a batch runs several rounds."""
     t = np.linspace(0.0, 2.0, 8)
     f = synth.pure_noise(60 + 1000 * seed_shift, 8, 512, 512, sigma=5.0, sky=50.0, t=t)
