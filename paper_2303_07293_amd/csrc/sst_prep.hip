@@ -70,6 +70,64 @@ __global__ __launch_bounds__(kWave) void k_median_sub(const float* __restrict__ 
     if (med_out) med_out[p] = med;
 }
 
+// Register form for n <= kMedRegs (group sizes of tens of frames): each
+// lane holds its pixel's keys in registers, so the counting passes touch no
+// memory.  Keys past n are the largest key, which is never below a trial
+// value, so they are never counted and never chosen.  Same selection, so
+// the same median and outputs bit for bit as the LDS form.
+constexpr int kMedRegs = 64;
+
+__global__ __launch_bounds__(kPrepThreads) void k_median_sub_reg(const float* __restrict__ F, int n, long long npx,
+                                                                    float* __restrict__ out,
+                                                                    float* __restrict__ med_out) {
+    const long long p = (long long)blockIdx.x * kPrepThreads + threadIdx.x;
+    if (p >= npx) return;
+    unsigned key[kMedRegs];
+#pragma unroll
+    for (int j = 0; j < kMedRegs; ++j) key[j] = j < n ? order_key(F[(long long)j * npx + p]) : 0xFFFFFFFFu;
+    // every order statistic lies in [kmin, kmax], so it shares their common
+    // leading bits: the bit-by-bit search starts below them
+    unsigned kmin = key[0], kmax = key[0];
+#pragma unroll
+    for (int j = 1; j < kMedRegs; ++j)
+        if (j < n) {
+            kmin = min(kmin, key[j]);
+            kmax = max(kmax, key[j]);
+        }
+    const int top = 31 - __clz((int)(kmin ^ kmax));  // highest differing bit, -1 if none
+    const unsigned prefix = top < 0 ? kmin : kmin & ~((2u << top) - 1u);
+    auto select = [&](int j) {
+        unsigned r = prefix;
+#pragma unroll 1
+        for (int b = top; b >= 0; --b) {
+            const unsigned trial = r | (1u << b);
+            int below = 0;
+#pragma unroll
+            for (int i = 0; i < kMedRegs; ++i) below += key[i] < trial;
+            if (below <= j) r = trial;
+        }
+        return r;
+    };
+    const int k = (n - 1) / 2;
+    const unsigned lo = select(k);
+    float med = key_value(lo);
+    if ((n & 1) == 0) {
+        int le = 0;
+        unsigned nxt = 0xFFFFFFFFu;
+#pragma unroll
+        for (int i = 0; i < kMedRegs; ++i) {
+            le += key[i] <= lo;
+            if (key[i] > lo && key[i] < nxt) nxt = key[i];
+        }
+        const unsigned hi = le >= k + 2 ? lo : nxt;
+        med = (key_value(lo) + key_value(hi)) * 0.5f;
+    }
+#pragma unroll
+    for (int j = 0; j < kMedRegs; ++j)
+        if (j < n) out[(long long)j * npx + p] = key_value(key[j]) - med;
+    if (med_out) med_out[p] = med;
+}
+
 // ---------------------------------------------------------------- co-add
 // out[g][p] = sum over j < group, ascending, of F[g * group + j][p]
 __global__ __launch_bounds__(kPrepThreads) void k_coadd(const float* __restrict__ F, long long npx, int group,
@@ -98,6 +156,11 @@ __global__ __launch_bounds__(kPrepThreads) void k_bin2x2(const float* __restrict
 
 hipError_t launch_median_sub(const float* F, int n, int h, int w, float* out, float* med, hipStream_t s) {
     const long long npx = (long long)h * w;
+    if (n <= kMedRegs) {
+        const unsigned blocks = (unsigned)((npx + kPrepThreads - 1) / kPrepThreads);
+        hipLaunchKernelGGL(k_median_sub_reg, dim3(blocks), dim3(kPrepThreads), 0, s, F, n, npx, out, med);
+        return hipGetLastError();
+    }
     const unsigned blocks = (unsigned)((npx + kWave - 1) / kWave);
     hipLaunchKernelGGL(k_median_sub, dim3(blocks), dim3(kWave), (size_t)n * kWave * sizeof(unsigned), s, F, n, npx,
                        out, med);

@@ -43,8 +43,10 @@ def _frames(seed, n, h, w, ties=False):
     return f
 
 
+# n <= 64 takes the register form of the kernel, larger n the LDS form
 @pytest.mark.parametrize("n,h,w,ties", [(1, 3, 5, False), (7, 33, 70, False), (8, 33, 70, True),
-                                        (64, 17, 130, False), (256, 5, 67, True), (13, 1, 1, False)])
+                                        (40, 20, 70, True), (64, 17, 130, False), (65, 9, 40, True),
+                                        (256, 5, 67, True), (13, 1, 1, False)])
 def test_median_subtract(sst, n, h, w, ties):
     _say(f"case median n={n} {h}x{w} ties={ties}")
     f = _frames(n, n, h, w, ties)
