@@ -21,6 +21,8 @@
 // workgroups.
 #include "sst_internal.h"
 
+#include <climits>
+
 namespace sst {
 
 constexpr int kRefThreads = 256;
@@ -43,7 +45,15 @@ __device__ __forceinline__ float block_sum5(float (&v)[5], float* sh) {
     return v[0];
 }
 
-template <int DT>
+// Window pixels per thread held in registers (KPER > 0: cutouts with
+// (C + 1)^2 <= KPER * kRefThreads): each thread's pixels, their window
+// coordinates and their four PSF weights do not change over frames and
+// steps, so they are computed once.  KPER = 0: the general loop, which
+// recomputes them per frame.  Both visit a thread's pixels in the same
+// order with the same arithmetic.
+constexpr int kRefPer = 5;
+
+template <int DT, int KPER>
 __global__ __launch_bounds__(kRefThreads) void k_refine(const RefineArgs A) {
     static_assert(kRefThreads == 4 * kWave, "four waves per candidate");
     __shared__ float wt[kRefW * kRefW];  // wt[(v + R + 1) * (C + 2) + (u + R + 1)], zero border
@@ -67,6 +77,21 @@ __global__ __launch_bounds__(kRefThreads) void k_refine(const RefineArgs A) {
     const float inv_norm = vtot > 0.0 ? rsqrtf((float)(A.sw2 * vtot)) : 0.f;
     __syncthreads();
 
+    int er[KPER > 0 ? KPER : 1], eq[KPER > 0 ? KPER : 1];
+    float w00[KPER > 0 ? KPER : 1], w01[KPER > 0 ? KPER : 1], w10[KPER > 0 ? KPER : 1], w11[KPER > 0 ? KPER : 1];
+#pragma unroll
+    for (int k = 0; k < KPER; ++k) {
+        const int e = tid + k * kRefThreads;
+        const int r = e < nel ? e / (C + 1) : 0, q = e < nel ? e - r * (C + 1) : 0;
+        // pixels past the window get an empty row, which fails the bounds test
+        er[k] = e < nel ? r : INT_MIN / 2;
+        eq[k] = q;
+        w00[k] = wt[(r + 1) * CW + q + 1];
+        w01[k] = wt[(r + 1) * CW + q];
+        w10[k] = wt[r * CW + q + 1];
+        w11[k] = wt[r * CW + q];
+    }
+
     float th[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) th[k] = A.params[(long long)c * 4 + k];
@@ -88,16 +113,22 @@ __global__ __launch_bounds__(kRefThreads) void k_refine(const RefineArgs A) {
             const float bi = A.b32[i];
             const long long fbase = (long long)i * A.h * A.w;
             float tx = 0.f, ty = 0.f;
-            for (int e = tid; e < nel; e += kRefThreads) {
-                const int r = e / (C + 1), q = e - r * (C + 1);
+            auto one = [&](int r, int q, float p00, float p01, float p10, float p11) __attribute__((always_inline)) {
                 const int px = ix + q, py = iy + r;
-                if (px < 0 || px >= A.w || py < 0 || py >= A.h) continue;
+                if (px < 0 || px >= A.w || py < 0 || py >= A.h) return;
                 const float G = frame_value<DT>(A.frames, fbase + (long long)py * A.w + px, sc) - bi;
-                const float p00 = wt[(r + 1) * CW + q + 1], p01 = wt[(r + 1) * CW + q];
-                const float p10 = wt[r * CW + q + 1], p11 = wt[r * CW + q];
                 acc[0] += G * (((k00 * p00 + k01 * p01) + k10 * p10) + k11 * p11);
                 tx += G * ((1.f - fy) * (p01 - p00) + fy * (p11 - p10));
                 ty += G * ((1.f - fx) * (p10 - p00) + fx * (p11 - p01));
+            };
+            if constexpr (KPER > 0) {
+#pragma unroll
+                for (int k = 0; k < KPER; ++k) one(er[k], eq[k], w00[k], w01[k], w10[k], w11[k]);
+            } else {
+                for (int e = tid; e < nel; e += kRefThreads) {
+                    const int r = e / (C + 1), q = e - r * (C + 1);
+                    one(r, q, wt[(r + 1) * CW + q + 1], wt[(r + 1) * CW + q], wt[r * CW + q + 1], wt[r * CW + q]);
+                }
             }
             acc[1] += tx;
             acc[2] += ty;
@@ -122,14 +153,22 @@ __global__ __launch_bounds__(kRefThreads) void k_refine(const RefineArgs A) {
     }
 }
 
+template <int KPER>
+void launch_refine_per(const RefineArgs& a, hipStream_t s) {
+    if (a.dtype == SST_BF16)
+        hipLaunchKernelGGL((k_refine<SST_BF16, KPER>), dim3(a.nc), dim3(kRefThreads), 0, s, a);
+    else if (a.dtype == SST_F16)
+        hipLaunchKernelGGL((k_refine<SST_F16, KPER>), dim3(a.nc), dim3(kRefThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_refine<SST_F32, KPER>), dim3(a.nc), dim3(kRefThreads), 0, s, a);
+}
+
 hipError_t launch_refine(const RefineArgs& a, hipStream_t s) {
     if (a.nc == 0) return hipSuccess;
-    if (a.dtype == SST_BF16)
-        hipLaunchKernelGGL(k_refine<SST_BF16>, dim3(a.nc), dim3(kRefThreads), 0, s, a);
-    else if (a.dtype == SST_F16)
-        hipLaunchKernelGGL(k_refine<SST_F16>, dim3(a.nc), dim3(kRefThreads), 0, s, a);
+    if ((a.cutout + 1) * (a.cutout + 1) <= kRefPer * kRefThreads)
+        launch_refine_per<kRefPer>(a, s);
     else
-        hipLaunchKernelGGL(k_refine<SST_F32>, dim3(a.nc), dim3(kRefThreads), 0, s, a);
+        launch_refine_per<0>(a, s);
     return hipGetLastError();
 }
 

@@ -73,9 +73,10 @@ def _tol(f, th, m, C, sn, b):
     return t_sn, t_g, dpos
 
 
-def test_refine_evaluate_matches_oracle(sst):
+# 33: window pixels held in registers (up to 5 per thread); 41: the general loop
+@pytest.mark.parametrize("C", [33, 41])
+def test_refine_evaluate_matches_oracle(sst, C):
     f = _field()
-    C = 33
     rng = np.random.default_rng(5)
     th = _thetas(f, rng, 24)
     _say(f"case refine evaluate {len(th)} candidates, {f.n}x{f.h}x{f.w}, cutout {C}")
