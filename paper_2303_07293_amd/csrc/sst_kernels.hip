@@ -185,11 +185,19 @@ __global__ __launch_bounds__(kAux) void k_stats_final(const double* __restrict__
 // pad[i][yp][xp] = F_i(xp - padL, yp - padT) - b32[i] inside the frame, 0
 // outside: out-of-frame samples then add nothing, and every staging read of
 // the stack kernel is an unconditional aligned 16-byte load.
+// One thread per 16-byte chunk of a frame's padded copy, numbered row by
+// row over the whole frame (every thread of a workgroup has a chunk, rows
+// need not fill workgroups).
 template <int DT>
 __global__ __launch_bounds__(kAux) void k_prep(const PrepArgs a) {
-    const int i = blockIdx.z, yp = blockIdx.y;
-    const int xp = (blockIdx.x * kAux + threadIdx.x) * 4;
-    if (xp >= a.Wp) return;
+    const int i = blockIdx.y;
+    // (a padded frame has fewer than 2^31 chunks: shifts are clamped to the
+    // frame's size, so each padded side is at most about three times 16384)
+    const unsigned c4 = (unsigned)a.Wp / 4;
+    const unsigned q = blockIdx.x * kAux + threadIdx.x;
+    if (q >= (unsigned)a.Hp * c4) return;
+    const int yp = (int)(q / c4);
+    const int xp = (int)(q - (unsigned)yp * c4) * 4;
     const int y = yp - a.padT;
     float o[4] = {0.f, 0.f, 0.f, 0.f};
     if (y >= 0 && y < a.h) {
@@ -1201,8 +1209,8 @@ hipError_t launch_quantize(const float* frames, int n, int h, int w, int dtype, 
 }
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
-    const int c4 = a.Wp / 4;
-    const dim3 grid((c4 + kAux - 1) / kAux, a.Hp, a.n);
+    const long long chunks = (long long)a.Hp * (a.Wp / 4);
+    const dim3 grid((unsigned)((chunks + kAux - 1) / kAux), a.n);
     if (a.dtype == SST_BF16)
         hipLaunchKernelGGL(k_prep<SST_BF16>, grid, dim3(kAux), 0, s, a);
     else if (a.dtype == SST_F16)
