@@ -70,15 +70,17 @@ def _check_stack(sst, f, bg=None, mode="sum", velocities=None):
         g = out[b, a].cpu().numpy().astype(np.float64)
         gc = cov[b, a].cpu().numpy()
         assert np.array_equal(gc, c), (k, np.argwhere(gc != c)[:5])
-        # 1e-5 of the sum of |terms| (the float32 target), plus the rounding of
-        # a float64 background to float32 once per term (c u |bg|)
+        # 1e-5 of the sum of |terms| (the float32 target; beyond 167 frames
+        # the worst-case float32 sum error 2 N u takes over), plus the
+        # rounding of a float64 background to float32 once per term (c u |bg|)
+        rel = max(1e-5, 2.0 * f.n * 2.0 ** -24)
         bgt = 0.0 if bg is None else 2.0 * 2.0 ** -24 * float(np.abs(bg).max())
         if mode == "mean":
             ref = np.where(c > 0, S / np.maximum(c, 1), 0.0)
-            tol = 1e-5 * np.where(c > 0, A / np.maximum(c, 1), 0.0) + bgt + 1e-30
+            tol = rel * np.where(c > 0, A / np.maximum(c, 1), 0.0) + bgt + 1e-30
         else:
             ref = S
-            tol = 1e-5 * A + c * bgt + 1e-30
+            tol = rel * A + c * bgt + 1e-30
         err = np.abs(g - ref)
         assert np.all(err <= tol), (k, float((err / tol).max()))
         worst = max(worst, float((err / np.maximum(A, 1e-30)).max()))
@@ -182,6 +184,52 @@ def test_extreme_frame_shapes(sst, seed, n, h, w, nvx, nvy, vmax, ties):
     _say(f"case {f.name}")
     _check_detect(sst, f, 2.5, 0, 6, max_marginal=4)
     _check_stack(sst, f)
+
+
+def test_random_cases(sst):
+    """Seeded random problems: frame counts 1-39 (and past one staging
+    chunk of 256), ragged sizes, grids, thresholds from far below the noise
+    to above it, coverage cuts, k_max 1-64, either velocity-block shape;
+    lists against the oracle and sampled plain stacks with coverage."""
+    rng = np.random.default_rng(2024)
+    marg = listed = 0
+    for case in range(30):
+        if case % 10 == 9:
+            n, h, w = int(rng.integers(257, 300)), int(rng.integers(1, 30)), int(rng.integers(1, 70))
+            vmax = float(rng.choice([0.01, 0.05]))
+        else:
+            n, h, w = int(rng.integers(1, 40)), int(rng.integers(1, 160)), int(rng.integers(1, 260))
+            vmax = float(rng.choice([0.3, 2.0, 6.0, 30.0]))
+        nvx, nvy = int(rng.integers(1, 14)), int(rng.integers(1, 14))
+        ties = bool(rng.integers(0, 2))
+        f = synth.small_case(700 + case, n, h, w, nvx, nvy, vmax=vmax, sky=float(rng.choice([0.0, 10.0, 1000.0])),
+                             sigma=2.0, ties=ties)
+        thr = float(rng.choice([-50.0, 1.0, 2.5, 4.0]))
+        cmin = int(rng.choice([0, 1, max(1, n // 2)]))
+        kmax = int(rng.choice([1, 5, 64]))
+        shape = int(rng.integers(0, 2))
+        _say(f"case {case}: {f.name} vmax {vmax} thr {thr} cmin {cmin} kmax {kmax} shape {shape}")
+        fr = _dev(f.frames)
+        if shape == 0:
+            cand, count = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax)
+        else:
+            plan = sst.sst_plan_detect(n, h, w, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax, shape=1)
+            cand, count = plan.run(fr)
+        torch.cuda.synchronize()
+        got = sst.candidates_to_numpy(cand)
+        cnt = count.cpu().numpy()
+        ref = oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax, keep_maps=True)
+        bmax = float(np.abs(oracle.frame_stats(f.frames)[0]).max())
+        for k in range(nvx * nvy):
+            marg += compare_velocity(got[k], int(cnt[k]), ref[k], n, bmax, thr, ref["c_min"], kmax, w)
+            listed += min(int(ref[k]["count"]), kmax)
+        ks = rng.choice(nvx * nvy, size=min(3, nvx * nvy), replace=False)
+        _check_stack(sst, f, velocities=[int(k) for k in ks])
+    # low thresholds list many candidates of nearly equal S/N, whose order
+    # is marginal (the oracle counts 554 such decisions in 28551 listed
+    # entries here); the bound keeps the comparison from going lax
+    _say(f"  {marg} marginal decisions, {listed} listed entries over 30 cases")
+    assert marg <= 0.05 * listed + 20
 
 
 def test_detect_many_candidates_truncation_and_merge(sst):
