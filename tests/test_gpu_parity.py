@@ -70,9 +70,10 @@ def _check_stack(sst, f, bg=None, mode="sum", velocities=None):
         g = out[b, a].cpu().numpy().astype(np.float64)
         gc = cov[b, a].cpu().numpy()
         assert np.array_equal(gc, c), (k, np.argwhere(gc != c)[:5])
-        # 1e-5 of the sum of |terms| (the float32 target; beyond 167 frames
-        # the worst-case float32 sum error 2 N u takes over), plus the
-        # rounding of a float64 background to float32 once per term (c u |bg|)
+        # 1e-5 of the sum of |terms| (the float32 target; from 84 frames on
+        # the worst-case float32 sum error N u, with a safety factor 2, takes
+        # over), plus the rounding of a float64 background to float32 once per
+        # term (c u |bg|)
         rel = max(1e-5, 2.0 * f.n * 2.0 ** -24)
         bgt = 0.0 if bg is None else 2.0 * 2.0 ** -24 * float(np.abs(bg).max())
         if mode == "mean":
