@@ -42,7 +42,8 @@ constexpr int kMaxSide = 16384;
 constexpr int kMaxGrid = 65535;
 constexpr double kMaxShift = 1073741824.0;  // 2^30
 // Device memory for the candidate slots of one stacking launch: velocity-
-// block rows beyond it run in further launches (one at the full field).
+// block rows beyond it run in further launches (64-entry lists of an 81 x 81
+// grid over 1024 x 1024 frames need 7.1 GB, one launch).
 constexpr size_t kEntryBudget = size_t(8) << 30;
 
 int check_dims(int n, int h, int w) {
