@@ -177,10 +177,12 @@ def test_detect_small_cases(sst, seed, n, h, w, nvx, nvy, vmax, sky):
     (40, 3, 2, 16384, 3, 2, 3.0, True),    # widest frame accepted, two rows
     (41, 3, 16384, 2, 2, 3, 3.0, True),    # tallest frame accepted, two columns
     (42, 300, 9, 13, 3, 2, 0.05, False),   # more frames than one staging chunk (256)
+    (43, 1100, 4, 9, 2, 2, 0.01, False),   # variance prefix too long for LDS: read from global memory
 ])
 def test_extreme_frame_shapes(sst, seed, n, h, w, nvx, nvy, vmax, ties):
-    """The largest side the library accepts, and a frame count that makes the
-    stacking loop cross from one chunk of frames to the next."""
+    """The largest side the library accepts, frame counts that make the
+    stacking loop cross from one chunk of frames to the next, and one whose
+    variance prefix (n + 1 entries) exceeds the detect kernel's LDS copy."""
     f = synth.small_case(seed, n, h, w, nvx, nvy, vmax=vmax, sky=5.0, sigma=2.0, ties=ties)
     _say(f"case {f.name}")
     _check_detect(sst, f, 2.5, 0, 6, max_marginal=4)
