@@ -213,6 +213,22 @@ def candidates_from_maps(sn: np.ndarray, c: np.ndarray, threshold: float, c_min:
 
 
 # --------------------------------------------------------------------- O6 --
+def velocity_list(ras: np.ndarray, m: Dict[str, np.ndarray], ia: int, ib: int, w: int, k_max: int):
+    """One velocity's output (O6): the first k_max candidates of `ras` (raster
+    indices already in key order) as records with their S/N, flux, coverage
+    and 0-based rank, and the number of candidates before truncation."""
+    top = ras[:k_max]
+    rec = np.zeros(len(top), dtype=CAND_DTYPE)
+    ys, xs = top // w, top % w
+    rec["ivx"], rec["ivy"] = ia, ib
+    rec["x"], rec["y"] = xs, ys
+    rec["snr"] = m["SN"][ys, xs]
+    rec["flux"] = m["S"][ys, xs]
+    rec["coverage"] = m["c"][ys, xs]
+    rec["rank"] = np.arange(len(top))
+    return rec, int(len(ras))
+
+
 def detect(frames: np.ndarray, t, t_ref: float, vx, vy, threshold: float,
            min_coverage: int, k_max: int,
            velocities: Optional[Sequence[int]] = None,
@@ -235,16 +251,8 @@ def detect(frames: np.ndarray, t, t_ref: float, vx, vy, threshold: float,
         ia, ib = k % nvx, k // nvx
         m = snr_velocity(frames, dx[:, ia], dy[:, ib], b, s2, absolute=keep_maps)
         ras = candidates_from_maps(m["SN"], m["c"], threshold, c_min)
-        top = ras[:k_max]
-        rec = np.zeros(len(top), dtype=CAND_DTYPE)
-        ys, xs = top // w, top % w
-        rec["ivx"], rec["ivy"] = ia, ib
-        rec["x"], rec["y"] = xs, ys
-        rec["snr"] = m["SN"][ys, xs]
-        rec["flux"] = m["S"][ys, xs]
-        rec["coverage"] = m["c"][ys, xs]
-        rec["rank"] = np.arange(len(top))
-        entry = {"cand": rec, "count": int(len(ras))}
+        rec, count = velocity_list(ras, m, ia, ib, w, k_max)
+        entry = {"cand": rec, "count": count}
         if keep_maps:
             entry.update(m)
             entry["all"] = ras

@@ -168,22 +168,46 @@ def test_candidate_rules():
     pin_candidate_rules()
 
 
+# Ten isolated static peaks on a zero sky (3 identical frames, 12 x 9, the
+# zero-velocity bin only): S' = 3 (F - b), V = 3 s2, so SN = sqrt(3) (F - b) /
+# sqrt(s2) with b = 54 / 108 and s2 = 366 / 108 - b^2 worked out by hand.
+TRUNC_PEAKS = [((1, 1), 5), ((4, 1), 9), ((7, 1), 3), ((10, 1), 9), ((1, 4), 7),
+               ((4, 4), 1), ((7, 4), 6), ((10, 4), 4), ((1, 7), 8), ((4, 7), 2)]
+
+
+def pin_truncation_and_count():
+    """O6: detect keeps the k_max best keys in key order, ranks them 0..k-1
+    and counts every candidate before truncation."""
+    h, w = 9, 12
+    img = np.zeros((h, w), np.float32)
+    for (x, y), v in TRUNC_PEAKS:
+        img[y, x] = v
+    frames = np.stack([img] * 3)
+    t = np.array([0.0, 0.5, 1.0])
+    b = Fraction(54, 108)
+    s2 = Fraction(366, 108) - b * b
+    # heights 4 and up clear SN 3 (SN(4) = 3.42, SN(3) = 2.44): 7 candidates;
+    # key order 9 (raster 16), 9 (raster 22, the tie goes to the lower index),
+    # 8 (85), 7 (49), 6 (55), 5 (13), 4 (58)
+    want = [16, 22, 85, 49, 55, 13, 58]
+    for k_max in (1, 4, 7, 10):
+        out = so.detect(frames, t, 0.0, [0.0], [0.0], 3.0, 0, k_max)
+        e = out[0]
+        assert e["count"] == 7
+        got = e["cand"]
+        nk = min(k_max, 7)
+        assert len(got) == nk
+        assert list(got["y"] * w + got["x"]) == want[:nk]
+        assert list(got["rank"]) == list(range(nk))
+        assert np.all(got["coverage"] == 3) and np.all(got["ivx"] == 0) and np.all(got["ivy"] == 0)
+        for r in got:
+            v = int(img[r["y"], r["x"]])
+            assert r["flux"] == pytest.approx(float(3 * (v - b)), rel=1e-14)
+            assert r["snr"] == pytest.approx(math.sqrt(3.0) * float(v - b) / math.sqrt(float(s2)), rel=1e-12)
+
+
 def test_truncation_and_count():
-    """k_max truncation keeps the best keys and reports the full count."""
-    h, w = 12, 12
-    sn = np.zeros((h, w))
-    val = 10.0
-    pts = []
-    for y in range(0, h, 3):
-        for x in range(0, w, 3):
-            sn[y, x] = val
-            pts.append(y * w + x)
-            val -= 0.5
-    frames = np.zeros((2, h, w), np.float32)  # maps are injected below
-    ras = so.candidates_from_maps(sn, np.full((h, w), 2), 1.0, 1)
-    assert list(ras) == pts  # descending values were assigned in raster order
-    assert len(ras) == 16 and list(ras[:5]) == pts[:5]
-    del frames
+    pin_truncation_and_count()
 
 
 # ------------------------------------------------------- O3 brute force --
@@ -438,3 +462,33 @@ def test_planted_threshold_inclusive_is_caught(monkeypatch):
         return real(sn, c, np.nextafter(threshold, -np.inf), c_min)
     monkeypatch.setattr(so, "candidates_from_maps", incl)
     _must_fail(pin_candidate_rules)
+
+
+def test_planted_count_after_truncation_is_caught(monkeypatch):
+    real = so.velocity_list
+
+    def bad(ras, m, ia, ib, w, k_max):
+        rec, _ = real(ras, m, ia, ib, w, k_max)
+        return rec, len(rec)
+    monkeypatch.setattr(so, "velocity_list", bad)
+    _must_fail(pin_truncation_and_count)
+
+
+def test_planted_one_based_rank_is_caught(monkeypatch):
+    real = so.velocity_list
+
+    def bad(ras, m, ia, ib, w, k_max):
+        rec, cnt = real(ras, m, ia, ib, w, k_max)
+        rec["rank"] += 1
+        return rec, cnt
+    monkeypatch.setattr(so, "velocity_list", bad)
+    _must_fail(pin_truncation_and_count)
+
+
+def test_planted_keep_last_k_is_caught(monkeypatch):
+    real = so.velocity_list
+
+    def bad(ras, m, ia, ib, w, k_max):
+        return real(ras[::-1][:k_max][::-1] if len(ras) > k_max else ras, m, ia, ib, w, k_max)
+    monkeypatch.setattr(so, "velocity_list", bad)
+    _must_fail(pin_truncation_and_count)

@@ -114,3 +114,40 @@ def test_planted_flipped_fraction_is_caught(monkeypatch):
     # (linear ramps cannot see it: any affine combination reproduces them)
     with pytest.raises(AssertionError):
         test_integer_positions_reduce_to_plain_stack()
+
+
+def pin_psf_weights():
+    """The Gaussian weights against facts that fix them: the centre weight
+    is 1; a FWHM of 4 px puts weight 1/2 exactly 2 px from the centre along
+    either axis and 1/4 on the diagonal there (the 2-D Gaussian is the
+    product of two 1-D ones); the grid is symmetric; and the sum of squared
+    weights over a wide cutout is the integral pi s^2 with s = FWHM /
+    (2 sqrt(2 ln 2)) (Poisson summation: the lattice sum of exp(-u^2/s^2)
+    equals sqrt(pi) s up to terms of order exp(-pi^2 s^2))."""
+    wts = refine.psf_weights(9, 4.0)
+    R = 4
+    assert wts.shape == (9, 9)
+    assert wts[R, R] == 1.0
+    for dy, dx in ((0, 2), (0, -2), (2, 0), (-2, 0)):
+        assert wts[R + dy, R + dx] == pytest.approx(0.5, rel=1e-14)
+    assert wts[R + 2, R + 2] == pytest.approx(0.25, rel=1e-14)
+    assert np.array_equal(wts, wts.T) and np.array_equal(wts, wts[::-1]) and np.array_equal(wts, wts[:, ::-1])
+    assert np.all(wts > 0) and np.all(wts <= 1)
+    fwhm = 6.0
+    s = fwhm / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+    w33 = refine.psf_weights(33, fwhm)
+    assert float((w33 ** 2).sum()) == pytest.approx(math.pi * s * s, rel=1e-12)
+
+
+def test_psf_weights_closed_forms():
+    pin_psf_weights()
+
+
+def test_planted_fwhm_as_sigma_is_caught(monkeypatch):
+    def bad(cutout, fwhm):
+        r = cutout // 2
+        u = np.arange(-r, r + 1, dtype=np.float64)
+        return np.exp(-(u[None, :] ** 2 + u[:, None] ** 2) / (2.0 * fwhm * fwhm))
+    monkeypatch.setattr(refine, "psf_weights", bad)
+    with pytest.raises(AssertionError):
+        pin_psf_weights()
