@@ -26,10 +26,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X FP32 vector issue rate for adds: 256 CUs x 4 SIMDs x 16 lanes x 2
-# (packed) x 2.4 GHz = 78.6 T adds/s (the 157.3 TFLOP/s FP32 figure counts an
-# FMA as two flops).
-PEAK_FP32_ADD_TFLOPS = 78.6
+# MI355X published FP32 vector peak: 157.3 TFLOP/s (256 CUs x 2.4 GHz x 128
+# lanes x 2 flops of an FMA).  One update of the search is one FP32 add, counted
+# as one flop.  The FP32 add rate itself is 256 x 128 x 2.4 GHz = 78.6 T adds/s
+# (a plain v_add_f32 loop measures 112 adds/clk/CU, 88 % of it).
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_ADD_T = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
@@ -63,18 +65,58 @@ def measured_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(f, n_vel: int, seed: int = 0):
+_ORACLE_FIELD = None
+
+
+def _oracle_share(ks):
+    """One worker's share of the oracle sample (velocity indices ks); the
+    field is inherited from the parent process (fork)."""
     import oracle
-    rng = np.random.default_rng(seed)
-    nk = len(f.vx) * len(f.vy)
-    ks = sorted(rng.choice(nk, size=n_vel, replace=False).tolist())
+    f = _ORACLE_FIELD
     t0 = time.perf_counter()
     oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, velocities=ks)
-    dt = time.perf_counter() - t0
-    ups = n_vel * f.n * f.h * f.w / dt
-    return {"value": ups, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_vel} of {nk} velocities of the same field (all {f.n} frames of {f.w}x{f.h}), "
-                      f"numpy float64 oracle incl. frame statistics, {dt:.1f} s"}
+    return time.perf_counter() - t0
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(f, per_core: int, max_workers: int = 16, seed: int = 0):
+    """The float64 oracle as written, timed on the host cores: velocity
+    indices of the same field spread over worker processes (fork; the frames
+    are shared copy-on-write), each worker running oracle.detect on its share
+    (its own frame statistics included, as the GPU step includes them).
+    Value: updates of the sample / wall time.  Also a single-core run."""
+    import multiprocessing as mp
+    global _ORACLE_FIELD
+    _ORACLE_FIELD = f
+    cores = max(1, min(os.cpu_count() or 1, max_workers))
+    rng = np.random.default_rng(seed)
+    nk = len(f.vx) * len(f.vy)
+    n_vel = min(nk, cores * per_core)
+    ks = sorted(rng.choice(nk, size=n_vel, replace=False).tolist())
+    shares = [ks[j::cores] for j in range(cores)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        busy = pool.map(_oracle_share, shares)
+        wall = time.perf_counter() - t0
+    one = ks[:per_core]
+    t1 = _oracle_share(one)
+    px = f.n * f.h * f.w
+    return {"value": n_vel * px / wall, "unit": "updates/s", "cores": cores, "kind": "oracle",
+            "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
+            "single_core_value": len(one) * px / t1,
+            "sample": f"{n_vel} of {nk} velocities of the same field (all {f.n} frames of {f.w}x{f.h}) in "
+                      f"{cores} worker processes, numpy float64 oracle incl. frame statistics; wall {wall:.1f} s, "
+                      f"{sum(busy):.1f} s of worker time; single core: {len(one)} velocities in {t1:.1f} s"}
 
 
 def copy_reference(torch, mib: int):
@@ -279,14 +321,22 @@ def batch_bench(torch, sst, args):
                       "ms_graph_replay_persistent_batch": t_graphb * 1e3}), flush=True)
 
 
-def stack_bench(torch, sst, args):
-    """The plain float32 stack (`sst_stack`, SUM, every [vy][vx][h][w] stack
-    written to HBM) on the full field's grid: 32 frames (the diagnostic shape,
-    where the written stacks make HBM a co-binding roof) or all 64.  Reported
-    as updates/s, and as compulsory HBM bytes (frames read once, stacks
-    written once) per step time against the HBM peak."""
-    import synth
-    f = synth.config_diagnostic() if args.workload == "stack" else synth.config2()
+def roofline(updates: float, kern_ms: float, launches: float, traffic=None, kernel="k_stack<detect>"):
+    """Roofline position of the stacking kernel: one FP32 add (one flop) per
+    update over the kernel's event-timed duration, against the published
+    FP32 vector peak; the FP32 add rate is a separate, labelled ceiling."""
+    achieved = updates / (kern_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "traffic_unit": "B/launch",
+            "kernel": kernel, "kernel_ms_per_step": round(kern_ms, 4), "launches_per_step": launches,
+            "add_rate_ceiling": {"peak": PEAK_FP32_ADD_T, "unit": "T adds/s",
+                                 "frac": round(achieved / PEAK_FP32_ADD_T, 4)}}
+
+
+def time_plain_stack(torch, sst, f, steps: int, warmup: int):
+    """sst_stack (SUM, every [vy][vx][h][w] float32 stack written to HBM) on
+    field f: step time, kernel time and the compulsory HBM bytes (frames read
+    once, stacks written once) per step against the HBM peak."""
     dev = torch.device("cuda:0")
     frames = torch.from_numpy(f.frames).to(dev)
     n, h, w = f.frames.shape
@@ -298,33 +348,75 @@ def stack_bench(torch, sst, args):
     def step():
         sst.sst_stack(frames, f.t, f.t_ref, f.vx, f.vy, out=out, ws=ws)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     sst.sst_profile_begin()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     kern_ms, launches = sst.sst_profile_end()
-    kern_ms /= args.steps
+    kern_ms /= steps
     updates = n * h * w * nvx * nvy
     nbytes = 4 * n * h * w + 4 * nvx * nvy * h * w
-    gbs = nbytes / dt / 1e9
-    achieved = updates / (kern_ms * 1e-3) / 1e12
+    del out, ws, frames
+    torch.cuda.empty_cache()
+    return {"workload": f.name, "ms_per_step": round(dt * 1e3, 4), "updates_per_s": updates / dt,
+            "compulsory_bytes": nbytes, "GB/s": round(nbytes / dt / 1e9, 1),
+            "frac_hbm": round(nbytes / dt / 1e9 / HBM_PEAK_GBS, 4),
+            "roofline": roofline(updates, kern_ms, launches / steps, None, "k_stack<stack>")}
+
+
+def stack_bench(torch, sst, args):
+    """The plain float32 stack (`sst_stack`, SUM, every [vy][vx][h][w] stack
+    written to HBM) on the full field's grid: 32 frames (the diagnostic shape,
+    where the written stacks make HBM a co-binding roof) or all 64.  Reported
+    as updates/s, and as compulsory HBM bytes (frames read once, stacks
+    written once) per step time against the HBM peak."""
+    import synth
+    f = synth.config_diagnostic() if args.workload == "stack" else synth.config2()
+    r = time_plain_stack(torch, sst, f, args.steps, args.warmup)
     print(json.dumps({
-        "metric": "frame*pixel*velocity updates/s", "value": updates / dt, "unit": "updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "metric": "frame*pixel*velocity updates/s", "value": r["updates_per_s"], "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"plain stack {n}x{h}x{w} grid{nvx}x{nvy}, SUM, stacks written",
-                   "output_bytes": 4 * nvx * nvy * h * w},
-        "hbm": {"compulsory_bytes": nbytes, "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_ADD_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_ADD_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_stack<stack>", "kernel_ms_per_step": round(kern_ms, 4),
-                     "launches_per_step": launches / args.steps},
+        "config": {"workload": f"plain stack {f.n}x{f.h}x{f.w} grid{len(f.vx)}x{len(f.vy)}, SUM, stacks written",
+                   "output_bytes": 4 * len(f.vx) * len(f.vy) * f.h * f.w},
+        "hbm": {"compulsory_bytes": r["compulsory_bytes"], "GB/s": r["GB/s"], "frac": r["frac_hbm"]},
+        "roofline": r["roofline"],
     }), flush=True)
+
+
+def time_detect(torch, sst, f, frames, scale, steps: int, warmup: int):
+    """sst_detect on field f (frames already on the device): seconds per
+    step, stacking-kernel ms per step, launches per step, candidates."""
+    dev = frames.device
+    n, h, w = f.frames.shape
+    nk = len(f.vx) * len(f.vy)
+    nb = sst.sst_workspace_bytes(sst.SST_OP_DETECT, n, h, w, f.t, f.t_ref, f.vx, f.vy, f.k_max)
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    cand = torch.empty((nk, f.k_max, 8), dtype=torch.int32, device=dev)
+    count = torch.empty((nk,), dtype=torch.int32, device=dev)
+
+    def step():
+        sst.sst_detect(frames, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max,
+                       scale=scale, ws=ws, cand=cand, count=count)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    sst.sst_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kern_ms, launches = sst.sst_profile_end()
+    cands = int(count.sum().item())
+    del ws, cand, count
+    return dt, kern_ms / steps, launches / steps, cands
 
 
 def main():
@@ -343,8 +435,11 @@ def main():
     ap.add_argument("--storage", choices=["f32", "bf16", "f16"], default="f32",
                     help="frame storage: 16-bit frames with per-frame scales (quantised on the GPU before the "
                          "timed region); arithmetic stays float32")
-    ap.add_argument("--cpu-velocities", type=int, default=96,
-                    help="oracle sample size in velocities (about 13 s of host time at the full field; 0: skip)")
+    ap.add_argument("--cpu-velocities", type=int, default=8,
+                    help="oracle sample: velocities per host core (a few seconds per core at the full field; "
+                         "0: skip)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="full workload: skip the 16-bit storage and plain-stack measurements")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (three times) and exit: "
                          "the reference point that scales the HBM byte counters of a profiler run")
@@ -385,46 +480,40 @@ def main():
         torch.cuda.synchronize()
     n, h, w = f.frames.shape
     nk = len(f.vx) * len(f.vy)
-    nb = sst.sst_workspace_bytes(sst.SST_OP_DETECT, n, h, w, f.t, f.t_ref, f.vx, f.vy, f.k_max)
-    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
-    cand = torch.empty((nk, f.k_max, 8), dtype=torch.int32, device=dev)
-    count = torch.empty((nk,), dtype=torch.int32, device=dev)
-
-    def step():
-        sst.sst_detect(frames, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max,
-                       scale=scale, ws=ws, cand=cand, count=count)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    sst.sst_profile_begin()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kern_ms, launches = sst.sst_profile_end()
-
+    dt, kern_ms_step, launches, cands = time_detect(torch, sst, f, frames, scale, args.steps, args.warmup)
     updates = f.updates
-    ms_step = dt * 1e3 / args.steps
-    value = updates / (dt / args.steps)
-    kern_ms_step = kern_ms / args.steps
-    achieved = updates / (kern_ms_step * 1e-3) / 1e12  # TFLOP/s at one FP32 add per update
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_ADD_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_ADD_TFLOPS, 4),
-            # the counters were taken on float32 frames of the full field
-            "traffic": measured_traffic() if args.workload == "full" and args.storage == "f32" else None,
-            "traffic_unit": "B/launch",
-            "kernel": "k_stack<detect>", "kernel_ms_per_step": round(kern_ms_step, 4),
-            "launches_per_step": launches / args.steps}
+    value = updates / dt
+    # the counters were taken on float32 frames of the full field
+    traffic = measured_traffic() if args.workload == "full" and args.storage == "f32" else None
     out = {
         "metric": "frame*pixel*velocity updates/s", "value": value, "unit": "updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f.name, "storage": args.storage, "frames": n, "height": h, "width": w, "velocities": nk,
-                   "threshold": f.threshold, "k_max": f.k_max, "candidates_last_step": int(count.sum().item())},
-        "roofline": roof,
+                   "threshold": f.threshold, "k_max": f.k_max, "candidates_last_step": cands},
+        "roofline": roofline(updates, kern_ms_step, launches, traffic),
     }
+    if args.workload == "full" and args.storage == "f32" and not args.no_extras:
+        # the rest of the metric: 16-bit storage against float32 on the same
+        # field, and the plain stacks' HBM fraction
+        del frames
+        torch.cuda.empty_cache()
+        fr32 = torch.from_numpy(f.frames).to(dev)
+        ratio = {"f32_ms_per_step": round(dt * 1e3, 4)}
+        for name, tdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+            q, sc, _ = sst.sst_quantize(fr32, tdt, center=True)
+            torch.cuda.synchronize()
+            d16, k16, _, c16 = time_detect(torch, sst, f, q, sc, max(3, args.steps // 2), 2)
+            ratio[f"{name}_ms_per_step"] = round(d16 * 1e3, 4)
+            ratio[f"speedup_{name}_vs_f32"] = round(dt / d16, 4)
+            ratio[f"{name}_candidates"] = c16
+            del q, sc
+        del fr32
+        torch.cuda.empty_cache()
+        out["storage_16bit_vs_f32"] = ratio
+        ps = max(2, args.steps // 5)
+        out["plain_stack_hbm"] = [time_plain_stack(torch, sst, synth.config_diagnostic(), ps, 1),
+                                  time_plain_stack(torch, sst, f, ps, 1)]
     if args.cpu_velocities > 0:
         out["cpu_baseline"] = cpu_baseline(f, args.cpu_velocities)
     print(json.dumps(out), flush=True)

@@ -204,7 +204,9 @@ int sst_plan_detect_shape(int shape, int n, int h, int w, const double* t, doubl
 
 /* What a plan does: its shape, whether its velocity blocks are staged in
  * LDS (1) or read through L2 (0, much slower: blocks too spread for the
- * staging window), and its stacking launches per run (chunks of block
+ * staging window, or padded frames of more than 2^31 bytes, which the
+ * staged path's 31-bit offsets cannot address), and its stacking launches
+ * per run (chunks of block
  * rows).  Any pointer may be NULL.  Errors: SST_E_ARG (plan NULL). */
 int sst_plan_info(const sst_plan* plan, int* shape, int* staged, int* launches);
 

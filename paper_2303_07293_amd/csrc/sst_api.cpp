@@ -204,6 +204,10 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
     const int need_h = std::max(Y0max + dymax + kRows, Y0max + dymax + kLdsRows) + p.padT;
     p.Wp = (int)align_up((size_t)std::max(4, need_w), 16);
     p.Hp = std::max(1, need_h);
+    // the staged path addresses each padded frame with 31-bit byte offsets;
+    // larger padded frames (shifts of thousands of pixels on large frames)
+    // take the direct path, which uses 64-bit addresses
+    if ((size_t)p.Hp * (size_t)p.Wp * sizeof(float) > (size_t)0x7FFFFFFF) p.staged = false;
     // Staging geometry of every velocity block and frame, the same for all
     // tiles (tile origins are multiples of 4 columns): the byte offset of the
     // window from the tile's origin in the frame's padded copy, then the LDS
@@ -947,6 +951,20 @@ int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, 
                const double* vx, int nvx, const double* vy, int nvy, float threshold, int min_coverage, int k_max,
                sst_candidate* cand, int32_t* count, double* frame_stats, void* ws, size_t ws_bytes, void* stream) {
     g_err.clear();
+    return sst::detect_call(frames, dtype, scale, n, h, w, t, t_ref, vx, nvx, vy, nvy, threshold, min_coverage, k_max,
+                            cand, count, frame_stats, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace sst {
+
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+int detect_call(const void* frames, int dtype, const float* scale, int n, int h, int w, const double* t,
+                double t_ref, const double* vx, int nvx, const double* vy, int nvy, float threshold,
+                int min_coverage, int k_max, sst_candidate* cand, int32_t* count, double* frame_stats, void* ws,
+                size_t ws_bytes, void* stream) {
     int rc = check_frames(frames, dtype, scale);
     if (rc) return rc;
     if (!cand || !count) return fail(SST_E_ARG, "cand/count is NULL");
@@ -967,6 +985,10 @@ int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, 
     }
     return SST_OK;
 }
+
+}  // namespace sst
+
+extern "C" {
 
 int sst_plan_detect(int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx, const double* vy,
                     int nvy, float threshold, int min_coverage, int k_max, void* ws, size_t ws_bytes, void* stream,

@@ -158,6 +158,15 @@ hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int nslot, int 
                         int nvx, int w, int k_first, int nk, void* cand, int32_t* count,
                         hipStream_t s);
 
+// The body of sst_detect on a given workspace (sst_api.cpp), shared with
+// the entry point that uses the library's static scratch (sst_noalloc.hip),
+// and the error-message setter of the C ABI.
+int detect_call(const void* frames, int dtype, const float* scale, int n, int h, int w, const double* t,
+                double t_ref, const double* vx, int nvx, const double* vy, int nvy, float threshold,
+                int min_coverage, int k_max, sst_candidate* cand, int32_t* count, double* frame_stats, void* ws,
+                size_t ws_bytes, void* stream);
+int set_error(int code, const char* msg);
+
 // sub-pixel refinement (sst_refine.hip)
 struct RefineArgs {
     const void* frames;  // [n][h][w] of dtype

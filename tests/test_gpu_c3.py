@@ -1,0 +1,179 @@
+"""GPU parity at the sizes of the batching workload (through the C ABI).
+
+* the persistent batch (SstBatch) over three uneven fields, against the
+  float64 oracle on sampled velocities of every field: the largest field of
+  the workload (121 frames of 2048^2, a 121 x 121 grid), whose candidate
+  slots need several stacking launches and whose padded frames span more
+  than one buffer descriptor, a 133-frame field and a 160-frame field; the
+  same largest field through sst_detect gives the batch's lists bit for bit;
+* the plain stack of the 160-frame field against the oracle: the float32 sum
+  of 160 terms in any order is within gamma_159 = 9.5e-6 of the sum of
+  |terms|, so the relative target 1e-5 is asserted directly;
+* frames whose padded copy exceeds 2^31 bytes take the 64-bit-addressed
+  direct path (the staged path addresses a padded frame with 31-bit byte
+  offsets) and agree with the oracle.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sst_oracle as so
+import synth
+from synth.fields import FieldSpec, SEED_BASE
+from parity import compare_velocity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sst():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_07293_amd as m
+    m.load()
+    return m
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _long_spec(n=160, side=512, grid=41, seed=SEED_BASE + 350):
+    """A field of the batching workload's recipe with a chosen frame count:
+    n frames over 4 h with 10 % of the slots dropped, sky 100, sigma 10,
+    movers scaled by area."""
+    rng = np.random.default_rng(seed)
+    m = int(round(n / 0.9))
+    slots = np.arange(m, dtype=np.float64) * (4.0 / (m - 1))
+    t = slots[np.sort(rng.choice(m, size=n, replace=False))]
+    n_movers = max(1, int(round(50 * side * side / 1024 ** 2)))
+    return FieldSpec(f"long{n} {n}x{side}x{side} grid{grid}x{grid}", seed, n, side, grid, t, n_movers)
+
+
+def _sample_velocities(f, extra=(), n_random=1, seed=0):
+    """Bins of the two brightest movers, the last grid row (the last
+    stacking launch of a chunked field) and random ones."""
+    nvx = len(f.vx)
+    ks = set(extra)
+    for mv in sorted(f.movers, key=lambda m: -m.amp)[:2]:
+        a = int(np.argmin(np.abs(f.vx - mv.vx)))
+        b = int(np.argmin(np.abs(f.vy - mv.vy)))
+        ks.add(b * nvx + a)
+    ks.add((len(f.vy) - 1) * nvx + nvx // 3)
+    rng = np.random.default_rng(seed)
+    ks.update(int(k) for k in rng.choice(nvx * len(f.vy), size=n_random, replace=False))
+    return sorted(ks)
+
+
+def _check_lists(f, got, cnt, ks, max_marginal):
+    ref = oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max,
+                        velocities=ks, keep_maps=True)
+    b, _ = ref["stats"]
+    bmax = float(np.abs(b).max())
+    marg, worst = 0, 0.0
+    for k in ks:
+        marg += compare_velocity(got[k], int(cnt[k]), ref[k], f.n, bmax, f.threshold, ref["c_min"], f.k_max, f.w)
+        # flux of the listed candidates against S' (relative to the sum of
+        # |F - b| over their frames): the measured error
+        m = min(int(cnt[k]), f.k_max)
+        g = got[k][:m]
+        if m:
+            e = np.abs(g["flux"] - ref[k]["S"][g["y"], g["x"]]) / ref[k]["A"][g["y"], g["x"]]
+            worst = max(worst, float(e.max()))
+    assert marg <= max_marginal, marg
+    return marg, worst
+
+
+@pytest.mark.timeout(600)
+def test_batch_uneven_fields_against_oracle(sst):
+    specs = [synth.config3()[9], synth.config3()[2], _long_spec()]
+    fields, frames, plans = [], [], []
+    for sp in specs:
+        _say(f"case batch field {sp.name}: generating")
+        f = sp.make()
+        fields.append(f)
+        frames.append(torch.from_numpy(f.frames).to("cuda:0"))
+        plans.append(sst.sst_plan_detect(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage,
+                                         f.k_max))
+    big = plans[0]
+    _say(f"  {specs[0].name}: {big.launches} stacking launches, staged={big.staged}")
+    assert big.staged and big.launches > 1
+    batch = sst.SstBatch(plans)
+    cands, counts = batch.run(frames)
+    torch.cuda.synchronize()
+    # the largest field through sst_detect (its own chunked launches): the
+    # same lists bit for bit
+    c2, n2 = sst.sst_detect(frames[0], fields[0].t, fields[0].t_ref, fields[0].vx, fields[0].vy,
+                            fields[0].threshold, fields[0].min_coverage, fields[0].k_max)
+    torch.cuda.synchronize()
+    assert torch.equal(c2, cands[0]) and torch.equal(n2, counts[0])
+    del c2, n2
+    for j, f in enumerate(fields):
+        got = sst.candidates_to_numpy(cands[j])
+        cnt = counts[j].cpu().numpy()
+        ks = _sample_velocities(f, seed=j, n_random=1 if j == 0 else 3)
+        _say(f"case batch field {f.name}: oracle on velocities {ks}")
+        marg, worst = _check_lists(f, got, cnt, ks, max_marginal=2)
+        _say(f"  {f.name}: {int(cnt[ks].sum())} candidates on the sampled velocities, {marg} marginal "
+             f"decisions, max |dS'|/A' of listed fluxes {worst:.3g}")
+        assert worst <= 1e-5
+        fields[j] = None
+    batch.close()
+    for p in plans:
+        p.close()
+
+
+@pytest.mark.timeout(300)
+def test_plain_stack_160_frames(sst):
+    f = _long_spec().make()
+    _say(f"case plain stack {f.name}")
+    fr = torch.from_numpy(f.frames).to("cuda:0")
+    out, cov = sst.sst_stack(fr, f.t, f.t_ref, f.vx, f.vy, with_coverage=True)
+    torch.cuda.synchronize()
+    dx = oracle.shift_table(f.t, f.t_ref, f.vx)
+    dy = oracle.shift_table(f.t, f.t_ref, f.vy)
+    nvx = len(f.vx)
+    worst = 0.0
+    for k in (0, 20 * nvx + 20, len(f.vy) * nvx - 1, 7 * nvx + 33):
+        a, b = k % nvx, k // nvx
+        S, c, _, A = so.stack_velocity(f.frames, dx[:, a], dy[:, b], absolute=True)
+        g = out[b, a].cpu().numpy().astype(np.float64)
+        assert np.array_equal(cov[b, a].cpu().numpy(), c)
+        rel = np.abs(g - S) / np.maximum(A, 1e-30)
+        worst = max(worst, float(rel.max()))
+    _say(f"  max |dS|/A over 4 velocities of 160 frames: {worst:.3g}")
+    assert worst <= 1e-5
+
+
+@pytest.mark.timeout(300)
+def test_padded_frame_over_2gib_uses_direct_path(sst):
+    """Two 8192^2 frames 8 h apart with t_ref midway and velocities near
+    1950 px/h: shifts of about +-7800 px widen the padded frame to about
+    23.8k^2 floats (2.3 GB), past the staged path's 31-bit byte offsets."""
+    rng = np.random.default_rng(SEED_BASE + 360)
+    n, side = 2, 8192
+    frames = rng.normal(0.0, 1.0, size=(n, side, side)).astype(np.float32)
+    t = np.array([0.0, 8.0])
+    v = np.array([1950.0, 1950.5, 1951.0])
+    f = synth.Field("wide-shift 2x8192x8192 grid3x3", frames, t, 4.0, v, v.copy(), threshold=3.5, min_coverage=1,
+                    k_max=64)
+    _say(f"case {f.name}")
+    plan = sst.sst_plan_detect(n, side, side, t, 4.0, v, v, f.threshold, f.min_coverage, f.k_max)
+    _say(f"  staged={plan.staged} launches={plan.launches}")
+    assert not plan.staged
+    plan.close()
+    fr = torch.from_numpy(frames).to("cuda:0")
+    cand, count = sst.sst_detect(fr, t, 4.0, v, v, f.threshold, f.min_coverage, f.k_max)
+    torch.cuda.synchronize()
+    got = sst.candidates_to_numpy(cand)
+    cnt = count.cpu().numpy()
+    ks = [0, 8]
+    marg, _ = _check_lists(f, got, cnt, ks, max_marginal=2)
+    _say(f"  {int(cnt[ks].sum())} candidates on velocities {ks} match the oracle ({marg} marginal)")
+    assert cnt[0] > 0

@@ -70,15 +70,17 @@ def _check_stack(sst, f, bg=None, mode="sum", velocities=None):
         g = out[b, a].cpu().numpy().astype(np.float64)
         gc = cov[b, a].cpu().numpy()
         assert np.array_equal(gc, c), (k, np.argwhere(gc != c)[:5])
-        # 1e-5 of the sum of |terms| (the float32 target; from 84 frames on
-        # the worst-case float32 sum error N u, with a safety factor 2, takes
-        # over), plus the rounding of a float64 background to float32 once per
-        # term (c u |bg|)
-        rel = max(1e-5, 2.0 * f.n * 2.0 ** -24)
-        bgt = 0.0 if bg is None else 2.0 * 2.0 ** -24 * float(np.abs(bg).max())
+        # 1e-5 of the sum of |terms| (the float32 target), or where it is
+        # larger the worst-case error of any order of float32 additions of N
+        # terms, gamma_{N-1} = (N-1) u / (1 - (N-1) u) (from 169 frames on),
+        # plus, with a background, one rounding of each term's subtraction
+        # (u |F - b|) and of the background to float32 (u |bg|)
+        u = 2.0 ** -24
+        rel = max(1e-5, (f.n - 1) * u / (1 - (f.n - 1) * u)) + (0.0 if bg is None else u)
+        bgt = 0.0 if bg is None else 2.0 * u * float(np.abs(bg).max())
         if mode == "mean":
             ref = np.where(c > 0, S / np.maximum(c, 1), 0.0)
-            tol = rel * np.where(c > 0, A / np.maximum(c, 1), 0.0) + bgt + 1e-30
+            tol = rel * np.where(c > 0, A / np.maximum(c, 1), 0.0) + bgt + u * np.abs(ref) + 1e-30
         else:
             ref = S
             tol = rel * A + c * bgt + 1e-30

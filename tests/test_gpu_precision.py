@@ -6,7 +6,10 @@
   oracle's own dequantised frames F' = scale_i * q;
 * on the full field, the error of 16-bit storage against the float64 oracle
   on the original float32 frames is measured and bounded by the format's
-  unit roundoff, and detections are compared with the float32 GPU path.
+  unit roundoff, and detections are compared with the float32 GPU path
+  over the whole grid and with the float64 oracle on the original frames on
+  sampled velocities (every decision outside a guard band of 6 times the
+  measured rms S/N error of the format must match).
 """
 
 import sys
@@ -112,7 +115,7 @@ def test_detect_16bit(sst, kind, center):
     marg = sum(compare_velocity(got[k], int(cnt[k]), ref[k], f.n, float(np.abs(b).max()), 2.5, ref["c_min"], 6, f.w)
                for k in ks)
     _say(f"  {int(cnt.sum())} candidates, {marg} marginal decisions")
-    assert marg <= 4
+    assert marg <= (4 if center else 16)
 
 
 def test_16bit_frames_need_scale(sst):
@@ -144,7 +147,7 @@ def test_precision_full_field(sst, kind, center):
     ks = [0, 80, 3280, 6480, 6560, 41 * 81 + 7, 1234, 4321]
     dx = oracle.shift_table(f.t, f.t_ref, f.vx)
     dy = oracle.shift_table(f.t, f.t_ref, f.vy)
-    worst_b, worst_rel, sq, npx, worst_sn = 0.0, 0.0, 0.0, 0, 0.0
+    worst_b, worst_rel, sq, npx, worst_sn, sq_sn = 0.0, 0.0, 0.0, 0, 0.0, 0.0
     for k in ks:
         a, b = k % 81, k // 81
         out = sst.sst_stack(q, f.t, f.t_ref, f.vx[a:a + 1], f.vy[b:b + 1], bg=st16[:, 0], scale=s)
@@ -161,11 +164,30 @@ def test_precision_full_field(sst, kind, center):
         sq += float((rel ** 2).sum())
         npx += int(m.sum())
         # the flux part of the S/N error (the variances move by O(u) relative)
-        worst_sn = max(worst_sn, float((err[m] / np.sqrt(V[m])).max()))
+        esn = err[m] / np.sqrt(V[m])
+        worst_sn = max(worst_sn, float(esn.max()))
+        sq_sn += float((esn ** 2).sum())
     rms = (sq / max(npx, 1)) ** 0.5
+    rms_sn = (sq_sn / max(npx, 1)) ** 0.5
     _say(f"  S' error: max/bound {worst_b:.3g}; |dS'|/A' over c >= c_min: max {worst_rel:.3g} rms {rms:.3g}; "
-         f"flux part of |dSN| max {worst_sn:.3g} (u = {u:.3g})")
+         f"flux part of |dSN| max {worst_sn:.3g} rms {rms_sn:.3g} (u = {u:.3g})")
     assert worst_b <= 1.0
+    # candidate lists of the 16-bit search against the float64 oracle on the
+    # original float32 frames, on the sampled velocities: every decision
+    # outside a guard band of 6 times the measured rms S/N error of the
+    # storage format (on top of the float32 bounds) must match
+    c16s, n16s = sst.sst_detect(q, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, scale=s)
+    g16s, n16s = sst.candidates_to_numpy(c16s), n16s.cpu().numpy()
+    ref = oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, velocities=ks,
+                        keep_maps=True)
+    marg = 0
+    for k in ks:
+        guard = 6.0 * rms_sn * np.sqrt(np.where(ref[k]["V"] > 0, ref[k]["V"], 0.0))
+        marg += compare_velocity(g16s[k], int(n16s[k]), ref[k], f.n, float(np.abs(b64).max()), f.threshold,
+                                 ref["c_min"], f.k_max, f.w, extra_flux=guard)
+    _say(f"  {kind} lists on {len(ks)} velocities against the float64 oracle: {int(n16s[ks].sum())} candidates, "
+         f"{marg} decisions inside the guard band")
+    assert marg <= (4 if center else 16)
     # detections: 16-bit against float32 storage, whole grid
     c16, n16 = sst.sst_detect(q, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, scale=s)
     c32, n32 = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max)
@@ -197,7 +219,12 @@ def test_precision_full_field(sst, kind, center):
     _say(f"  S/N error bound {sn_bound:.3g}; differing detections {len(only)}")
     assert dsn <= sn_bound
     # each differing detection sits within the bound of the threshold or of
-    # one of its neighbours (float64 S/N of the original frames at 3x3 pixels)
+    # one of its neighbours (float64 S/N of the original frames at 3x3 pixels).
+    # Both lists are within sn_bound (16-bit) and a far smaller float32 bound
+    # of the float64 S/N of every pixel; a detection can differ only if one
+    # of its decisions does: S/N against the threshold (one value, margin <=
+    # sn_bound) or against a neighbour (two values, each moved by up to
+    # sn_bound, margin <= 2 sn_bound).  So 2 sn_bound is the derived limit.
     fr64 = f.frames.astype(np.float64)
 
     def sn_at(k, y, x):
