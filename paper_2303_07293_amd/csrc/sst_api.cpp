@@ -112,7 +112,8 @@ struct Plan {
     int shape = 0, vbx = 0, vby = 0;  // velocity-block shape
     int kt = 0, rows_per_chunk = 0, nchunk = 0;
     std::vector<int32_t> DX, DY;
-    std::vector<int32_t> G;  // per (velocity block, frame) staging geometry, kGeomRec ints
+    std::vector<int32_t> G;  // per velocity block: frame order and staging geometry (ord_stride ints)
+    size_t ord_stride = 0;
     // workspace offsets (bytes)
     size_t o_geom = 0, o_tab = 0, o_part = 0, o_b = 0, o_s2 = 0, o_P = 0, o_b32 = 0, o_sdev = 0;
     size_t o_ix = 0, o_iy = 0, o_pad = 0, o_tcount = 0, o_ent = 0, o_qpart = 0, o_dt = 0, total = 0;
@@ -174,7 +175,7 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
     p.ntiles = p.tiles_x * p.tiles_y;
     p.nslot = 2 * p.ntiles;  // one candidate slot per (tile, row half)
 
-    int dxmin = 0, dxmax = 0, dymin = 0, dymax = 0, sx = 0, sy = 0;
+    int dxmin = 0, dxmax = 0, dymin = 0, dymax = 0, sx = 0;
     for (int i = 0; i < n; ++i) {
         const int32_t* rx = &p.DX[(size_t)i * p.ldx];
         for (int a0 = 0; a0 < p.ldx; a0 += p.vbx) {
@@ -184,47 +185,81 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
             sx = std::max(sx, *mm.second - *mm.first);
         }
         const int32_t* ry = &p.DY[(size_t)i * p.ldy];
-        for (int b0 = 0; b0 < p.ldy; b0 += p.vby) {
-            const auto mm = std::minmax_element(ry + b0, ry + b0 + p.vby);
-            dymin = std::min(dymin, *mm.first);
-            dymax = std::max(dymax, *mm.second);
-            sy = std::max(sy, *mm.second - *mm.first);
-        }
+        const auto mm = std::minmax_element(ry, ry + p.ldy);
+        dymin = std::min(dymin, *mm.first);
+        dymax = std::max(dymax, *mm.second);
     }
-    p.staged = sx <= kSMaxX && sy <= kSMaxY;
+    // the staged window is CW columns wide: the tile plus the x-shift spread
+    // of a block
+    const int CW = shape_cw_max(shape);
+    p.staged = sx <= CW - kTileW;
     // zero padding so that every staged or direct read stays inside the copy
     const int X0max = (p.tiles_x - 1) * p.step_x;
     const int Y0max = (p.tiles_y - 1) * p.step_y;
-    p.padL = (int)align_up((size_t)std::max(0, -dxmin), 4);
+    p.padL = std::max(0, -dxmin);
     p.padT = std::max(0, -dymin);
-    // the staged window is kLdsPitch x kLdsRows from the block's smallest
-    // shift (aligned down by up to 3 columns), the direct path reads up to the
-    // largest shift plus the tile
-    const int need_w = std::max(X0max + dxmax + kTileW, X0max + dxmax + kStageW) + p.padL + 4;
-    const int need_h = std::max(Y0max + dymax + kRows, Y0max + dymax + kLdsRows) + p.padT;
-    p.Wp = (int)align_up((size_t)std::max(4, need_w), 16);
-    p.Hp = std::max(1, need_h);
+    // columns: a staged window runs CW columns from the tile origin plus the
+    // block's smallest shift; rows: kRG row groups from the row group of the
+    // pair's smaller y shift; the direct path reads up to the largest shift
+    // plus the tile; the frame itself lies inside
+    const int need_w = std::max(X0max + std::max(dxmax, 0) + CW, w) + p.padL;
+    const int need_h = std::max(Y0max + std::max(dymax, 0) + 4 * kRG + 4, h) + p.padT;
+    p.Wp = need_w;
+    p.Hp = (int)align_up((size_t)need_h, 4);
     // the staged path addresses each padded frame with 31-bit byte offsets;
     // larger padded frames (shifts of thousands of pixels on large frames)
     // take the direct path, which uses 64-bit addresses
     if ((size_t)p.Hp * (size_t)p.Wp * sizeof(float) > (size_t)0x7FFFFFFF) p.staged = false;
-    // Staging geometry of every velocity block and frame, the same for all
-    // tiles (tile origins are multiples of 4 columns): the byte offset of the
-    // window from the tile's origin in the frame's padded copy, then the LDS
-    // column of each x velocity and the LDS row offset of each y velocity.
-    p.G.assign((size_t)p.nvbx * p.nvby * n * kGeomRec, 0);
-    for (int by = 0; by < p.nvby; ++by)
-        for (int bx = 0; bx < p.nvbx; ++bx)
+    // Frame order and staging geometry of every velocity block (the same for
+    // all tiles: tile origins are multiples of 4 rows).  For frame i the
+    // pair's first rows sit at e0, e1 (shift + padT); the window starts at row
+    // group gy = min(e0, e1) / 4, and the read pattern is (f0, f1) = (e0, e1) -
+    // 4 gy when they are within 4 rows, else two separate reads at row groups
+    // G0, G1 past gy with phases e0 % 4, e1 % 4.  Frames are sorted by pattern
+    // (stable: ascending i within one); each block holds the frame count of
+    // every pattern, then per frame in that order its record: i, window byte
+    // offset in the frame (tile origin excluded), G0, G1, and the window
+    // column of each x velocity of the block.
+    const int rec_ints = shape_rec_ints(shape);
+    p.ord_stride = (size_t)kCountInts + (size_t)n * rec_ints;
+    p.G.assign((size_t)p.nvbx * p.nvby * p.ord_stride, 0);
+    std::vector<int> cas(n);
+    std::vector<int> order(n);
+    for (int by = 0; by < p.nvby && rc == SST_OK; ++by)
+        for (int bx = 0; bx < p.nvbx; ++bx) {
+            int32_t* blk = &p.G[((size_t)by * p.nvbx + bx) * p.ord_stride];
             for (int i = 0; i < n; ++i) {
-                const int32_t* rx = &p.DX[(size_t)i * p.ldx + (size_t)bx * p.vbx];
-                const int32_t* ry = &p.DY[(size_t)i * p.ldy + (size_t)by * p.vby];
-                const int mx = *std::min_element(rx, rx + p.vbx), my = *std::min_element(ry, ry + p.vby);
-                const int gx = mx + p.padL, xa = gx & ~3;
-                int32_t* g = &p.G[(((size_t)by * p.nvbx + bx) * n + i) * kGeomRec];
-                g[0] = (int32_t)((((long long)(my + p.padT)) * p.Wp + xa) * 4);
-                for (int j = 0; j < p.vbx; ++j) g[1 + j] = gx - xa + rx[j] - mx;
-                for (int j = 0; j < p.vby; ++j) g[1 + p.vbx + j] = (ry[j] - my) * kLdsPitch;
+                const int32_t* ry = &p.DY[(size_t)i * p.ldy + (size_t)by * kVYW];
+                const int e0 = ry[0] + p.padT, e1 = ry[1] + p.padT;
+                const int gy = std::min(e0, e1) >> 2;
+                const int f0 = e0 - 4 * gy, f1 = e1 - 4 * gy;
+                if (std::abs(f1 - f0) <= 4) {
+                    cas[i] = std::min(f0, f1) * 9 + (f1 - f0 + 4);
+                } else {
+                    cas[i] = kNShared + (e0 & 3) * 4 + (e1 & 3);
+                    // a separate read ends at row group G + 4 + 4 of the window
+                    if (std::max((e0 >> 2) - gy, (e1 >> 2) - gy) > kRG - 9) p.staged = false;
+                }
+                blk[cas[i]]++;
             }
+            for (int i = 0; i < n; ++i) order[i] = i;
+            std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return cas[u] < cas[v]; });
+            for (int k = 0; k < n; ++k) {
+                const int i = order[k];
+                const int32_t* rx = &p.DX[(size_t)i * p.ldx + (size_t)bx * p.vbx];
+                const int32_t* ry = &p.DY[(size_t)i * p.ldy + (size_t)by * kVYW];
+                const int mx = *std::min_element(rx, rx + p.vbx);
+                const int e0 = ry[0] + p.padT, e1 = ry[1] + p.padT;
+                const int gy = std::min(e0, e1) >> 2;
+                int32_t* r = &blk[kCountInts + (size_t)k * rec_ints];
+                r[0] = i;
+                // (meaningful on the staged path only, where it is below 2^31)
+                r[1] = (int32_t)((((long long)gy * p.Wp + mx + p.padL) * 16) & 0x7FFFFFFF);
+                r[2] = cas[i] >= kNShared ? (e0 >> 2) - gy : 0;
+                r[3] = cas[i] >= kNShared ? (e1 >> 2) - gy : 0;
+                for (int j = 0; j < p.vbx; ++j) r[4 + j] = rx[j] - mx;
+            }
+        }
 
     p.o_tab = take(cur, ((size_t)n * p.ldx + (size_t)n * p.ldy) * sizeof(int32_t));
     p.o_geom = take(cur, p.G.size() * sizeof(int32_t));
@@ -300,14 +335,16 @@ StackArgs stack_args(const Plan& p, void* ws) {
     StackArgs a{};
     a.pad = at<float>(ws, p.o_pad);
     a.fstride = (long long)p.Hp * p.Wp;
-    a.gchunk = (int)std::max<long long>(1, std::min<long long>(kGeomChunk, 0x7FFFFFFFll / (a.fstride * 4)));
     a.n = p.n;
     a.h = p.h;
     a.w = p.w;
     a.Wp = p.Wp;
     a.padL = p.padL;
     a.padT = p.padT;
-    a.geom = at<int>(ws, p.o_geom);
+    a.ord = at<int>(ws, p.o_geom);
+    a.ord_stride = (long long)p.ord_stride;
+    a.cw = shape_cw_max(p.shape);
+    a.ni = shape_ni_max(p.shape);
     a.DX = at<int>(ws, p.o_tab);
     a.DY = at<int>(ws, p.o_tab + (size_t)p.n * p.ldx * sizeof(int32_t));
     a.ldx = p.ldx;
@@ -319,8 +356,6 @@ StackArgs stack_args(const Plan& p, void* ws) {
     a.P = p.o_P ? at<double>(ws, p.o_P) : nullptr;
     a.tiles_x = p.tiles_x;
     a.tiles_y = p.tiles_y;
-    a.step_x = p.step_x;
-    a.step_y = p.step_y;
     a.nvbx = p.nvbx;
     a.vby0 = 0;
     a.nvby = p.nvby;
@@ -617,9 +652,10 @@ int sst_batch_create(const sst_plan* const* plans, int nplans, void* ws, size_t 
         R.args.start = at<int>(ws, L.o_start[r]);
         R.args.nprob = np;
         R.args.counter = at<int>(ws, L.o_cnt[r]);
-        // one workgroup per CU (the stacking kernel's occupancy), at least
-        // one per queue, the same number per queue
-        const int want = std::max(1, std::min(start[np], std::max(ncu, kBatchQueues)));
+        // as many workgroups as fit on the CUs at once (one per CU of 12
+        // waves, two of 6), at least one per queue, the same number per queue
+        const int per_cu = kMaxWaves / shape_waves(R.shape);
+        const int want = std::max(1, std::min(start[np], std::max(ncu * per_cu, kBatchQueues)));
         R.groups = (want + kBatchQueues - 1) / kBatchQueues * kBatchQueues;
         std::memcpy(host.data() + L.o_tab[r], tab.data(), tab.size() * sizeof(StackArgs));
         std::memcpy(host.data() + L.o_start[r], start.data(), start.size() * sizeof(int));

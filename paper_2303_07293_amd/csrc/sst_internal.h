@@ -16,55 +16,57 @@ namespace sst {
 typedef int i4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// Work decomposition of the stack kernels.  A workgroup is kWaves wave64s
-// (three per SIMD); it owns a tile of 64 columns (one per lane) by kRows
-// rows and a block of VBX x VBY trial velocities (a shape below), so every
-// staged frame tile is reused by all VBX * VBY velocities of the block.  Wave
-// w handles kRowsW = kRows / 2 rows (half w % 2) of kVPW x velocities and
-// kVYW = 2 neighbouring y velocities:
-// kVPW * kVYW * kRowsW float accumulators per lane.  For one frame the two
-// y velocities of a pair sample rows a small uniform distance d apart, so
-// one read of kRowsW + |d| staged rows feeds both sets of accumulators.
+// Work decomposition of the stack kernels.  A workgroup owns a tile of 64
+// columns (one per lane) by kRows rows and a block of VBX x 2 trial
+// velocities: one pair of neighbouring y velocities and VBX x velocities, so
+// that every staged frame window serves all 2 VBX velocities.  Wave w
+// handles the kRowsW = kRows / 2 rows of half w % 2 for kVPW x velocities
+// (group w / 2) and both y velocities: kVPW * 2 * kRowsW float accumulators
+// per lane.  For one frame the two y velocities sample rows a uniform
+// distance apart, so one read of the rows between them feeds both.
 constexpr int kWave = 64;
-constexpr int kWaves = 12;
-constexpr int kThreads = kWave * kWaves;
 constexpr int kTileW = 64;
 constexpr int kRows = 32;
 constexpr int kRowsW = kRows / 2;  // rows per wave
 constexpr int kVPW = 3;  // x velocities per wave
-constexpr int kVYW = 2;  // y velocities per wave
-constexpr int kDMax = 4; // largest |d| read once for both y velocities of a pair
-// Velocity-block shapes (chosen per plan): the kWaves / 2 waves of a row
-// half are NXG groups of kVPW x velocities times kWaves / 2 / NXG pairs of y
-// velocities.  Shape 0 is 9 x 4 (the default), shape 1 is 3 x 12 (for
-// small grids of small spread: less padding of the grid to whole blocks).
+constexpr int kVYW = 2;  // y velocities per block (one pair)
+// Velocity-block shapes (chosen per plan): workgroups of 12 waves (one per
+// CU; 18 x velocities per block) or of 6 waves (two per CU; 9 x velocities,
+// for grids whose x shifts spread too far for 18, or fewer x velocities).
 constexpr int kNShapes = 2;
-__host__ __device__ constexpr int shape_nxg(int sh) { return sh == 0 ? 3 : 1; }
-__host__ __device__ constexpr int shape_vbx(int sh) { return kVPW * shape_nxg(sh); }
-__host__ __device__ constexpr int shape_vby(int sh) { return kVYW * (kWaves / 2 / shape_nxg(sh)); }
-static_assert(shape_vbx(0) * shape_vby(0) * 2 == kVPW * kVYW * kWaves, "every (velocity, row half) of a block has one wave");
-static_assert(shape_vbx(1) * shape_vby(1) * 2 == kVPW * kVYW * kWaves, "every (velocity, row half) of a block has one wave");
-// LDS staging: the frame region a velocity block needs is the tile widened by
-// the spread of the block's shifts (at most kSMaxX / kSMaxY px) plus 3
-// columns of alignment slack for 16-byte staging.  A fixed window of
-// kStageW x kLdsRows floats is staged per frame; LDS rows are kLdsPitch = 128
-// floats apart so that every row of a column is reachable from one base
-// address (row offsets are multiples of 64 dwords).
-constexpr int kSMaxX = 40;
-constexpr int kSMaxY = 16;
-constexpr int kStageW = kTileW + kSMaxX + 4;
-constexpr int kLdsPitch = 128;
-constexpr int kLdsRows = kRows + kSMaxY;
-constexpr int kLdsBuf = kLdsPitch * kLdsRows;  // floats per staging buffer
-static_assert(kStageW % 4 == 0 && kStageW <= kLdsPitch, "16-byte staging chunks fit an LDS row");
+constexpr int kMaxWaves = 12;
+__host__ __device__ constexpr int shape_waves(int sh) { return sh == 0 ? 12 : 6; }
+__host__ __device__ constexpr int shape_vbx(int sh) { return kVPW * shape_waves(sh) / 2; }
+__host__ __device__ constexpr int shape_vby(int) { return kVYW; }
+// LDS staging.  The padded copy of every frame is stored in groups of four
+// rows: element (y, x) of a frame at float ((y / 4) * Wp + x) * 4 + y % 4, so
+// that one 16-byte chunk holds four consecutive rows of one column.  Per
+// frame a window of kRG row groups by cw columns (the tile widened by the
+// block's x-shift spread) is staged into LDS with the same layout, and a
+// lane reads four rows of its column with one 16-byte LDS read.
+constexpr int kRG = 13;  // row groups (52 rows) of the staged window
+__host__ __device__ constexpr int shape_cw_max(int sh) { return sh == 0 ? 144 : 100; }
+__host__ __device__ constexpr int shape_nbuf(int sh) { return sh == 0 ? 4 : 3; }
+// staging instructions (64 chunks each) of the largest window
+__host__ __device__ constexpr int shape_ni_max(int sh) { return (kRG * shape_cw_max(sh) + kWave - 1) / kWave; }
+// Frame order.  Within the window the rows of the pair's two y velocities
+// start at row offsets f0, f1 of the window's first row group; the pattern
+// (f0, f1) of a frame is one of kNCase read cases: 36 where the two start
+// within 4 rows of each other (min(f0, f1) in 0..3, f1 - f0 in -4..4; one
+// read of the rows between them serves both) and 16 where they are further
+// apart (each y velocity read on its own, at its own row group, phases 0..3).
+// The host sorts each block's frames by case, and the kernel runs one loop
+// per case whose read pattern is fixed at compile time.
+constexpr int kNShared = 36;
+constexpr int kNCase = kNShared + 16;
+constexpr int kCountInts = 64;  // per-block header: frames of each case (kNCase used)
+__host__ __device__ constexpr int shape_rec_ints(int sh) { return (4 + shape_vbx(sh) + 3) / 4 * 4; }
 
 constexpr int kStatThreads = 256;
 constexpr int kStatChunk = 8192;  // pixels per frame-statistics workgroup
 constexpr int kMaxK = 1024;       // largest k_max accepted
 constexpr int kMergeLds = 2048;   // entries ranked in LDS by the merge kernel
 constexpr int kPLds = 1024;       // variance-prefix entries the stack kernel keeps in LDS
-constexpr int kGeomChunk = 256;   // frames per buffer descriptor of the stack kernel (at most)
-constexpr int kGeomRec = 16;      // ints per (velocity block, frame) geometry record
 
 // One candidate kept by a (tile, velocity) before the per-velocity merge.
 struct Entry {
@@ -91,11 +93,19 @@ __device__ __forceinline__ float frame_value(const void* f, long long e, float s
 }
 
 struct StackArgs {
-    const float* pad;   // zero-padded, background-subtracted frames [n][Hp][Wp]
-    long long fstride;  // Hp * Wp
+    const float* pad;   // zero-padded, background-subtracted frames [n][Hp/4][Wp][4] (row groups)
+    long long fstride;  // Hp * Wp floats per frame
     int n, h, w;
     int Wp, padL, padT;
-    const int* geom;  // [nvby][nvbx][n][kGeomRec] staging geometry of each velocity block and frame
+    // per velocity block [nvby][nvbx]: kCountInts ints (frames of each read
+    // case), then per frame in the block's order a record of rec ints:
+    // frame index, window byte offset in the frame (tile origin excluded),
+    // row-group offsets of the two y velocities (separate-read cases), and
+    // the window column of each x velocity of the block
+    const int* ord;
+    long long ord_stride;  // ints per block
+    int cw;   // window columns
+    int ni;   // staging instructions (64 chunks) per frame
     const int* DX;  // [n][ldx] clamped x shifts, columns >= nvx repeat column nvx-1
     const int* DY;  // [n][ldy]
     int ldx, ldy;
@@ -103,8 +113,7 @@ struct StackArgs {
     const int* IX;    // [nvx][w][2]: first and last frame whose x sample is in the frame
     const int* IY;    // [nvy][h][2]
     const double* P;  // [n+1] prefix sums of the frame variances
-    int gchunk;     // frames per geometry chunk (their padded frames span < 2^31 bytes)
-    int tiles_x, tiles_y, step_x, step_y;
+    int tiles_x, tiles_y;
     int nvbx;        // velocity blocks along x
     int vby0, nvby;  // velocity-block rows handled by this launch
     // plain stack

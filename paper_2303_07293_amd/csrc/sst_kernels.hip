@@ -18,6 +18,7 @@
 #include <climits>
 #include <cmath>
 #include <type_traits>
+#include <utility>
 
 namespace sst {
 
@@ -182,36 +183,35 @@ __global__ __launch_bounds__(kAux) void k_stats_final(const double* __restrict__
 }
 
 // ------------------------------------------------------------ padded copy
-// pad[i][yp][xp] = F_i(xp - padL, yp - padT) - b32[i] inside the frame, 0
-// outside: out-of-frame samples then add nothing, and every staging read of
-// the stack kernel is an unconditional aligned 16-byte load.
-// One thread per 16-byte chunk of a frame's padded copy, numbered row by
-// row over the whole frame (every thread of a workgroup has a chunk, rows
-// need not fill workgroups).
+// pad[i] = F_i(x - padL, y - padT) - b32[i] inside the frame, 0 outside, in
+// row groups: element (y, x) at float ((y / 4) * Wp + x) * 4 + y % 4.  Out-of-
+// frame samples then add nothing, and the stack kernel stages any window
+// with unconditional 16-byte loads, each holding four rows of one column.
+// One thread per 16-byte chunk (row group, column) of a frame; consecutive
+// threads take consecutive columns, so the four row reads and the chunk
+// write are coalesced.
 template <int DT>
 __global__ __launch_bounds__(kAux) void k_prep(const PrepArgs a) {
     const int i = blockIdx.y;
-    // (a padded frame has fewer than 2^31 chunks: shifts are clamped to the
-    // frame's size, so each padded side is at most about three times 16384)
-    const unsigned c4 = (unsigned)a.Wp / 4;
+    // (a padded frame has fewer than 2^31 bytes on the staged path and far
+    // fewer than 2^32 chunks on any path: sides are at most about 3 x 16384)
     const unsigned q = blockIdx.x * kAux + threadIdx.x;
-    if (q >= (unsigned)a.Hp * c4) return;
-    const int yp = (int)(q / c4);
-    const int xp = (int)(q - (unsigned)yp * c4) * 4;
-    const int y = yp - a.padT;
+    const unsigned ng = (unsigned)a.Hp / 4;
+    if (q >= ng * (unsigned)a.Wp) return;
+    const int g = (int)(q / (unsigned)a.Wp);
+    const int xp = (int)(q - (unsigned)g * (unsigned)a.Wp);
+    const int x = xp - a.padL;
     float o[4] = {0.f, 0.f, 0.f, 0.f};
-    if (y >= 0 && y < a.h) {
+    if (x >= 0 && x < a.w) {
         const float bb = a.b32 ? a.b32[i] : 0.f;
         const float sc = DT == SST_F32 ? 1.f : a.scale[i];
-        const long long row = ((long long)i * a.h + y) * a.w;
-        const int x0 = xp - a.padL;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int x = x0 + k;
-            o[k] = (x >= 0 && x < a.w) ? frame_value<DT>(a.frames, row + x, sc) - bb : 0.f;
+            const int y = 4 * g + k - a.padT;
+            if (y >= 0 && y < a.h) o[k] = frame_value<DT>(a.frames, ((long long)i * a.h + y) * a.w + x, sc) - bb;
         }
     }
-    f4* dst = reinterpret_cast<f4*>(a.pad + (long long)i * a.Hp * a.Wp + (long long)yp * a.Wp + xp);
+    f4* dst = reinterpret_cast<f4*>(a.pad + (long long)i * a.Hp * a.Wp + (long long)q * 4);
     *dst = f4{o[0], o[1], o[2], o[3]};
 }
 
@@ -301,43 +301,143 @@ __device__ __forceinline__ int coverage(int xlo, int xhi, int ylo, int yhi, int&
 }
 
 // -------------------------------------------------------------- stacking
-// Per-frame geometry of a velocity block comes from a table the host builds
-// with the shift tables (the same for every tile, whose origins are
-// multiples of 4 columns): for frame i the staged window is the kStageW x
-// kLdsRows region of the padded copy whose origin is the 16-byte aligned
-// column at or left of X0 + (smallest x shift of the block) and the row Y0 +
-// (smallest y shift); its record holds the window's byte offset from the
-// tile's origin, the LDS column of each x velocity and the LDS row offset of
-// each y velocity.  The frames of one buffer descriptor (a chunk of at most
-// kGeomChunk frames, fewer when they would span more than 2^31 bytes of the
-// padded copy) are addressed by 31-bit byte offsets.
-constexpr int kNBuf = 3;  // staging buffers: frames j and j + 1 readable, j + 2 loading
+// A work item is a tile (64 columns x 32 rows) and a velocity block (VBX x
+// velocities, one pair of y velocities).  Per frame the workgroup stages one
+// window of the padded copy into LDS: kRG row groups by CW columns starting
+// at the tile origin shifted by the block's smallest x shift and by the
+// smaller of the pair's y shifts, rounded down to a row group.  Every
+// velocity of the block then reads its samples from that window: lane l of
+// x velocity a reads column c_a + l, y velocity b reads rows from f_b, with
+// one 16-byte LDS read per four rows.  The row phases (f0, f1) of a frame
+// select one of kNCase read patterns; the host sorts each block's frames by
+// pattern and the kernel runs one loop per pattern, so every read and add is
+// fixed at compile time and no per-frame dispatch remains.  Frames are summed
+// in that order (the float32 sum of the same terms, in a fixed order that
+// depends only on the block and the frames' shifts).
+//
+// Staging is a ring of NBUF buffers: while frame k is added, frames k + 1 ..
+// k + NBUF - 2 have been issued and frame k + NBUF - 1 is issued now; each
+// wave waits only for its own loads of frame k + 1 before the barrier that
+// ends frame k.  Loads go straight to LDS (buffer load with LDS destination:
+// lane l's 16 bytes land at the instruction's base + 16 l), each frame through
+// its own buffer descriptor (the frame's padded copy is below 2^31 bytes on
+// this path).  The workgroup has exactly one LDS object: with several, the
+// compiler makes every LDS read wait for all pending LDS-destination loads.
 
-constexpr int kC4 = kStageW / 4;  // float4 chunks per staged row
-static_assert(kC4 <= 32 && kLdsRows % (2 * kWaves) == 0, "two staged rows per wave instruction");
-constexpr int kStage = kLdsRows / (2 * kWaves);  // staging loads per thread and frame
+typedef const __attribute__((address_space(3))) int LInt;
+typedef const __attribute__((address_space(3))) float LFloat;
+// read-only tables of the launch (the frame order): uniform loads are scalar
+typedef const __attribute__((address_space(4))) int CInt;
 
-// Staging: wave w, load j covers staged rows 2*(w + kWaves*j) and the next
-// one: lane l reads float4 column l & 31 of row 2*(w + kWaves*j) + (l >> 5),
-// lanes with column >= kC4 idle.  The LDS layout is lane-contiguous (32
-// float4 per 128-float row), so each load writes LDS directly (buffer load
-// with LDS destination: lane l's 16 bytes land at the wave's row base + 16 l)
-// and no register holds the window.  The per-lane part of the address is
-// constant; the frame and j parts are scalar byte offsets.
-__device__ __forceinline__ void stage_frame(__amdgpu_buffer_rsrc_t rsrc, int voff, int sbyte, int Wp, bool act,
-                                            float* buf, int wave) {
+// float index of element (y, x) of a padded frame in row-group layout
+__device__ __forceinline__ long long pad_at(int y, int x, int Wp) {
+    return ((long long)(y >> 2) * Wp + x) * 4 + (y & 3);
+}
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// Read pattern C: row phases f0, f1 of the pair's first rows in the groups
+// read, and the number of row groups holding a wave's 16 rows from a phase.
+template <int C>
+struct Case {
+    static constexpr bool shared = C < kNShared;
+    static constexpr int lo = C / 9, dd = C % 9 - 4;
+    static constexpr int f0 = shared ? (dd >= 0 ? lo : lo - dd) : (C - kNShared) / 4;
+    static constexpr int f1 = shared ? (dd >= 0 ? lo + dd : lo) : (C - kNShared) % 4;
+    static constexpr int g0 = (f0 + kRowsW - 1) / 4 + 1;
+    static constexpr int g1 = (f1 + kRowsW - 1) / 4 + 1;
+    static constexpr int gs = (cmax(f0, f1) + kRowsW - 1) / 4 + 1;
+};
+
+// G row groups of one column from p (group stride CW chunks) into v
+template <int G, int CW>
+__device__ __forceinline__ void read_groups(const f4* p, float (&v)[24]) {
+    static_assert(G <= 6, "at most 24 rows");
 #pragma unroll
-    for (int j = 0; j < kStage; ++j) {
-        if (act) {
-            auto* dst = (__attribute__((address_space(3))) void*)(buf + 2 * (wave + kWaves * j) * kLdsPitch);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, dst, 16, voff, sbyte + j * 2 * kWaves * Wp * 4, 0, 0);
+    for (int j = 0; j < G; ++j) {
+        const f4 t = p[j * CW];
+        v[4 * j] = t.x;
+        v[4 * j + 1] = t.y;
+        v[4 * j + 2] = t.z;
+        v[4 * j + 3] = t.w;
+    }
+}
+
+template <int F>
+__device__ __forceinline__ void add_rows(const float (&v)[24], float (&a)[kRowsW]) {
+    static_assert(F + kRowsW <= 24, "rows inside the read");
+#pragma unroll
+    for (int r = 0; r < kRowsW; ++r) a[r] += v[r + F];
+}
+
+// Frame k's adds for the wave's kVPW x velocities (columns col[q]) in
+// pattern C; base = the wave's first row group of the staged window at lane
+// column 0; go0, go1 = row-group offsets of the two y velocities (separate
+// patterns only).  The reads of the next x velocity are issued before the
+// adds of the current one.
+template <int C, int CW>
+__device__ __forceinline__ void add_frame(const f4* base, const int (&col)[kVPW], int go0, int go1,
+                                          float (&acc)[kVPW][kVYW][kRowsW]) {
+    using K = Case<C>;
+    static_assert(kVPW == 3, "three x velocities per wave");
+    float va[24], vb[24];
+    if constexpr (K::shared) {
+        read_groups<K::gs, CW>(base + col[0], va);
+        read_groups<K::gs, CW>(base + col[1], vb);
+        add_rows<K::f0>(va, acc[0][0]);
+        add_rows<K::f1>(va, acc[0][1]);
+        read_groups<K::gs, CW>(base + col[2], va);
+        add_rows<K::f0>(vb, acc[1][0]);
+        add_rows<K::f1>(vb, acc[1][1]);
+        add_rows<K::f0>(va, acc[2][0]);
+        add_rows<K::f1>(va, acc[2][1]);
+    } else {
+        const f4* b0 = base + go0 * CW;
+        const f4* b1 = base + go1 * CW;
+#pragma unroll
+        for (int q = 0; q < kVPW; ++q) {
+            read_groups<K::g0, CW>(b0 + col[q], va);
+            read_groups<K::g1, CW>(b1 + col[q], vb);
+            add_rows<K::f0>(va, acc[q][0]);
+            add_rows<K::f1>(vb, acc[q][1]);
         }
     }
 }
 
-// Wait until this wave's loads into LDS have landed (vmcnt 0; expcnt and
-// lgkmcnt not waited for); a barrier after it publishes them to the group.
-__device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// This wave's share of one frame's staging: its loads j < nst (instruction
+// wave + NW j of the frame), each 64 lanes x 16 bytes from the padded frame
+// at byte offsets voff[j] + soff into buf + 64 (wave + NW j) chunks.
+template <int NW, int NSTX>
+__device__ __forceinline__ void stage_window(const float* frame, int fbytes, const int (&voff)[NSTX], int nst,
+                                             int soff, float* buf, int wave) {
+    // (device pass only: the host pass of a template instantiated from a
+    // lambda cannot resolve the buffer-resource builtins)
+#if defined(__HIP_DEVICE_COMPILE__)
+    const auto rs = __builtin_amdgcn_make_buffer_rsrc((void*)frame, 0, fbytes, 0x00020000);
+#pragma unroll
+    for (int j = 0; j < NSTX; ++j) {
+        if (j < nst) {
+            auto* dst = (__attribute__((address_space(3))) void*)(buf + (wave + NW * j) * kWave * 4);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 16, voff[j], soff, 0, 0);
+        }
+    }
+#endif
+}
+
+// Wait until at most N of this wave's loads into LDS are in flight (vmcnt N;
+// expcnt and lgkmcnt not waited for).
+template <int N>
+__device__ __forceinline__ void wait_loads() {
+    static_assert(N >= 0 && N < 16, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt(0x0F70 | N);
+}
+
+// Workgroup barrier with no memory fence: every wave has already waited for
+// its own loads into LDS, and a staging buffer is refilled only after the
+// barrier that follows the last reads of its frame.  (A fenced barrier would
+// make each wave wait for all of its loads, including the frames still
+// meant to be in flight.)
+__device__ __forceinline__ void barrier_no_fence() { asm volatile("s_barrier" ::: "memory"); }
 
 // S/N, peak test and candidate output of one (tile, velocity) for one wave.
 // Tiles do not overlap: the wave holds rows 16h .. 16h + 15 (h = row half)
@@ -351,18 +451,13 @@ __device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70
 // (that row, and the columns left of lane 0 and right of lane 63) first
 // count as -infinity; a pixel that passes the test against everything
 // inside the tile then has its outside neighbours' S/N evaluated directly,
-// a sum over the frames of the padded copy in frame order: the same float32
-// adds of the same values as the workgroup that owns that pixel, hence the
-// same S/N.  The S/N of a row is recomputed where it is needed rather than
-// stored, to keep the register footprint of this epilogue below the main
-// loop's.
+// a sum over the frames of the padded copy in the block's frame order: the
+// same float32 adds of the same values as the workgroup that owns that
+// pixel, hence the same S/N.  The S/N of a row is recomputed where it is
+// needed rather than stored, to keep the register footprint of this
+// epilogue below the main loop's.
 constexpr int kColRows = kRowsW + 2;
 constexpr unsigned kEmitRows = ((1u << (kColRows - 1)) - 1u) & ~1u;  // column rows 1 .. kColRows - 2
-
-// LDS and global pointers by address space, so that a function that is not
-// inlined still reads LDS with LDS instructions (not flat ones)
-typedef const __attribute__((address_space(3))) int LInt;
-typedef const __attribute__((address_space(3))) float LFloat;
 
 struct SnCtx {
     LInt* IYr;    // [kColRows][2] y coverage intervals of the column's rows
@@ -393,10 +488,11 @@ __device__ __forceinline__ float sn_row(const SnCtx& c, float acc, int r, int& c
     return V > 0.0 ? acc * rsqrtf((float)V) : 0.f;
 }
 
-// S/N of pixel (x, y) at velocity (a, b) evaluated on its own: the
-// frame-ordered sum of its shifted samples of the padded copy, then the same
-// normalisation as sn_row.
-__device__ __forceinline__ float sn_direct(KArgs A, const double* P, int a, int b, int x, int y) {
+// S/N of pixel (x, y) at velocity (a, b) evaluated on its own: the sum of its
+// shifted samples of the padded copy in its block's frame order (the order of
+// the work items), then the same normalisation as sn_row.  vbx and rec are
+// the shape's block width and record size.
+__device__ __forceinline__ float sn_direct(KArgs A, const double* P, int a, int b, int x, int y, int vbx, int rec) {
     if (x < 0 || x >= A->w || y < 0 || y >= A->h) return -INFINITY;
     int xlo, xhi, ylo, yhi, lo, hi;
     load_iv(A->IX, (long long)a * A->w + x, xlo, xhi);
@@ -407,14 +503,16 @@ __device__ __forceinline__ float sn_direct(KArgs A, const double* P, int a, int 
     GFloat* pad = (GFloat*)A->pad;
     GInt* DX = (GInt*)A->DX;
     GInt* DY = (GInt*)A->DY;
+    GInt* ordr = (GInt*)(A->ord + (long long)((b / kVYW) * A->nvbx + a / vbx) * A->ord_stride + kCountInts);
     const long long fstride = A->fstride;
     const int Wp = A->Wp, ldx = A->ldx, ldy = A->ldy, n = A->n;
     const int x0 = x + A->padL, y0 = y + A->padT;
     float acc = 0.f;
 #pragma unroll 1
-    for (int i = 0; i < n; ++i) {
+    for (int k = 0; k < n; ++k) {
+        const int i = ordr[(long long)k * rec];
         const int dx = DX[(long long)i * ldx + a], dy = DY[(long long)i * ldy + b];
-        acc += pad[(long long)i * fstride + (long long)(y0 + dy) * Wp + (x0 + dx)];
+        acc += pad[(long long)i * fstride + pad_at(y0 + dy, x0 + dx, Wp)];
     }
     const double V = P[hi + 1] - P[lo];
     return V > 0.0 ? acc * rsqrtf((float)V) : 0.f;
@@ -428,7 +526,7 @@ __device__ __forceinline__ float sn_direct(KArgs A, const double* P, int a, int 
 __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* RSr, const double* P,
                                                     int xlo, int xhi, int a, int b, long long slot,
                                                     LFloat* col, unsigned fl, int lane, int x, int Yc,
-                                                    int orow) {
+                                                    int orow, int vbx, int rec) {
     SnCtx c;
     c.IYr = IYr;
     c.RSr = RSr;
@@ -491,7 +589,7 @@ __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* 
             const int dy = k / 3 - 1, dx = k % 3 - 1;
             const bool outside = lane + dx < 0 || lane + dx >= kWave || r + dy == orow;
             if (k == 4 || !outside) continue;
-            const float sq = sn_direct(A, P, a, b, x + dx, Yc + r + dy);
+            const float sq = sn_direct(A, P, a, b, x + dx, Yc + r + dy, vbx, rec);
             const bool earlier = dy < 0 || (dy == 0 && dx < 0);
             ok = earlier ? s > sq : s >= sq;
         }
@@ -547,11 +645,12 @@ __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* 
 // else NaN, so that acc * rsm[r] > threshold is exactly the threshold and
 // coverage test (NaN compares false).  xrow is the other row half's boundary
 // row of the same velocity; IYr and RSr start at column row 0 (tile row R0).
-__device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, int vby, const float (&acc)[kRowsW],
+__device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, const float (&acc)[kRowsW],
                                                 const float (&rsm)[kRowsW], int a, int b, int x, bool xin, int lane,
                                                 int h, int Y0, int tile, float* col, const float* xrow,
-                                                const int* IYr, const float* RSr, const double* P, int xlo, int xhi) {
-    const long long kc = (long long)(b - A.vby0 * vby) * A.nvx + a;
+                                                const int* IYr, const float* RSr, const double* P, int xlo, int xhi,
+                                                int vbx, int rec) {
+    const long long kc = (long long)(b - A.vby0 * kVYW) * A.nvx + a;
     const long long slot = kc * A.nslot + 2 * tile + h;
     SnCtx c;
     c.IYr = (LInt*)IYr;
@@ -597,109 +696,48 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, in
 #pragma unroll
     for (int r = 0; r < kRowsW; ++r) own[r * kWave + lane] = acc[r];
     col[(h ? 0 : kColRows - 1) * kWave + lane] = xrow[lane];
-    candidates_from_column(Ap, (LInt*)IYr, (LFloat*)RSr, P, xlo, xhi, a, b, slot, (LFloat*)col, fl,
-                           lane, x, Y0 + kRowsW * h - 1, h ? kColRows - 1 : 0);
+    candidates_from_column(Ap, (LInt*)IYr, (LFloat*)RSr, P, xlo, xhi, a, b, slot, (LFloat*)col, fl, lane, x,
+                           Y0 + kRowsW * h - 1, h ? kColRows - 1 : 0, vbx, rec);
 }
-
-// One frame's samples for a wave whose two y velocities sample rows D apart
-// (velocity S0 the upper one): staged rows j = 0 .. kRowsW + D - 1 from p
-// feed acc[.][S0][j] and acc[.][1 - S0][j - D].
-template <int D, int S0>
-__device__ __forceinline__ void accum_pair(const float* p, const int (&col)[kVPW],
-                                           float (&acc)[kVPW][kVYW][kRowsW]) {
-    float v[kVPW][kRowsW + D];
-#pragma unroll
-    for (int q = 0; q < kVPW; ++q)
-#pragma unroll
-        for (int j = 0; j < kRowsW + D; ++j) v[q][j] = p[col[q] + j * kLdsPitch];
-#pragma unroll
-    for (int q = 0; q < kVPW; ++q)
-#pragma unroll
-        for (int r = 0; r < kRowsW; ++r) {
-            acc[q][S0][r] += v[q][r];
-            acc[q][1 - S0][r] += v[q][r + D];
-        }
-}
-
-// The same for rows too far apart to share reads.
-__device__ __forceinline__ void accum_sep(const float* p0, const float* p1, const int (&col)[kVPW],
-                                          float (&acc)[kVPW][kVYW][kRowsW]) {
-#pragma unroll
-    for (int s = 0; s < kVYW; ++s) {
-        const float* p = s ? p1 : p0;
-        float v[kVPW][kRowsW];
-#pragma unroll
-        for (int q = 0; q < kVPW; ++q)
-#pragma unroll
-            for (int r = 0; r < kRowsW; ++r) v[q][r] = p[col[q] + r * kLdsPitch];
-#pragma unroll
-        for (int q = 0; q < kVPW; ++q)
-#pragma unroll
-            for (int r = 0; r < kRowsW; ++r) acc[q][s][r] += v[q][r];
-    }
-}
-
-// Pipelined form of the above.  For each x velocity all kRowsW + kDMax
-// staged rows from the lower of the pair's two row offsets are read,
-// whatever d the frame has (for |d| > kDMax the values are not used); the
-// adds of a frame then only pick v[.][r] and v[.][r + D].  The reads of a
-// frame are staggered: those of its first x velocity are issued before the
-// previous barrier, the second's before its adds start and the third's
-// after the first velocity's adds, so that a wave has at most about 14 LDS
-// operations in flight and each wait covers one velocity's rows.
-constexpr int kRowsR = kRowsW + kDMax;
-
-__device__ __forceinline__ void read_rows_q(const float* p, int col, float (&vq)[kRowsR]) {
-#pragma unroll
-    for (int j = 0; j < kRowsR; ++j) vq[j] = p[col + j * kLdsPitch];
-}
-
-template <int D, int S0>
-__device__ __forceinline__ void add_rows_q(const float (&vq)[kRowsR], float (&aq)[kVYW][kRowsW]) {
-#pragma unroll
-    for (int r = 0; r < kRowsW; ++r) {
-        aq[S0][r] += vq[r];
-        aq[1 - S0][r] += vq[r + D];
-    }
-}
-
-// The adds of one frame (read distance D, S0 the upper y velocity), with
-// the third x velocity's rows read from p after the first one's adds.
-template <int D, int S0>
-__device__ __forceinline__ void add_frame(float (&v)[kVPW][kRowsR], float (&acc)[kVPW][kVYW][kRowsW],
-                                          const float* p, int col2) {
-    static_assert(kVPW == 3, "three x velocities per wave");
-    add_rows_q<D, S0>(v[0], acc[0]);
-    read_rows_q(p, col2, v[2]);
-    add_rows_q<D, S0>(v[1], acc[1]);
-    add_rows_q<D, S0>(v[2], acc[2]);
-}
-
-// Workgroup barrier that leaves LDS reads in flight.  Ordering is the
-// caller's: every wave waits for its own loads into LDS before it, and a
-// staging buffer is only refilled two frames after the adds that consumed
-// its reads.  The memory clobber keeps the compiler from moving memory
-// accesses across it.
-__device__ __forceinline__ void barrier_keep_reads() { asm volatile("s_barrier" ::: "memory"); }
 
 template <int V>
 using ic = std::integral_constant<int, V>;
 
+// f(ic<C>{}) for every C of the sequence, in order
+template <typename F, int... Cs>
+__device__ __forceinline__ void for_cases(F& f, std::integer_sequence<int, Cs...>) {
+    (f(ic<Cs>{}), ...);
+}
+
+// LDS floats of a workgroup of shape SH: the staging ring, or after the frame
+// loop the epilogue's areas (candidate columns, exchanged boundary rows,
+// coverage and normaliser tables, variance prefix), whichever is larger, plus
+// one int for the batch kernel's work counter.
+template <int SH>
+struct Lds {
+    static constexpr int NW = shape_waves(SH);
+    static constexpr int buf = shape_ni_max(SH) * kWave * 4;  // floats per staging buffer
+    static constexpr int stage = shape_nbuf(SH) * buf;
+    static constexpr int colf = NW * kColRows * kWave;
+    static constexpr int xch = NW * kVPW * kVYW * kWave;
+    static constexpr int iy = ((kVYW * kRows + 1) * 2 + 3) / 4 * 4;  // (areas stay 16-byte aligned)
+    static constexpr int rs = (kVYW * kRows + 1 + 3) / 4 * 4;
+    static constexpr int rm = kVYW * kRows;
+    static constexpr int p = 2 * kPLds;  // doubles
+    static constexpr int epi = colf + xch + iy + rs + rm + p;
+    static constexpr int total = (stage > epi ? stage : epi) + 4;
+};
+
 // One work item of the stacking kernels: tile and velocity block number
-// `logical` of the problem A describes (Ap: where a callee reads A).
+// `logical` of the problem A describes (Ap: where a callee reads A); lds is
+// the workgroup's LDS array (Lds<SH>::total floats).
 template <bool DETECT, bool STAGED, int SH>
-__device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int logical) {
-    constexpr int VBX = shape_vbx(SH), VBY = shape_vby(SH), NYP = VBY / kVYW;
-    static_assert(1 + VBX + VBY <= kGeomRec, "geometry record");
-    // LDS: two staging buffers during the frame loop; afterwards each wave's
-    // candidate column and the published boundary rows of every wave
-    constexpr int kColFloats = kWaves * kColRows * kWave;
-    constexpr int kXchFloats = kWaves * kVPW * kVYW * kWave;
-    // three staging buffers, plus the rows the unconditional read of the
-    // last buffer may run past its end
-    constexpr int kStageFloats = kNBuf * kLdsBuf + kDMax * kLdsPitch;
-    constexpr int kLdsFloats = (kStageFloats > kColFloats + kXchFloats) ? kStageFloats : kColFloats + kXchFloats;
-    __shared__ __attribute__((aligned(16))) float lds[kLdsFloats];
+__device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int logical, float* lds) {
+    constexpr int NW = shape_waves(SH), VBX = shape_vbx(SH), CW = shape_cw_max(SH);
+    constexpr int NBUF = shape_nbuf(SH), NI = shape_ni_max(SH), REC = shape_rec_ints(SH);
+    constexpr int BUFF = Lds<SH>::buf;
+    constexpr int NSTX = (NI + NW - 1) / NW;  // most staging loads per wave and frame
+    static_assert(NI >= NW && NSTX * (NBUF - 2 > 0 ? NBUF - 2 : 1) < 16, "every wave stages; vmcnt field");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -707,18 +745,19 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     const int tile = logical / nvb;
     const int vb = logical - tile * nvb;
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
-    const int a0 = (vb % A.nvbx) * VBX;
-    const int b0 = (A.vby0 + vb / A.nvbx) * VBY;
-    const int xg = wave / (2 * NYP);  // which kVPW-group of the block's x velocities
-    const int yp = (wave / 2) % NYP;  // which pair of the block's y velocities
-    const int h = wave % 2;           // row half
-    const int aw = a0 + kVPW * xg;    // this wave's first x velocity
-    const int bw = b0 + kVYW * yp;    // this wave's first y velocity
+    const int bxi = vb % A.nvbx, byi = A.vby0 + vb / A.nvbx;
+    const int a0 = bxi * VBX;
+    const int b0 = byi * kVYW;  // the pair's first y velocity
+    const int xg = wave >> 1;   // which kVPW-group of the block's x velocities
+    const int h = wave & 1;     // row half
+    const int aw = a0 + kVPW * xg;  // this wave's first x velocity
     const int X0 = tx * kTileW;
     const int Y0 = ty * kRows;
     // waves whose velocities all lie past the grid (in a partial last block)
     // only help stage the frames
-    const bool busy = aw < A.nvx && bw < A.nvy;
+    const bool busy = aw < A.nvx && b0 < A.nvy;
+    CInt* blk = (CInt*)(A.ord + (long long)(byi * A.nvbx + bxi) * A.ord_stride);
+    CInt* rec = blk + kCountInts;  // record of the block's k-th frame at rec + k * REC
 
     float acc[kVPW][kVYW][kRowsW];
 #pragma unroll
@@ -729,147 +768,112 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             for (int r = 0; r < kRowsW; ++r) acc[q][s][r] = 0.f;
 
     if constexpr (STAGED) {
-        const int srow = 2 * wave + (lane >> 5);  // staged row of this lane's first load
-        const int scol = lane & 31;               // float4 column
-        const bool act = scol < kC4;
-        const int voff = (srow * A.Wp + 4 * scol) * 4;  // bytes, per lane
-        // this wave's geometry of a frame (its record in the block's table):
-        // the LDS row offsets of its two y velocities and the kVPW column
-        // offsets, read with buffer loads (counted by vmcnt, like the
-        // staging loads, so that LDS waits stay partial) and made scalar
-        const int gw_row = 1 + VBX + kVYW * yp, gw_col = 1 + kVPW * xg;
-        const int hoff = h * kRowsW * kLdsPitch;
-        const int tbase = (Y0 * A.Wp + X0) * 4;  // bytes of the tile's origin in a padded frame
-        const long long blk = (long long)((A.vby0 + vb / A.nvbx) * A.nvbx + vb % A.nvbx) * A.n;
-        for (int f0 = 0; f0 < A.n; f0 += A.gchunk) {
-            const int cnt = min(A.gchunk, A.n - f0);
-            const auto grs = __builtin_amdgcn_make_buffer_rsrc((void*)(A.geom + (blk + f0) * kGeomRec), 0,
-                                                               cnt * kGeomRec * 4, 0x00020000);
-            // record of frame k of the chunk: past the chunk's end its last
-            // frame (staged but never read)
-            auto recb = [&](int k) __attribute__((always_inline)) { return min(k, cnt - 1) * (kGeomRec * 4); };
-            auto ld_rows = [&](int k) __attribute__((always_inline)) {
-                return __builtin_amdgcn_raw_buffer_load_b64(grs, 0, recb(k) + gw_row * 4, 0);
-            };
-            auto ld_cols = [&](int k) __attribute__((always_inline)) {
-                return __builtin_amdgcn_raw_buffer_load_b128(grs, 0, recb(k) + gw_col * 4, 0);
-            };
-            auto ld_win = [&](int k) __attribute__((always_inline)) {
-                return __builtin_amdgcn_raw_buffer_load_b32(grs, 0, recb(k), 0);
-            };
-            // byte offset of frame k's window from the chunk's first frame
-            // (< 2^31 by the chunk size)
-            auto win = [&](int k, int rel) __attribute__((always_inline)) {
-                return (int)((long long)min(k, cnt - 1) * A.fstride * 4) + tbase + __builtin_amdgcn_readfirstlane((int)rel);
-            };
-            const long long rem = (long long)(A.n - f0) * A.fstride * 4;
-            const auto rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)(A.pad + (long long)f0 * A.fstride), 0,
-                                                                (int)min(rem, 0x7FFFFFFFll), 0x00020000);
-            // (the previous chunk's last barrier follows every wave's last
-            // use of its staged frames; its reads still in flight target
-            // staging rows whose values are never used)
-            // prologue: frames 0 and 1 of the chunk into buffers 0 and 1
-            stage_frame(rsrc, voff, win(0, ld_win(0)), A.Wp, act, lds, wave);
-            stage_frame(rsrc, voff, win(1, ld_win(1)), A.Wp, act, lds + kLdsBuf, wave);
-            // geometry of the frame being added (c), of the frame being read
-            // (n), and the window of the frame loaded next
-            const auto rw0 = ld_rows(0), rw1 = ld_rows(1);
-            const auto cl0 = ld_cols(0), cl1 = ld_cols(1);
-            int soff2 = win(2, ld_win(2));
-            int r0c = __builtin_amdgcn_readfirstlane((int)rw0[0]), r1c = __builtin_amdgcn_readfirstlane((int)rw0[1]);
-            int r0n = __builtin_amdgcn_readfirstlane((int)rw1[0]), r1n = __builtin_amdgcn_readfirstlane((int)rw1[1]);
-            int colc[kVPW] = {__builtin_amdgcn_readfirstlane((int)cl0[0]), __builtin_amdgcn_readfirstlane((int)cl0[1]),
-                              __builtin_amdgcn_readfirstlane((int)cl0[2])};
-            int coln[kVPW] = {__builtin_amdgcn_readfirstlane((int)cl1[0]), __builtin_amdgcn_readfirstlane((int)cl1[1]),
-                              __builtin_amdgcn_readfirstlane((int)cl1[2])};
-            static_assert(kVPW == 3, "three columns per record read");
-            stage_wait();
-            __syncthreads();
-            if (!busy) {
-                // the same staging loads and barriers as below, no adds
-                int bl = 2;
-                for (int j = 0; j < cnt; ++j) {
-                    const int nw = ld_win(j + 3);
-                    stage_frame(rsrc, voff, soff2, A.Wp, act, lds + bl * kLdsBuf, wave);
-                    soff2 = win(j + 3, nw);
-                    bl = bl == kNBuf - 1 ? 0 : bl + 1;
-                    stage_wait();
-                    barrier_keep_reads();
-                }
-                continue;
-            }
-            float v[kVPW][kRowsR];
-            read_rows_q(lds + min(r0c, r1c) + hoff + lane, colc[0], v[0]);
-            int bc = 0;  // buffer of frame j; frame j + 1 is in (bc + 1) % 3, frame j + 2 goes to (bc + 2) % 3
-            for (int j = 0; j < cnt; ++j) {
-                const int bn = bc == kNBuf - 1 ? 0 : bc + 1;
-                const int bl = bn == kNBuf - 1 ? 0 : bn + 1;
-                // geometry of frame j + 2 and the window of frame j + 3
-                // (issued before the staging loads, so that waiting for them
-                // leaves those in flight)
-                const auto nrw = ld_rows(j + 2);
-                const auto ncl = ld_cols(j + 2);
-                const int nw = ld_win(j + 3);
-                // load frame j + 2 into the buffer whose frame (j - 1) was
-                // consumed before the last barrier (past the chunk's end: a
-                // repeat of its last frame, never read)
-                stage_frame(rsrc, voff, soff2, A.Wp, act, lds + bl * kLdsBuf, wave);
-                // frame j: the second x velocity's rows, then the adds, one
-                // block per read pattern, each updating the sums in place (a
-                // chain of two-way branches keeps every sum in one register)
-                const float* pc = lds + bc * kLdsBuf + min(r0c, r1c) + hoff + lane;
-                read_rows_q(pc, colc[1], v[1]);
-                const int d = (r1c - r0c) / kLdsPitch;
-                if (d == 0) add_frame<0, 0>(v, acc, pc, colc[2]);
-                if (d == 1) add_frame<1, 0>(v, acc, pc, colc[2]);
-                if (d == 2) add_frame<2, 0>(v, acc, pc, colc[2]);
-                if (d == 3) add_frame<3, 0>(v, acc, pc, colc[2]);
-                if (d == 4) add_frame<4, 0>(v, acc, pc, colc[2]);
-                if (d == -1) add_frame<1, 1>(v, acc, pc, colc[2]);
-                if (d == -2) add_frame<2, 1>(v, acc, pc, colc[2]);
-                if (d == -3) add_frame<3, 1>(v, acc, pc, colc[2]);
-                if (d == -4) add_frame<4, 1>(v, acc, pc, colc[2]);
-                if (d < -kDMax || d > kDMax) {
-                    // rows too far apart to share: read both sets (frame j's
-                    // buffer stays intact until frame j + 3 loads into it)
-                    const float* buf = lds + bc * kLdsBuf + lane;
-                    accum_sep(buf + r0c + hoff, buf + r1c + hoff, colc, acc);
-                }
-                static_assert(kDMax == 4, "one case per shared-read distance");
-                // the first x velocity's rows of frame j + 1, in flight
-                // across the barrier, then the geometry moves on
-                read_rows_q(lds + bn * kLdsBuf + min(r0n, r1n) + hoff + lane, coln[0], v[0]);
-                r0c = r0n;
-                r1c = r1n;
+        // this wave's staging loads: instructions wave, wave + NW, ... of the
+        // NI per frame; lane l of instruction s copies chunk 64 s + l of the
+        // window (row group g = chunk / CW, column chunk % CW), lanes past the
+        // window copy its first chunk into the buffer's slack
+        const int nst = (NI - wave + NW - 1) / NW;
+        int voff[NSTX];
 #pragma unroll
-                for (int q = 0; q < kVPW; ++q) colc[q] = coln[q];
-                r0n = __builtin_amdgcn_readfirstlane((int)nrw[0]);
-                r1n = __builtin_amdgcn_readfirstlane((int)nrw[1]);
-                coln[0] = __builtin_amdgcn_readfirstlane((int)ncl[0]);
-                coln[1] = __builtin_amdgcn_readfirstlane((int)ncl[1]);
-                coln[2] = __builtin_amdgcn_readfirstlane((int)ncl[2]);
-                soff2 = win(j + 3, nw);
-                bc = bn;
-                stage_wait();
-                barrier_keep_reads();
-            }
+        for (int j = 0; j < NSTX; ++j) {
+            const int q = (wave + NW * j) * kWave + lane;
+            voff[j] = q < kRG * CW ? ((q / CW) * A.Wp + q % CW) * 16 : 0;
         }
+        const int toff = ((Y0 >> 2) * A.Wp + X0) * 16;  // bytes of the tile origin in a padded frame
+        const int fbytes = (int)(A.fstride * 4);        // < 2^31 on this path
+        const int nlast = A.n - 1;
+        // frame k of the block into its ring buffer (past the last frame: a
+        // repeat of it, never read); fi, woff from k's record
+        auto stage = [&](int k, int fi, int woff) __attribute__((always_inline)) {
+            stage_window<NW, NSTX>(A.pad + (long long)fi * A.fstride, fbytes, voff, nst, woff + toff,
+                                   lds + (k % NBUF) * BUFF, wave);
+        };
+        // the first NBUF - 1 frames
+#pragma unroll
+        for (int k = 0; k < NBUF - 1; ++k) {
+            const int kk = min(k, nlast);
+            const int fi = rec[kk * REC], woff = rec[kk * REC + 1];
+            stage(k, fi, woff);
+        }
+        // this wave's loads of frame 0 have landed
+        if (nst == NSTX)
+            wait_loads<NSTX * (NBUF - 2)>();
+        else
+            wait_loads<(NSTX - 1) * (NBUF - 2)>();
+        barrier_no_fence();
+        // records: the staging one for the next frame to load, and the
+        // columns and row-group offsets of the frame being added (loaded one
+        // frame ahead; scalar loads, first used after the frame's LDS reads)
+        int sk = min(NBUF - 1, nlast);
+        int sfi = rec[sk * REC], swoff = rec[sk * REC + 1];
+        int cg0 = rec[2], cg1 = rec[3];
+        int ccol[kVPW];
+#pragma unroll
+        for (int q = 0; q < kVPW; ++q) ccol[q] = rec[4 + kVPW * xg + q];
+        int k = 0;
+        auto frame = [&](auto cc) __attribute__((always_inline)) {
+            constexpr int C = decltype(cc)::value;
+            // frame k + NBUF - 1 into the buffer frame k - 1 used
+            stage(k + NBUF - 1, sfi, swoff);
+            // next records
+            const int nk = min(k + NBUF, nlast), ck = min(k + 1, nlast);
+            const int nfi = rec[nk * REC], nwoff = rec[nk * REC + 1];
+            const int ng0 = rec[ck * REC + 2], ng1 = rec[ck * REC + 3];
+            int ncol[kVPW];
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q) ncol[q] = rec[ck * REC + 4 + kVPW * xg + q];
+            if (busy) {
+                const f4* base = reinterpret_cast<const f4*>(lds + (k % NBUF) * BUFF) + 4 * h * CW + lane;
+                add_frame<C, CW>(base, ccol, cg0, cg1, acc);
+            }
+            // this wave's loads of frame k + 1 have landed; after the
+            // barrier, everyone's have
+            if (nst == NSTX)
+                wait_loads<NSTX * (NBUF - 2)>();
+            else
+                wait_loads<(NSTX - 1) * (NBUF - 2)>();
+            barrier_no_fence();
+            sfi = nfi;
+            swoff = nwoff;
+            cg0 = ng0;
+            cg1 = ng1;
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q) ccol[q] = ncol[q];
+            ++k;
+        };
+        // one loop per read pattern, in the order the host sorted the frames
+        auto loop = [&](auto cc) __attribute__((always_inline)) {
+            constexpr int C = decltype(cc)::value;
+            const int cnt = blk[C];
+#pragma unroll 1
+            for (int t = 0; t < cnt; ++t) frame(cc);
+        };
+        for_cases(loop, std::make_integer_sequence<int, kNCase>{});
+        // the repeats issued past the last frame land before LDS is reused
+        wait_loads<0>();
+        barrier_no_fence();
     } else {
         // Direct path for velocity blocks whose shift spread does not fit the
-        // LDS region: every sample is read from the padded copy through L2.
-        for (int i = 0; i < A.n; ++i) {
-            const int* rx = A.DX + (long long)i * A.ldx + aw;
-            const int* ry = A.DY + (long long)i * A.ldy + bw;
+        // staged window: every sample is read from the padded copy through L2,
+        // frames in the block's order.
+        typedef const __attribute__((address_space(1))) float GFloat;
+        GFloat* pad = (GFloat*)A.pad;
+        if (busy) {
+            for (int k = 0; k < A.n; ++k) {
+                const int i = rec[k * REC];
+                const int* rx = A.DX + (long long)i * A.ldx + aw;
+                const int* ry = A.DY + (long long)i * A.ldy + b0;
+                GFloat* fr = pad + (long long)i * A.fstride;
 #pragma unroll
-            for (int s = 0; s < kVYW; ++s) {
-                const float* base = A.pad + (long long)i * A.fstride +
-                                    (long long)(Y0 + h * kRowsW + ry[s] + A.padT) * A.Wp + (X0 + lane + A.padL);
+                for (int s = 0; s < kVYW; ++s) {
+                    const int yb = Y0 + h * kRowsW + ry[s] + A.padT;
 #pragma unroll
-                for (int q = 0; q < kVPW; ++q) {
-                    const float* p = base + rx[q];
+                    for (int q = 0; q < kVPW; ++q) {
+                        const int xc = X0 + lane + rx[q] + A.padL;
 #pragma unroll
-                    for (int r = 0; r < kRowsW; ++r) acc[q][s][r] += p[(long long)r * A.Wp];
-                    __builtin_amdgcn_sched_barrier(0);
+                        for (int r = 0; r < kRowsW; ++r) acc[q][s][r] += fr[pad_at(yb + r, xc, A.Wp)];
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                 }
             }
         }
@@ -878,17 +882,20 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     const int x = X0 + lane;
     const bool xin = x >= 0 && x < A.w;
 
-    // Coverage tables for the epilogue, staged once per workgroup: the y
-    // intervals of the block's velocity rows over the tile's rows, the
-    // variance prefix (when it fits) and each lane's x intervals.
-    // (sIY and sRS have one row before tile row 0 of the first velocity
-    // row, so that a column starting at tile row -1 has a valid base)
-    __shared__ int sIYa[(VBY * kRows + 1) * 2];
-    __shared__ float sRSa[DETECT ? VBY * kRows + 1 : 2];
+    // Coverage tables for the epilogue, once per workgroup: the y intervals of
+    // the pair's two velocity rows over the tile's rows, the variance prefix
+    // (when it fits) and each lane's x intervals.  (sIY and sRS have one row
+    // before tile row 0 of the first velocity row, so that a column starting
+    // at tile row -1 has a valid base.)
+    using L = Lds<SH>;
+    float* const colarea = lds;
+    float* const xch = lds + L::colf;
+    int* const sIYa = reinterpret_cast<int*>(xch + L::xch);
+    float* const sRSa = reinterpret_cast<float*>(sIYa + L::iy);
+    float* const sRM = sRSa + L::rs;
+    double* const sP = reinterpret_cast<double*>(sRM + L::rm);
     int* const sIY = sIYa + 2;
     float* const sRS = sRSa + 1;
-    __shared__ __attribute__((aligned(16))) float sRM[DETECT ? VBY * kRows : 4];
-    __shared__ double sP[DETECT ? kPLds : 1];
     const bool need_c = DETECT || A.mean || A.cov != nullptr;
     int xlo[kVPW], xhi[kVPW];
 #pragma unroll
@@ -898,7 +905,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         if (need_c && xin && aw + q < A.nvx) load_iv(A.IX, (long long)(aw + q) * A.w + x, xlo[q], xhi[q]);
     }
     if (need_c) {
-        for (int e = tid; e < VBY * kRows; e += kThreads) {
+        for (int e = tid; e < kVYW * kRows; e += NW * kWave) {
             const int bb = b0 + e / kRows, y = Y0 + e % kRows;
             int lo = A.n, hi = -1;
             if (bb < A.nvy && y >= 0 && y < A.h) load_iv(A.IY, (long long)bb * A.h + y, lo, hi);
@@ -909,9 +916,9 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     const bool p_lds = DETECT && A.n + 1 <= kPLds;
     if (DETECT) {
         if (p_lds)
-            for (int e = tid; e <= A.n; e += kThreads) sP[e] = A.P[e];
+            for (int e = tid; e <= A.n; e += NW * kWave) sP[e] = A.P[e];
         // per (velocity row, tile row): 1/sqrt(V) over the row's y interval
-        for (int e = tid; e < VBY * kRows; e += kThreads) {
+        for (int e = tid; e < kVYW * kRows; e += NW * kWave) {
             const int bb = b0 + e / kRows, y = Y0 + e % kRows;
             int lo = A.n, hi = -1;
             if (bb < A.nvy && y >= 0 && y < A.h) load_iv(A.IY, (long long)bb * A.h + y, lo, hi);
@@ -925,7 +932,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         }
         // publish the row next to the other half: row kRowsW - 1 of the upper
         // half, row 0 of the lower one
-        float* xo = lds + kColFloats + wave * (kVPW * kVYW * kWave);
+        float* xo = xch + wave * (kVPW * kVYW * kWave);
 #pragma unroll
         for (int q = 0; q < kVPW; ++q)
 #pragma unroll
@@ -940,10 +947,10 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         for (int q = 0; q < kVPW; ++q) {
 #pragma unroll
             for (int s = 0; s < kVYW; ++s) {
-                const int a = aw + q, bb = bw + s;
+                const int a = aw + q, bb = b0 + s;
                 if (a < A.nvx && bb < A.nvy) {
                     const long long kk = (long long)bb * A.nvx + a;
-                    const int* IYr = sIY + (bb - b0) * kRows * 2;
+                    const int* IYr = sIY + s * kRows * 2;
 #pragma unroll
                     for (int r = 0; r < kRowsW; ++r) {
                         const int tr = h * kRowsW + r;
@@ -971,16 +978,15 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     } else {
         // written out per velocity (not a loop) so that acc stays in
         // registers: the epilogue is too large for the unroller to replicate
-        float* col = lds + wave * (kColRows * kWave);
-        const float* xin_rows = lds + kColFloats + (wave ^ 1) * (kVPW * kVYW * kWave);
+        float* col = colarea + wave * (kColRows * kWave);
+        const float* xin_rows = xch + (wave ^ 1) * (kVPW * kVYW * kWave);
         const int R0 = kRowsW * h - 1;
         auto one = [&](auto qc, auto sc, const double* P) __attribute__((always_inline)) {
             constexpr int q = decltype(qc)::value, s = decltype(sc)::value;
-            const int bb = bw + s;
+            const int bb = b0 + s;
             if (aw + q < A.nvx && bb < A.nvy) {
-                const int vr = kVYW * yp + s;  // velocity row within the block
                 float rsm[kRowsW];  // this row half's multipliers (uniform)
-                const f4* src = reinterpret_cast<const f4*>(sRM + vr * kRows + h * kRowsW);
+                const f4* src = reinterpret_cast<const f4*>(sRM + s * kRows + h * kRowsW);
 #pragma unroll
                 for (int k = 0; k < kRowsW / 4; ++k) {
                     const f4 t = src[k];
@@ -989,9 +995,9 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
                     rsm[4 * k + 2] = t.z;
                     rsm[4 * k + 3] = t.w;
                 }
-                detect_epilogue(A, Ap, VBY, acc[q][s], rsm, aw + q, bb, x, xin, lane, h, Y0, tile, col,
-                                xin_rows + (q * kVYW + s) * kWave, sIY + (vr * kRows + R0) * 2, sRS + vr * kRows + R0,
-                                P, xlo[q], xhi[q]);
+                detect_epilogue(A, Ap, acc[q][s], rsm, aw + q, bb, x, xin, lane, h, Y0, tile, col,
+                                xin_rows + (q * kVYW + s) * kWave, sIY + (s * kRows + R0) * 2, sRS + s * kRows + R0,
+                                P, xlo[q], xhi[q], VBX, REC);
             }
             __builtin_amdgcn_sched_barrier(0);
         };
@@ -1013,8 +1019,10 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
 }
 
 template <bool DETECT, bool STAGED, int SH>
-__global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
-    stack_item<DETECT, STAGED, SH>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(), xcd_remap(blockIdx.x, gridDim.x));
+__global__ __launch_bounds__(shape_waves(SH) * kWave) void k_stack(const StackArgs A) {
+    __shared__ __attribute__((aligned(16))) float lds[Lds<SH>::total];
+    stack_item<DETECT, STAGED, SH>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(),
+                                   xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
 // Persistent form for a batch of detect problems (all staged): each
@@ -1022,11 +1030,12 @@ __global__ __launch_bounds__(kThreads) void k_stack(const StackArgs A) {
 // helps the other queues; an item is a (tile, velocity block) of one
 // problem, found by binary search of the problems' first items.
 template <int SH>
-__global__ __launch_bounds__(kThreads) void k_stack_batch(const BatchArgs B) {
+__global__ __launch_bounds__(shape_waves(SH) * kWave) void k_stack_batch(const BatchArgs B) {
     // the table is read-only during the launch: read it through the constant
     // address space, so that the (uniform) loads are scalar
     typedef const __attribute__((address_space(4))) StackArgs CArgs;
-    __shared__ int s_item;
+    __shared__ __attribute__((aligned(16))) float lds[Lds<SH>::total];
+    int* const s_item = reinterpret_cast<int*>(lds + Lds<SH>::total - 4);
     const int q0 = blockIdx.x % kBatchQueues;
     // the workgroup's own queue first, then (for the tail of the launch)
     // the other queues in turn; every queue ends, so every workgroup exits
@@ -1034,9 +1043,9 @@ __global__ __launch_bounds__(kThreads) void k_stack_batch(const BatchArgs B) {
         const int q = (q0 + k) % kBatchQueues;
         const int begin = B.qbegin[q], end = B.qbegin[q + 1];
         for (;;) {
-            if (threadIdx.x == 0) s_item = begin + atomicAdd(B.counter + q, 1);
+            if (threadIdx.x == 0) *s_item = begin + atomicAdd(B.counter + q, 1);
             __syncthreads();
-            const int g = __builtin_amdgcn_readfirstlane(s_item);
+            const int g = __builtin_amdgcn_readfirstlane(*s_item);
             __syncthreads();
             if (g >= end) break;
             int lo = 0, hi = B.nprob - 1;
@@ -1048,7 +1057,7 @@ __global__ __launch_bounds__(kThreads) void k_stack_batch(const BatchArgs B) {
                     hi = mid - 1;
             }
             const StackArgs* Ap = (const StackArgs*)((CArgs*)B.tab + lo);
-            stack_item<true, true, SH>(*Ap, Ap, g - B.start[lo]);
+            stack_item<true, true, SH>(*Ap, Ap, g - B.start[lo], lds);
             // every wave has finished the item before the next one reuses LDS
             __syncthreads();
         }
@@ -1209,7 +1218,7 @@ hipError_t launch_quantize(const float* frames, int n, int h, int w, int dtype, 
 }
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
-    const long long chunks = (long long)a.Hp * (a.Wp / 4);
+    const long long chunks = (long long)(a.Hp / 4) * a.Wp;
     const dim3 grid((unsigned)((chunks + kAux - 1) / kAux), a.n);
     if (a.dtype == SST_BF16)
         hipLaunchKernelGGL(k_prep<SST_BF16>, grid, dim3(kAux), 0, s, a);
@@ -1227,7 +1236,7 @@ hipError_t launch_cov(const int* D, int ld, int n, int nv, int size, int* I, hip
 
 template <int SH>
 void launch_stack_shape(const StackArgs& a, bool detect, bool staged, dim3 grid, hipStream_t s) {
-    const dim3 block(kThreads);
+    const dim3 block(shape_waves(SH) * kWave);
     if (detect) {
         if (staged)
             hipLaunchKernelGGL((k_stack<true, true, SH>), grid, block, 0, s, a);
@@ -1255,9 +1264,9 @@ hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, int shape,
 hipError_t launch_stack_batch(const BatchArgs& b, int groups, int shape, hipStream_t s) {
     if (groups <= 0) return hipSuccess;
     if (shape == 1)
-        hipLaunchKernelGGL(k_stack_batch<1>, dim3((unsigned)groups), dim3(kThreads), 0, s, b);
+        hipLaunchKernelGGL(k_stack_batch<1>, dim3((unsigned)groups), dim3(shape_waves(1) * kWave), 0, s, b);
     else
-        hipLaunchKernelGGL(k_stack_batch<0>, dim3((unsigned)groups), dim3(kThreads), 0, s, b);
+        hipLaunchKernelGGL(k_stack_batch<0>, dim3((unsigned)groups), dim3(shape_waves(0) * kWave), 0, s, b);
     return hipGetLastError();
 }
 

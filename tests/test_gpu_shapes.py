@@ -46,9 +46,10 @@ def _fields():
 
 def test_shapes_listed(sst):
     shapes = sst.sst_shapes()
-    assert shapes[0] == (9, 4) and len(shapes) >= 2
+    assert shapes[0] == (18, 2) and len(shapes) >= 2
     for vbx, vby in shapes:
-        assert vbx * vby == 36
+        # one pair of y velocities per block, three x velocities per wave
+        assert vby == 2 and vbx % 3 == 0
 
 
 def test_every_shape_matches_default(sst):
