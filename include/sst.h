@@ -176,6 +176,26 @@ int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, 
                sst_candidate* cand, int32_t* count, double* frame_stats,
                void* ws, size_t ws_bytes, void* stream);
 
+/* sst_detect for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same search and results, with the library's own static device scratch of
+ * sst_noalloc_scratch_bytes() bytes (256 MiB) as the workspace instead of
+ * a caller's.  Each GPU the library runs on holds one such array until the
+ * process ends; its address is looked up on the first call on a device.
+ * All calls on one GPU share that array, so calls on one GPU that overlap in
+ * time (other host threads, other streams) race; nothing needs clearing
+ * between calls (every region the search reads is written by the same call
+ * first).  Arguments as for sst_detect without ws/ws_bytes.  Errors: as
+ * sst_detect; SST_E_WORKSPACE when the problem needs more workspace than
+ * the scratch holds (sst_workspace_bytes(SST_OP_DETECT, ...) > the size),
+ * checked before any device work.  The call allocates nothing on the
+ * device (it waits for `stream` once, for the shift-table upload). */
+int sst_detect_noalloc(const void* frames, int dtype, const float* scale, int n, int h, int w,
+                       const double* t, double t_ref, const double* vx, int nvx, const double* vy, int nvy,
+                       float threshold, int min_coverage, int k_max,
+                       sst_candidate* cand, int32_t* count, double* frame_stats, void* stream);
+size_t sst_noalloc_scratch_bytes(void);
+
 /* ---- prepared searches: set-up once, enqueue-only runs ----
  * A run of a prepared plan enqueues kernels only: no host synchronisation,
  * no allocation and no memset, so it may be captured into a hipGraph (for

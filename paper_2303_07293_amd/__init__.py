@@ -26,9 +26,11 @@ from .binding import (  # noqa: F401
     sst_bin2x2,
     sst_coadd,
     sst_detect,
+    sst_detect_noalloc,
     sst_frame_stats,
     sst_last_error,
     sst_median_subtract,
+    sst_noalloc_scratch_bytes,
     sst_plan_detect,
     sst_profile_begin,
     sst_profile_end,

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsst.so")
 
-SOURCES = ["sst_api.cpp", "sst_kernels.hip", "sst_prep.hip", "sst_refine.hip"]
+SOURCES = ["sst_api.cpp", "sst_kernels.hip", "sst_prep.hip", "sst_refine.hip", "sst_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

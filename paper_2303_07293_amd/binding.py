@@ -39,7 +39,8 @@ EXPORTS = ("sst_shift_table", "sst_workspace_bytes", "sst_quantize", "sst_median
            "sst_frame_stats", "sst_stack", "sst_detect", "sst_refine", "sst_plan_detect", "sst_plan_run",
            "sst_plan_destroy", "sst_batch_workspace_bytes", "sst_batch_create", "sst_batch_run", "sst_batch_destroy",
            "sst_shape_info", "sst_workspace_bytes_shape", "sst_plan_detect_shape", "sst_plan_info",
-           "sst_profile_begin", "sst_profile_end", "sst_last_error", "sst_version")
+           "sst_profile_begin", "sst_profile_end", "sst_last_error", "sst_version", "sst_detect_noalloc",
+           "sst_noalloc_scratch_bytes")
 
 
 class SstError(RuntimeError):
@@ -93,6 +94,10 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.sst_detect.argtypes = [_p, _i, _p, _i, _i, _i, _p, _d, _p, _i, _p, _i, _f, _i, _i, _p, _p, _p, _p, _sz,
                                _p]
     lib.sst_detect.restype = _i
+    lib.sst_detect_noalloc.argtypes = [_p, _i, _p, _i, _i, _i, _p, _d, _p, _i, _p, _i, _f, _i, _i, _p, _p, _p, _p]
+    lib.sst_detect_noalloc.restype = _i
+    lib.sst_noalloc_scratch_bytes.argtypes = []
+    lib.sst_noalloc_scratch_bytes.restype = _sz
     lib.sst_refine.argtypes = [_p, _i, _p, _i, _i, _i, _p, _d, _i, _p, _i, _f, _i, _f, _p, _p, _p, _sz, _p]
     lib.sst_refine.restype = _i
     lib.sst_plan_detect.argtypes = [_i, _i, _i, _p, _d, _p, _i, _p, _i, _f, _i, _i, _p, _sz, _p,
@@ -351,6 +356,29 @@ def sst_detect(frames, t, t_ref: float, vx, vy, threshold: float, min_coverage: 
                              _ptr(vx), len(vx), _ptr(vy), len(vy), float(threshold), int(min_coverage), int(k_max),
                              _dev(cand), _dev(count), _ptr(stats), _dev(ws), ws.numel(), _stream(frames.device)))
     return (cand, count, stats) if want_stats else (cand, count)
+
+
+def sst_detect_noalloc(frames, t, t_ref: float, vx, vy, threshold: float, min_coverage: int, k_max: int, cand,
+                       count, scale=None):
+    """sst_detect on the library's static device scratch: allocates nothing.
+    cand (int32 [nvy*nvx][k_max][8]) and count (int32 [nvy*nvx]) are the
+    caller's device tensors.  Problems needing more workspace than
+    `sst_noalloc_scratch_bytes()` are rejected (SstError)."""
+    _check_frames(frames)
+    n, h, w = frames.shape
+    t, vx, vy = _f64(t), _f64(vx), _f64(vy)
+    nk = len(vx) * len(vy)
+    if tuple(cand.shape) != (nk, k_max, 8) or tuple(count.shape) != (nk,):
+        raise ValueError("cand must be [nvy*nvx][k_max][8] and count [nvy*nvx]")
+    _check(load().sst_detect_noalloc(_dev(frames), _frames_dtype(frames), _check_scale(frames, scale), n, h, w,
+                                     _ptr(t), float(t_ref), _ptr(vx), len(vx), _ptr(vy), len(vy), float(threshold),
+                                     int(min_coverage), int(k_max), _dev(cand), _dev(count), None,
+                                     _stream(frames.device)))
+    return cand, count
+
+
+def sst_noalloc_scratch_bytes() -> int:
+    return int(load().sst_noalloc_scratch_bytes())
 
 
 def sst_refine(frames, t, t_ref: float, params, cutout: int = 33, fwhm: float = 2.5, steps: int = 20,
