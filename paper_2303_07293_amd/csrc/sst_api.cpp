@@ -221,7 +221,7 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
     // offset in the frame (tile origin excluded), G0, G1, and the window
     // column of each x velocity of the block.
     const int rec_ints = shape_rec_ints(shape);
-    p.ord_stride = (size_t)kCountInts + (size_t)n * rec_ints;
+    p.ord_stride = (size_t)kCountInts + (size_t)(n + kRecPad) * rec_ints;
     p.G.assign((size_t)p.nvbx * p.nvby * p.ord_stride, 0);
     std::vector<int> cas(n);
     std::vector<int> order(n);
@@ -244,20 +244,23 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
             }
             for (int i = 0; i < n; ++i) order[i] = i;
             std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return cas[u] < cas[v]; });
-            for (int k = 0; k < n; ++k) {
-                const int i = order[k];
+            for (int k = 0; k < n + kRecPad; ++k) {
+                const int i = order[std::min(k, n - 1)];
                 const int32_t* rx = &p.DX[(size_t)i * p.ldx + (size_t)bx * p.vbx];
                 const int32_t* ry = &p.DY[(size_t)i * p.ldy + (size_t)by * kVYW];
                 const int mx = *std::min_element(rx, rx + p.vbx);
                 const int e0 = ry[0] + p.padT, e1 = ry[1] + p.padT;
                 const int gy = std::min(e0, e1) >> 2;
                 int32_t* r = &blk[kCountInts + (size_t)k * rec_ints];
-                r[0] = i;
+                // r[0], r[1]: the frame's address, written with the workspace
+                // address when the tables are uploaded
                 // (meaningful on the staged path only, where it is below 2^31)
-                r[1] = (int32_t)((((long long)gy * p.Wp + mx + p.padL) * 16) & 0x7FFFFFFF);
-                r[2] = cas[i] >= kNShared ? (e0 >> 2) - gy : 0;
-                r[3] = cas[i] >= kNShared ? (e1 >> 2) - gy : 0;
-                for (int j = 0; j < p.vbx; ++j) r[4 + j] = rx[j] - mx;
+                r[2] = (int32_t)((((long long)gy * p.Wp + mx + p.padL) * 16) & 0x7FFFFFFF);
+                const int g0 = cas[i] >= kNShared ? (e0 >> 2) - gy : 0;
+                const int g1 = cas[i] >= kNShared ? (e1 >> 2) - gy : 0;
+                r[3] = (int32_t)((unsigned)(g0 & 0xFFFF) | ((unsigned)(g1 & 0xFFFF) << 16));
+                r[4] = i;
+                for (int j = 0; j < p.vbx; ++j) r[kRecCol + j] = rx[j] - mx;
             }
         }
 
@@ -316,6 +319,20 @@ int upload_tables(const Plan& p, const double* bg, void* ws, hipStream_t s) {
     std::memcpy(host.data(), p.DX.data(), nx * sizeof(int32_t));
     std::memcpy(host.data() + nx * sizeof(int32_t), p.DY.data(), ny * sizeof(int32_t));
     std::memcpy(host.data() + (p.o_geom - p.o_tab), p.G.data(), p.G.size() * sizeof(int32_t));
+    {
+        // each frame record's padded-copy address in this workspace
+        int32_t* g = reinterpret_cast<int32_t*>(host.data() + (p.o_geom - p.o_tab));
+        const int rec_ints = shape_rec_ints(p.shape);
+        const uintptr_t pad = reinterpret_cast<uintptr_t>(ws) + p.o_pad;
+        const size_t fbytes = (size_t)p.Hp * p.Wp * sizeof(float);
+        for (size_t b = 0; b < (size_t)p.nvbx * p.nvby; ++b)
+            for (int k = 0; k < p.n + kRecPad; ++k) {
+                int32_t* r = g + b * p.ord_stride + kCountInts + (size_t)k * rec_ints;
+                const uint64_t a = (uint64_t)pad + (uint64_t)r[4] * fbytes;
+                r[0] = (int32_t)(uint32_t)(a & 0xFFFFFFFFu);
+                r[1] = (int32_t)(uint32_t)(a >> 32);
+            }
+    }
     size_t bytes = p.o_geom - p.o_tab + p.G.size() * sizeof(int32_t);
     if (bg) {
         float* f = reinterpret_cast<float*>(host.data() + (p.o_b32 - p.o_tab));

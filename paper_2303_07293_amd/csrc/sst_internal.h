@@ -60,7 +60,11 @@ __host__ __device__ constexpr int shape_ni_max(int sh) { return (kRG * shape_cw_
 constexpr int kNShared = 36;
 constexpr int kNCase = kNShared + 16;
 constexpr int kCountInts = 64;  // per-block header: frames of each case (kNCase used)
-__host__ __device__ constexpr int shape_rec_ints(int sh) { return (4 + shape_vbx(sh) + 3) / 4 * 4; }
+// per-frame record: frame address (2 ints), window byte offset, row-group
+// offsets (2 x 16 bits), frame index, window column of each x velocity
+constexpr int kRecCol = 5;
+__host__ __device__ constexpr int shape_rec_ints(int sh) { return (kRecCol + shape_vbx(sh) + 3) / 4 * 4; }
+constexpr int kRecPad = 4;  // copies of a block's last record after it (the staging ring reads ahead)
 
 constexpr int kStatThreads = 256;
 constexpr int kStatChunk = 8192;  // pixels per frame-statistics workgroup
@@ -98,10 +102,12 @@ struct StackArgs {
     int n, h, w;
     int Wp, padL, padT;
     // per velocity block [nvby][nvbx]: kCountInts ints (frames of each read
-    // case), then per frame in the block's order a record of rec ints:
-    // frame index, window byte offset in the frame (tile origin excluded),
-    // row-group offsets of the two y velocities (separate-read cases), and
-    // the window column of each x velocity of the block
+    // case), then per frame in the block's order (and kRecPad copies of the
+    // last) a record of rec ints: the frame's padded-copy address (low, high
+    // 32 bits), the window byte offset in the frame (tile origin excluded),
+    // the row-group offsets of the two y velocities (separate-read cases;
+    // 16 bits each), the frame index, and the window column of each x
+    // velocity of the block
     const int* ord;
     long long ord_stride;  // ints per block
     int cw;   // window columns

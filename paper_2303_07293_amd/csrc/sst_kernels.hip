@@ -351,23 +351,27 @@ struct Case {
 
 // G row groups of one column from p (group stride CW chunks) into v
 template <int G, int CW>
-__device__ __forceinline__ void read_groups(const f4* p, float (&v)[24]) {
+__device__ __forceinline__ void read_groups(const f4* p, f4 (&v)[6]) {
     static_assert(G <= 6, "at most 24 rows");
 #pragma unroll
-    for (int j = 0; j < G; ++j) {
-        const f4 t = p[j * CW];
-        v[4 * j] = t.x;
-        v[4 * j + 1] = t.y;
-        v[4 * j + 2] = t.z;
-        v[4 * j + 3] = t.w;
-    }
+    for (int j = 0; j < G; ++j) v[j] = p[j * CW];
 }
 
 template <int F>
-__device__ __forceinline__ void add_rows(const float (&v)[24], float (&a)[kRowsW]) {
+__device__ __forceinline__ void add_rows(const f4 (&v)[6], float (&a)[kRowsW]) {
     static_assert(F + kRowsW <= 24, "rows inside the read");
 #pragma unroll
-    for (int r = 0; r < kRowsW; ++r) a[r] += v[r + F];
+    for (int r = 0; r < kRowsW; ++r) a[r] += v[(r + F) / 4][(r + F) % 4];
+}
+
+// Keeps the G groups of v live up to this point: a group's components that
+// no add uses would otherwise count as dead at once, and their registers be
+// handed to the next read while the load into them is still in flight
+// (costing a wait for every LDS read outstanding).
+template <int G>
+__device__ __forceinline__ void hold(const f4 (&v)[6]) {
+#pragma unroll
+    for (int j = 0; j < G; ++j) asm volatile("" ::"v"(v[j]));
 }
 
 // Frame k's adds for the wave's kVPW x velocities (columns col[q]) in
@@ -380,17 +384,21 @@ __device__ __forceinline__ void add_frame(const f4* base, const int (&col)[kVPW]
                                           float (&acc)[kVPW][kVYW][kRowsW]) {
     using K = Case<C>;
     static_assert(kVPW == 3, "three x velocities per wave");
-    float va[24], vb[24];
+    f4 va[6], vb[6];
     if constexpr (K::shared) {
-        read_groups<K::gs, CW>(base + col[0], va);
-        read_groups<K::gs, CW>(base + col[1], vb);
+        constexpr int G = K::gs;
+        read_groups<G, CW>(base + col[0], va);
+        read_groups<G, CW>(base + col[1], vb);
         add_rows<K::f0>(va, acc[0][0]);
         add_rows<K::f1>(va, acc[0][1]);
-        read_groups<K::gs, CW>(base + col[2], va);
+        hold<G>(va);
+        read_groups<G, CW>(base + col[2], va);
         add_rows<K::f0>(vb, acc[1][0]);
         add_rows<K::f1>(vb, acc[1][1]);
+        hold<G>(vb);
         add_rows<K::f0>(va, acc[2][0]);
         add_rows<K::f1>(va, acc[2][1]);
+        hold<G>(va);
     } else {
         const f4* b0 = base + go0 * CW;
         const f4* b1 = base + go1 * CW;
@@ -399,7 +407,9 @@ __device__ __forceinline__ void add_frame(const f4* base, const int (&col)[kVPW]
             read_groups<K::g0, CW>(b0 + col[q], va);
             read_groups<K::g1, CW>(b1 + col[q], vb);
             add_rows<K::f0>(va, acc[q][0]);
+            hold<K::g0>(va);
             add_rows<K::f1>(vb, acc[q][1]);
+            hold<K::g1>(vb);
         }
     }
 }
@@ -510,7 +520,7 @@ __device__ __forceinline__ float sn_direct(KArgs A, const double* P, int a, int 
     float acc = 0.f;
 #pragma unroll 1
     for (int k = 0; k < n; ++k) {
-        const int i = ordr[(long long)k * rec];
+        const int i = ordr[(long long)k * rec + 4];
         const int dx = DX[(long long)i * ldx + a], dy = DY[(long long)i * ldy + b];
         acc += pad[(long long)i * fstride + pad_at(y0 + dy, x0 + dx, Wp)];
     }
@@ -781,19 +791,18 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         }
         const int toff = ((Y0 >> 2) * A.Wp + X0) * 16;  // bytes of the tile origin in a padded frame
         const int fbytes = (int)(A.fstride * 4);        // < 2^31 on this path
-        const int nlast = A.n - 1;
         // frame k of the block into its ring buffer (past the last frame: a
-        // repeat of it, never read); fi, woff from k's record
-        auto stage = [&](int k, int fi, int woff) __attribute__((always_inline)) {
-            stage_window<NW, NSTX>(A.pad + (long long)fi * A.fstride, fbytes, voff, nst, woff + toff,
-                                   lds + (k % NBUF) * BUFF, wave);
+        // repeat of it, never read); the frame's address and window offset
+        // from k's record
+        auto stage = [&](int k, int lo, int hi, int woff) __attribute__((always_inline)) {
+            const float* fr = reinterpret_cast<const float*>(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+            stage_window<NW, NSTX>(fr, fbytes, voff, nst, woff + toff, lds + (k % NBUF) * BUFF, wave);
         };
         // the first NBUF - 1 frames
 #pragma unroll
         for (int k = 0; k < NBUF - 1; ++k) {
-            const int kk = min(k, nlast);
-            const int fi = rec[kk * REC], woff = rec[kk * REC + 1];
-            stage(k, fi, woff);
+            const int lo = rec[k * REC], hi = rec[k * REC + 1], woff = rec[k * REC + 2];
+            stage(k, lo, hi, woff);
         }
         // this wave's loads of frame 0 have landed
         if (nst == NSTX)
@@ -801,31 +810,38 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         else
             wait_loads<(NSTX - 1) * (NBUF - 2)>();
         barrier_no_fence();
-        // records: the staging one for the next frame to load, and the
-        // columns and row-group offsets of the frame being added (loaded one
-        // frame ahead; scalar loads, first used after the frame's LDS reads)
-        int sk = min(NBUF - 1, nlast);
-        int sfi = rec[sk * REC], swoff = rec[sk * REC + 1];
-        int cg0 = rec[2], cg1 = rec[3];
+        // records of the next frame to load (rs) and of the frame being added
+        // (rc), read one frame ahead (scalar loads, first used after the
+        // frame's LDS reads); the block's list has copies of its last record
+        // past its end
+        CInt* rs = rec + (NBUF - 1) * REC;
+        CInt* rc = rec;
+        int slo = rs[0], shi = rs[1], swoff = rs[2];
+        int cgg = rc[3];
         int ccol[kVPW];
 #pragma unroll
-        for (int q = 0; q < kVPW; ++q) ccol[q] = rec[4 + kVPW * xg + q];
+        for (int q = 0; q < kVPW; ++q) ccol[q] = rc[kRecCol + kVPW * xg + q];
         int k = 0;
         auto frame = [&](auto cc) __attribute__((always_inline)) {
             constexpr int C = decltype(cc)::value;
             // frame k + NBUF - 1 into the buffer frame k - 1 used
-            stage(k + NBUF - 1, sfi, swoff);
-            // next records
-            const int nk = min(k + NBUF, nlast), ck = min(k + 1, nlast);
-            const int nfi = rec[nk * REC], nwoff = rec[nk * REC + 1];
-            const int ng0 = rec[ck * REC + 2], ng1 = rec[ck * REC + 3];
-            int ncol[kVPW];
-#pragma unroll
-            for (int q = 0; q < kVPW; ++q) ncol[q] = rec[ck * REC + 4 + kVPW * xg + q];
+            stage(k + NBUF - 1, slo, shi, swoff);
             if (busy) {
                 const f4* base = reinterpret_cast<const f4*>(lds + (k % NBUF) * BUFF) + 4 * h * CW + lane;
-                add_frame<C, CW>(base, ccol, cg0, cg1, acc);
+                add_frame<C, CW>(base, ccol, cgg & 0xFFFF, cgg >> 16, acc);
             }
+            // next records, loaded after the frame's LDS reads have been
+            // used (scalar loads share their wait counter with LDS reads and
+            // return out of order: issued earlier, they would turn the
+            // partial waits on LDS reads into full ones)
+            __builtin_amdgcn_sched_barrier(0);
+            rs += REC;
+            rc += REC;
+            const int nlo = rs[0], nhi = rs[1], nwoff = rs[2];
+            const int ngg = rc[3];
+            int ncol[kVPW];
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q) ncol[q] = rc[kRecCol + kVPW * xg + q];
             // this wave's loads of frame k + 1 have landed; after the
             // barrier, everyone's have
             if (nst == NSTX)
@@ -833,10 +849,10 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             else
                 wait_loads<(NSTX - 1) * (NBUF - 2)>();
             barrier_no_fence();
-            sfi = nfi;
+            slo = nlo;
+            shi = nhi;
             swoff = nwoff;
-            cg0 = ng0;
-            cg1 = ng1;
+            cgg = ngg;
 #pragma unroll
             for (int q = 0; q < kVPW; ++q) ccol[q] = ncol[q];
             ++k;
@@ -860,7 +876,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         GFloat* pad = (GFloat*)A.pad;
         if (busy) {
             for (int k = 0; k < A.n; ++k) {
-                const int i = rec[k * REC];
+                const int i = rec[k * REC + 4];
                 const int* rx = A.DX + (long long)i * A.ldx + aw;
                 const int* ry = A.DY + (long long)i * A.ldy + b0;
                 GFloat* fr = pad + (long long)i * A.fstride;
@@ -1019,7 +1035,8 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
 }
 
 template <bool DETECT, bool STAGED, int SH>
-__global__ __launch_bounds__(shape_waves(SH) * kWave) void k_stack(const StackArgs A) {
+__global__ __launch_bounds__(shape_waves(SH) * kWave) __attribute__((amdgpu_waves_per_eu(3)))
+void k_stack(const StackArgs A) {
     __shared__ __attribute__((aligned(16))) float lds[Lds<SH>::total];
     stack_item<DETECT, STAGED, SH>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(),
                                    xcd_remap(blockIdx.x, gridDim.x), lds);
@@ -1030,7 +1047,8 @@ __global__ __launch_bounds__(shape_waves(SH) * kWave) void k_stack(const StackAr
 // helps the other queues; an item is a (tile, velocity block) of one
 // problem, found by binary search of the problems' first items.
 template <int SH>
-__global__ __launch_bounds__(shape_waves(SH) * kWave) void k_stack_batch(const BatchArgs B) {
+__global__ __launch_bounds__(shape_waves(SH) * kWave) __attribute__((amdgpu_waves_per_eu(3)))
+void k_stack_batch(const BatchArgs B) {
     // the table is read-only during the launch: read it through the constant
     // address space, so that the (uniform) loads are scalar
     typedef const __attribute__((address_space(4))) StackArgs CArgs;
