@@ -103,17 +103,20 @@ size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double 
 /* Velocity-block shapes.  The stacking kernels are compiled for several
  * blocks of VBX x VBY trial velocities per workgroup (the velocity grid is
  * padded to whole blocks; a block's frame window is widened by the spread
- * of its shifts).  Shape 0 (9 x 4) is the default of every one-shot call;
- * shape 1 (3 x 12) wastes less on small grids whose y shifts spread little.
- * sst_shape_info writes the block size of `shape` (vbx/vby may be NULL) and
- * returns the number of shapes, or SST_E_ARG for an unknown shape.  Which
- * shape is faster for a problem is left to the caller (a tuner times
- * plans of each). */
+ * of its x shifts).  Shape 0 (6 x 2, three workgroups per compute unit)
+ * has the narrower window; shape 1 (18 x 2, one workgroup of 12 waves per
+ * compute unit) holds x shifts that spread about three times as far per
+ * velocity step.  The one-shot calls, sst_workspace_bytes and
+ * sst_plan_detect take the first shape whose window holds the grid's
+ * shifts (shape 0 if none does).  sst_shape_info writes the block size of
+ * `shape` (vbx/vby may be NULL) and returns the number of shapes, or
+ * SST_E_ARG for an unknown shape.  A tuner may time plans of each. */
 int sst_shape_info(int shape, int* vbx, int* vby);
 
-/* sst_workspace_bytes for velocity-block shape `shape` (sst_workspace_bytes
- * is shape 0): the shift tables are padded to whole blocks and the slots of
- * a detect launch hold whole block rows. */
+/* sst_workspace_bytes for velocity-block shape `shape` (0 .. number of
+ * shapes - 1, or -1 for the default choice of sst_workspace_bytes): the
+ * shift tables are padded to whole blocks and the slots of a detect launch
+ * hold whole block rows. */
 size_t sst_workspace_bytes_shape(int op, int shape, int n, int h, int w, const double* t, double t_ref,
                                  const double* vx, int nvx, const double* vy, int nvy, int k_max);
 
@@ -214,8 +217,9 @@ int sst_plan_detect(int n, int h, int w, const double* t, double t_ref, const do
                     const double* vy, int nvy, float threshold, int min_coverage, int k_max,
                     void* ws, size_t ws_bytes, void* stream, sst_plan** plan);
 
-/* sst_plan_detect with velocity-block shape `shape` (sst_plan_detect is
- * shape 0; ws >= sst_workspace_bytes_shape(SST_OP_DETECT, shape, ...)).
+/* sst_plan_detect with velocity-block shape `shape` (-1: the default choice
+ * of sst_plan_detect; ws >= sst_workspace_bytes_shape(SST_OP_DETECT, shape,
+ * ...)). 
  * Every shape gives the same candidate lists bit for bit; only the time
  * differs.  Errors: as sst_plan_detect, SST_E_ARG for an unknown shape. */
 int sst_plan_detect_shape(int shape, int n, int h, int w, const double* t, double t_ref, const double* vx,

@@ -180,7 +180,9 @@ def sst_shift_table(t, t_ref: float, v) -> np.ndarray:
 
 
 def sst_workspace_bytes(op: int, n: int, h: int, w: int, t=None, t_ref: float = 0.0, vx=None, vy=None,
-                        k_max: int = 0, shape: int = 0) -> int:
+                        k_max: int = 0, shape: int = -1) -> int:
+    """Workspace bytes of an operation (shape -1: the library's default
+    velocity-block shape choice)."""
     t = None if t is None else _f64(t)
     vx = None if vx is None else _f64(vx)
     vy = None if vy is None else _f64(vy)
@@ -448,9 +450,10 @@ class SstPlan:
 
 
 def sst_plan_detect(n: int, h: int, w: int, t, t_ref: float, vx, vy, threshold: float, min_coverage: int = 0,
-                    k_max: int = 64, device="cuda:0", shape: int = 0) -> SstPlan:
+                    k_max: int = 64, device="cuda:0", shape: int = -1) -> SstPlan:
     """Prepare sst_detect for one geometry (uploads the shift tables once),
-    with velocity-block shape `shape` (see sst_shapes)."""
+    with velocity-block shape `shape` (see sst_shapes; -1: the library's
+    default choice)."""
     import torch
     t, vx, vy = _f64(t), _f64(vx), _f64(vy)
     nb = sst_workspace_bytes(SST_OP_DETECT, n, h, w, t, t_ref, vx, vy, k_max, shape=shape)

@@ -125,8 +125,8 @@ size_t take(size_t& cur, size_t bytes) {
     return o;
 }
 
-int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
-              const double* vy, int nvy, int k_max, Plan& p, int shape = 0) {
+int make_plan_shape(int op, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
+                    const double* vy, int nvy, int k_max, Plan& p, int shape) {
     int rc = check_dims(n, h, w);
     if (rc) return rc;
     if (shape < 0 || shape >= kNShapes) return fail(SST_E_ARG, "velocity-block shape %d: need 0..%d", shape, kNShapes - 1);
@@ -287,6 +287,27 @@ int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const 
         p.o_ent = take(cur, nk * p.nslot * p.kt * sizeof(Entry));
     }
     p.total = cur;
+    return SST_OK;
+}
+
+constexpr int kShapeAuto = -1;
+
+// make_plan_shape with the velocity-block shape given, or (kShapeAuto) the
+// first shape whose window holds the grid's shift spread (the direct path
+// with the first shape if none does).
+int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
+              const double* vy, int nvy, int k_max, Plan& p, int shape = kShapeAuto) {
+    if (shape != kShapeAuto) return make_plan_shape(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p, shape);
+    int rc = make_plan_shape(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p, 0);
+    if (rc || p.staged || (op != SST_OP_STACK && op != SST_OP_DETECT)) return rc;
+    for (int sh = 1; sh < kNShapes; ++sh) {
+        Plan q;
+        if (make_plan_shape(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, q, sh) == SST_OK && q.staged) {
+            p = std::move(q);
+            break;
+        }
+    }
+    g_err.clear();
     return SST_OK;
 }
 
@@ -807,12 +828,19 @@ int sst_shift_table(const double* t, int n, double t_ref, const double* v, int n
 
 size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
                            const double* vy, int nvy, int k_max) {
-    return sst_workspace_bytes_shape(op, 0, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max);
+    g_err.clear();
+    Plan p;
+    if (make_plan(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p) != SST_OK) return 0;
+    return p.total;
 }
 
 size_t sst_workspace_bytes_shape(int op, int shape, int n, int h, int w, const double* t, double t_ref,
                                  const double* vx, int nvx, const double* vy, int nvy, int k_max) {
     g_err.clear();
+    if (shape != kShapeAuto && (shape < 0 || shape >= kNShapes)) {
+        fail(SST_E_ARG, "velocity-block shape %d: need 0..%d", shape, kNShapes - 1);
+        return 0;
+    }
     Plan p;
     if (make_plan(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p, shape) != SST_OK) return 0;
     return p.total;
@@ -1046,14 +1074,18 @@ extern "C" {
 int sst_plan_detect(int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx, const double* vy,
                     int nvy, float threshold, int min_coverage, int k_max, void* ws, size_t ws_bytes, void* stream,
                     sst_plan** plan) {
-    return sst_plan_detect_shape(0, n, h, w, t, t_ref, vx, nvx, vy, nvy, threshold, min_coverage, k_max, ws, ws_bytes,
-                                 stream, plan);
+    return sst_plan_detect_shape(kShapeAuto, n, h, w, t, t_ref, vx, nvx, vy, nvy, threshold, min_coverage, k_max, ws,
+                                 ws_bytes, stream, plan);
 }
 
 int sst_plan_detect_shape(int shape, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
                           const double* vy, int nvy, float threshold, int min_coverage, int k_max, void* ws,
                           size_t ws_bytes, void* stream, sst_plan** plan) {
     g_err.clear();
+    if (shape != kShapeAuto && (shape < 0 || shape >= kNShapes)) {
+        if (plan) *plan = nullptr;
+        return fail(SST_E_ARG, "velocity-block shape %d: need 0..%d", shape, kNShapes - 1);
+    }
     if (!plan) return fail(SST_E_ARG, "plan is NULL");
     *plan = nullptr;
     if (std::isnan(threshold)) return fail(SST_E_ARG, "threshold is NaN");

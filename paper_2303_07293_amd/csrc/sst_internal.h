@@ -30,12 +30,17 @@ constexpr int kRows = 32;
 constexpr int kRowsW = kRows / 2;  // rows per wave
 constexpr int kVPW = 3;  // x velocities per wave
 constexpr int kVYW = 2;  // y velocities per block (one pair)
-// Velocity-block shapes (chosen per plan): workgroups of 12 waves (one per
-// CU; 18 x velocities per block) or of 6 waves (two per CU; 9 x velocities,
-// for grids whose x shifts spread too far for 18, or fewer x velocities).
+// Velocity-block shapes (chosen per plan).  Workgroups of 4 waves, 6 x
+// velocities per block, three workgroups per CU (one waiting at its
+// per-frame barrier leaves the SIMDs to the other two; workgroups of 6 or
+// 12 waves with windows this size get a CU to themselves and lose that).
+// The shapes differ in the width of the staged window: shape 0 holds an x
+// shift spread of 25 px over a block's 6 velocities in three ring buffers,
+// shape 1 one of 80 px in two (for grids whose shifts grow faster per
+// velocity step), both within the LDS that three workgroups may share.
 constexpr int kNShapes = 2;
-constexpr int kMaxWaves = 12;
-__host__ __device__ constexpr int shape_waves(int sh) { return sh == 0 ? 12 : 6; }
+constexpr int kMaxWaves = 12;  // waves per CU at the kernels' register use
+__host__ __device__ constexpr int shape_waves(int) { return 4; }
 __host__ __device__ constexpr int shape_vbx(int sh) { return kVPW * shape_waves(sh) / 2; }
 __host__ __device__ constexpr int shape_vby(int) { return kVYW; }
 // LDS staging.  The padded copy of every frame is stored in groups of four
@@ -44,9 +49,9 @@ __host__ __device__ constexpr int shape_vby(int) { return kVYW; }
 // frame a window of kRG row groups by cw columns (the tile widened by the
 // block's x-shift spread) is staged into LDS with the same layout, and a
 // lane reads four rows of its column with one 16-byte LDS read.
-constexpr int kRG = 13;  // row groups (52 rows) of the staged window
-__host__ __device__ constexpr int shape_cw_max(int sh) { return sh == 0 ? 144 : 100; }
-__host__ __device__ constexpr int shape_nbuf(int sh) { return sh == 0 ? 4 : 3; }
+constexpr int kRG = 10;  // row groups (40 rows) of the staged window
+__host__ __device__ constexpr int shape_cw_max(int sh) { return sh == 0 ? 89 : 144; }
+__host__ __device__ constexpr int shape_nbuf(int sh) { return sh == 0 ? 3 : 2; }
 // staging instructions (64 chunks each) of the largest window
 __host__ __device__ constexpr int shape_ni_max(int sh) { return (kRG * shape_cw_max(sh) + kWave - 1) / kWave; }
 // Frame order.  Within the window the rows of the pair's two y velocities
@@ -64,13 +69,15 @@ constexpr int kCountInts = 64;  // per-block header: frames of each case (kNCase
 // offsets (2 x 16 bits), frame index, window column of each x velocity
 constexpr int kRecCol = 5;
 __host__ __device__ constexpr int shape_rec_ints(int sh) { return (kRecCol + shape_vbx(sh) + 3) / 4 * 4; }
-constexpr int kRecPad = 4;  // copies of a block's last record after it (the staging ring reads ahead)
+// copies of a block's last record after it: the staging ring stages up to
+// NBUF - 2 frames past the last and reads the record after those
+constexpr int kRecPad = 6;
 
 constexpr int kStatThreads = 256;
 constexpr int kStatChunk = 8192;  // pixels per frame-statistics workgroup
 constexpr int kMaxK = 1024;       // largest k_max accepted
 constexpr int kMergeLds = 2048;   // entries ranked in LDS by the merge kernel
-constexpr int kPLds = 1024;       // variance-prefix entries the stack kernel keeps in LDS
+constexpr int kPLds = 256;        // variance-prefix entries the stack kernel keeps in LDS
 
 // One candidate kept by a (tile, velocity) before the per-velocity merge.
 struct Entry {

@@ -347,6 +347,10 @@ struct Case {
     static constexpr int g0 = (f0 + kRowsW - 1) / 4 + 1;
     static constexpr int g1 = (f1 + kRowsW - 1) / 4 + 1;
     static constexpr int gs = (cmax(f0, f1) + kRowsW - 1) / 4 + 1;
+    // the lower row half reads from row group 4 of the window on; a separate
+    // read may start up to kRG - 9 groups further (the host checks that)
+    static_assert(!shared || 4 + gs <= kRG, "a shared read stays inside the window");
+    static_assert(shared || 4 + cmax(g0, g1) <= 9, "separate reads span at most 5 row groups");
 };
 
 // G row groups of one column from p (group stride CW chunks) into v
@@ -748,6 +752,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     constexpr int BUFF = Lds<SH>::buf;
     constexpr int NSTX = (NI + NW - 1) / NW;  // most staging loads per wave and frame
     static_assert(NI >= NW && NSTX * (NBUF - 2 > 0 ? NBUF - 2 : 1) < 16, "every wave stages; vmcnt field");
+    static_assert(NBUF <= kRecPad, "records read ahead stay inside the block's list");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);

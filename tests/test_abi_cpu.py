@@ -297,13 +297,17 @@ def test_batch_argument_errors(lib):
 def test_shape_argument_errors(lib):
     vbx, vby = ctypes.c_int(0), ctypes.c_int(0)
     nsh = lib.sst_shape_info(0, ctypes.byref(vbx), ctypes.byref(vby))
-    assert nsh >= 2 and (vbx.value, vby.value) == (18, 2)
+    assert nsh >= 2 and (vbx.value, vby.value) == (6, 2)
     assert lib.sst_shape_info(nsh, None, None) == B.SST_E_ARG
     assert lib.sst_shape_info(-1, None, None) == B.SST_E_ARG
     t = np.arange(4, dtype=np.float64)
     v = np.array([0.0, 1.0])
     assert lib.sst_workspace_bytes_shape(B.SST_OP_DETECT, nsh, 4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 4) == 0
+    assert lib.sst_workspace_bytes_shape(B.SST_OP_DETECT, -2, 4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 4) == 0
     assert lib.sst_workspace_bytes_shape(B.SST_OP_DETECT, 1, 4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 4) > 0
+    # -1: the default choice, the same size as sst_workspace_bytes
+    assert (lib.sst_workspace_bytes_shape(B.SST_OP_DETECT, -1, 4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 4)
+            == lib.sst_workspace_bytes(B.SST_OP_DETECT, 4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 4))
     h = ctypes.c_void_p()
     assert lib.sst_plan_detect_shape(nsh, 4, 8, 8, _p(t), 0.0, _p(v), 2, _p(v), 2, 5.0, 0, 4, FAKE, 1 << 40, None,
                                      ctypes.byref(h)) == B.SST_E_ARG
