@@ -500,10 +500,17 @@ def main():
         torch.cuda.empty_cache()
         fr32 = torch.from_numpy(f.frames).to(dev)
         ratio = {"f32_ms_per_step": round(dt * 1e3, 4)}
-        for name, tdt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        # bf16 and f16 searched on a float32 copy (the default), and f16
+        # searched on its 16-bit samples (mixed-precision FMA, opt-in)
+        for name, tdt, direct in (("bf16", torch.bfloat16, False), ("f16", torch.float16, False),
+                                  ("f16_direct", torch.float16, True)):
             q, sc, _ = sst.sst_quantize(fr32, tdt, center=True)
             torch.cuda.synchronize()
-            d16, k16, _, c16 = time_detect(torch, sst, f, q, sc, max(3, args.steps // 2), 2)
+            prev = sst.sst_set_half_search(direct)
+            try:
+                d16, k16, _, c16 = time_detect(torch, sst, f, q, sc, max(3, args.steps // 2), 2)
+            finally:
+                sst.sst_set_half_search(prev)
             ratio[f"{name}_ms_per_step"] = round(d16 * 1e3, 4)
             ratio[f"speedup_{name}_vs_f32"] = round(dt / d16, 4)
             ratio[f"{name}_candidates"] = c16

@@ -343,6 +343,20 @@ int sst_coadd(const float* frames, int n, int h, int w, int group, float* out, c
  * [n][h/2][w/2].  Errors: SST_E_ARG, SST_E_DEVICE.  Asynchronous. */
 int sst_bin2x2(const float* frames, int n, int h, int w, float* out, void* stream);
 
+/* Search of IEEE-half frames on their 16-bit samples (process-wide, off by
+ * default; returns the previous setting).  Off, sst_detect and plan runs
+ * widen 16-bit frames (with their scales) into the float32 padded copy and
+ * search that, as for float32 frames.  On, a staged plan given SST_F16
+ * frames stages the 16-bit samples themselves (half the bytes into LDS and
+ * out of it) and adds each as one mixed-precision FMA, fma(q, scale_i, S),
+ * subtracting the covering frames' means after the sum (a prefix sum of the
+ * means, as for the variances); the candidate lists follow the same parity
+ * rules against the oracle on the dequantised frames.  It is off by default
+ * because on gfx950 the mixed-precision FMA issues at under half the rate of
+ * a float32 add, which costs more than the halved LDS traffic saves on the
+ * full-field search (about 21 ms against 18 ms).  Not used by batches. */
+int sst_set_half_search(int on);
+
 /* Kernel timing for measurements.  Between sst_profile_begin() and
  * sst_profile_end(), every launch of the stacking kernel (the dominant cost
  * of sst_stack and sst_detect) is bracketed by HIP events recorded on the

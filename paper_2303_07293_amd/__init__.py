@@ -36,6 +36,7 @@ from .binding import (  # noqa: F401
     sst_profile_end,
     sst_quantize,
     sst_refine,
+    sst_set_half_search,
     sst_shapes,
     sst_shift_table,
     sst_stack,

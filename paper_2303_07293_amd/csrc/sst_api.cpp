@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <new>
 #include <cmath>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -115,7 +116,7 @@ struct Plan {
     std::vector<int32_t> G;  // per velocity block: frame order and staging geometry (ord_stride ints)
     size_t ord_stride = 0;
     // workspace offsets (bytes)
-    size_t o_geom = 0, o_tab = 0, o_part = 0, o_b = 0, o_s2 = 0, o_P = 0, o_b32 = 0, o_sdev = 0;
+    size_t o_geom = 0, o_tab = 0, o_part = 0, o_b = 0, o_s2 = 0, o_P = 0, o_Pb = 0, o_b32 = 0, o_sdev = 0;
     size_t o_ix = 0, o_iy = 0, o_pad = 0, o_tcount = 0, o_ent = 0, o_qpart = 0, o_dt = 0, total = 0;
 };
 
@@ -275,6 +276,7 @@ int make_plan_shape(int op, int n, int h, int w, const double* t, double t_ref, 
         p.o_b = take(cur, (size_t)n * sizeof(double));
         p.o_s2 = take(cur, (size_t)n * sizeof(double));
         p.o_P = take(cur, (size_t)(n + 1) * sizeof(double));
+        p.o_Pb = take(cur, (size_t)(n + 1) * sizeof(double));
         p.o_sdev = take(cur, (size_t)n * 2 * sizeof(double));
         p.kt = k_max;
         const size_t per_row = (size_t)p.vby * nvx * p.nslot * ((size_t)p.kt * sizeof(Entry) + sizeof(int32_t));
@@ -392,6 +394,9 @@ StackArgs stack_args(const Plan& p, void* ws) {
     a.IX = at<int>(ws, p.o_ix);
     a.IY = at<int>(ws, p.o_iy);
     a.P = p.o_P ? at<double>(ws, p.o_P) : nullptr;
+    a.Pb = p.o_Pb ? at<double>(ws, p.o_Pb) : nullptr;
+    a.half = 0;
+    a.scale = nullptr;
     a.tiles_x = p.tiles_x;
     a.tiles_y = p.tiles_y;
     a.nvbx = p.nvbx;
@@ -402,8 +407,9 @@ StackArgs stack_args(const Plan& p, void* ws) {
 }
 
 int prep_and_cov(const Plan& p, const void* frames, int dtype, const float* scale, const float* b32, void* ws,
-                 hipStream_t s) {
+                 hipStream_t s, bool half = false) {
     PrepArgs pa{};
+    pa.half = half ? 1 : 0;
     pa.frames = frames;
     pa.dtype = dtype;
     pa.scale = scale;
@@ -485,14 +491,27 @@ StackArgs detect_args(const Plan& p, void* ws, float threshold, int min_coverage
     return a;
 }
 
-// Frame statistics, padded copy and coverage intervals of a detect call.
+// Whether a detect run of plan p on frames of dtype searches the 16-bit
+// samples themselves (IEEE half frames on a staged plan) rather than a
+// float32 copy.
+std::atomic<int> g_half_search{0};
+bool half_search(const Plan& p, int dtype) { return g_half_search.load() != 0 && dtype == SST_F16 && p.staged; }
+
+// Frame statistics, padded copy and coverage intervals of a detect call (and
+// for a search on 16-bit samples the frame scales in the records).
 int detect_prepare(const Plan& p, void* ws, const void* frames, int dtype, const float* scale, bool stats_out,
-                   hipStream_t s) {
+                   bool half, hipStream_t s) {
     hipError_t e = launch_stats(frames, dtype, scale, p.n, p.h, p.w, at<double>(ws, p.o_part), p.nchunk,
                                 at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
-                                at<double>(ws, p.o_P), stats_out ? at<double>(ws, p.o_sdev) : nullptr, s);
+                                at<double>(ws, p.o_P), at<double>(ws, p.o_Pb),
+                                stats_out ? at<double>(ws, p.o_sdev) : nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
-    return prep_and_cov(p, frames, dtype, scale, at<float>(ws, p.o_b32), ws, s);
+    if (half) {
+        e = launch_rec_scale(at<int>(ws, p.o_geom), p.nvbx * p.nvby, (long long)p.ord_stride, p.n + kRecPad,
+                             shape_rec_ints(p.shape), scale, s);
+        if (e != hipSuccess) return hip_fail(e, "record scale kernel");
+    }
+    return prep_and_cov(p, frames, dtype, scale, at<float>(ws, p.o_b32), ws, s, half);
 }
 
 // Merge of the slots of velocity-block rows [r0, r0 + rows) into the lists.
@@ -512,10 +531,15 @@ int detect_merge(const Plan& p, void* ws, int k_max, int r0, int rows, sst_candi
 int detect_enqueue(const Plan& p, void* ws, const void* frames, int dtype, const float* scale, float threshold,
                    int min_coverage, int k_max, sst_candidate* cand, int32_t* count, bool stats_out, hipStream_t s) {
     int rc;
-    if ((rc = detect_prepare(p, ws, frames, dtype, scale, stats_out, s))) return rc;
+    const bool half = half_search(p, dtype);
+    if ((rc = detect_prepare(p, ws, frames, dtype, scale, stats_out, half, s))) return rc;
     for (int r0 = 0; r0 < p.nvby; r0 += p.rows_per_chunk) {
         const int rows = std::min(p.rows_per_chunk, p.nvby - r0);
-        const StackArgs a = detect_args(p, ws, threshold, min_coverage, r0, rows);
+        StackArgs a = detect_args(p, ws, threshold, min_coverage, r0, rows);
+        if (half) {
+            a.half = 1;
+            a.scale = scale;
+        }
         const hipError_t e = launch_stack_profiled(a, true, p.staged, p.shape, s);
         if (e != hipSuccess) return hip_fail(e, "detect kernel");
         if ((rc = detect_merge(p, ws, k_max, r0, rows, cand, count, s))) return rc;
@@ -746,7 +770,7 @@ int sst_batch_run(const sst_batch* batch, const void* const* frames, const int* 
             rc = detect_enqueue(pl->p, pl->ws, frames[j], dtypes[j], sc, pl->threshold, pl->min_coverage, pl->k_max,
                                 cand[j], count[j], false, on(j));
         else
-            rc = detect_prepare(pl->p, pl->ws, frames[j], dtypes[j], sc, false, on(j));
+            rc = detect_prepare(pl->p, pl->ws, frames[j], dtypes[j], sc, false, false, on(j));
         if (rc) return rc;
     }
     if ((e = join()) != hipSuccess) return hip_fail(e, "batch join");
@@ -769,6 +793,8 @@ int sst_batch_run(const sst_batch* batch, const void* const* frames, const int* 
 }
 
 void sst_batch_destroy(sst_batch* batch) { delete batch; }
+
+int sst_set_half_search(int on) { return g_half_search.exchange(on ? 1 : 0); }
 
 int sst_profile_begin(void) {
     g_err.clear();
@@ -869,7 +895,7 @@ int sst_quantize(const float* frames, int n, int h, int w, int dtype, int center
     if (center) {
         // offset = float32 of each frame's float64 mean (the statistics kernels)
         e = launch_stats(frames, SST_F32, nullptr, n, h, w, at<double>(ws, p.o_part), p.nchunk, at<double>(ws, p.o_b),
-                         at<double>(ws, p.o_s2), offset, at<double>(ws, p.o_P), nullptr, s);
+                         at<double>(ws, p.o_s2), offset, at<double>(ws, p.o_P), nullptr, nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
     }
     e = launch_quantize(frames, n, h, w, dtype, center ? offset : nullptr, at<float>(ws, p.o_qpart), p.nchunk, scale,
@@ -899,7 +925,7 @@ int sst_refine(const void* frames, int dtype, const float* scale, int n, int h, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = launch_stats(frames, dtype, scale, n, h, w, at<double>(ws, p.o_part), p.nchunk,
                                 at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
-                                at<double>(ws, p.o_P), nullptr, s);
+                                at<double>(ws, p.o_P), nullptr, nullptr, s);
     if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
     std::vector<float> dt(n);
     for (int i = 0; i < n; ++i) dt[i] = (float)(t[i] - t_ref);
@@ -997,7 +1023,7 @@ int sst_frame_stats(const void* frames, int dtype, const float* scale, int n, in
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = launch_stats(frames, dtype, scale, n, h, w, at<double>(ws, p.o_part), p.nchunk,
                                 at<double>(ws, p.o_b), at<double>(ws, p.o_s2), at<float>(ws, p.o_b32),
-                                at<double>(ws, p.o_P), stats, s);
+                                at<double>(ws, p.o_P), nullptr, stats, s);
     if (e != hipSuccess) return hip_fail(e, "frame statistics kernels");
     return SST_OK;
 }

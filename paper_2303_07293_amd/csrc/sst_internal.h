@@ -54,6 +54,10 @@ __host__ __device__ constexpr int shape_cw_max(int sh) { return sh == 0 ? 89 : 1
 __host__ __device__ constexpr int shape_nbuf(int sh) { return sh == 0 ? 3 : 2; }
 // staging instructions (64 chunks each) of the largest window
 __host__ __device__ constexpr int shape_ni_max(int sh) { return (kRG * shape_cw_max(sh) + kWave - 1) / kWave; }
+// The same window of 16-bit samples: four rows of a column in 8 bytes, so a
+// 16-byte staging chunk holds two columns and the window width is even.
+__host__ __device__ constexpr int shape_cw_half(int sh) { return (shape_cw_max(sh) + 1) / 2 * 2; }
+__host__ __device__ constexpr int shape_ni_half(int sh) { return (kRG * shape_cw_half(sh) / 2 + kWave - 1) / kWave; }
 // Frame order.  Within the window the rows of the pair's two y velocities
 // start at row offsets f0, f1 of the window's first row group; the pattern
 // (f0, f1) of a frame is one of kNCase read cases: 36 where the two start
@@ -66,8 +70,11 @@ constexpr int kNShared = 36;
 constexpr int kNCase = kNShared + 16;
 constexpr int kCountInts = 64;  // per-block header: frames of each case (kNCase used)
 // per-frame record: frame address (2 ints), window byte offset, row-group
-// offsets (2 x 16 bits), frame index, window column of each x velocity
-constexpr int kRecCol = 5;
+// offsets (2 x 16 bits), frame index, the frame's scale (float bits; written
+// by each run of a search on 16-bit samples), window column of each x
+// velocity
+constexpr int kRecScale = 5;
+constexpr int kRecCol = 6;
 __host__ __device__ constexpr int shape_rec_ints(int sh) { return (kRecCol + shape_vbx(sh) + 3) / 4 * 4; }
 // copies of a block's last record after it: the staging ring stages up to
 // NBUF - 2 frames past the last and reads the record after those
@@ -104,8 +111,16 @@ __device__ __forceinline__ float frame_value(const void* f, long long e, float s
 }
 
 struct StackArgs {
-    const float* pad;   // zero-padded, background-subtracted frames [n][Hp/4][Wp][4] (row groups)
+    // zero-padded frames in row groups, [n][Hp/4][Wp][4]: float32 samples
+    // minus the frame's background, or (half != 0) the 16-bit samples as
+    // stored (IEEE half, frame i at half index 2 i fstride), each multiplied
+    // by its frame's scale as it is added, the backgrounds subtracted after
+    // the sum through the prefix Pb
+    const float* pad;
     long long fstride;  // Hp * Wp floats per frame
+    int half;
+    const float* scale;  // [n] per-frame scales (half only)
+    const double* Pb;    // [n+1] prefix sums of the frame means (half only)
     int n, h, w;
     int Wp, padL, padT;
     // per velocity block [nvby][nvbx]: kCountInts ints (frames of each read
@@ -163,17 +178,22 @@ struct PrepArgs {
     const float* b32;    // [n] subtracted per frame, or nullptr
     float* pad;
     int n, h, w, Hp, Wp, padL, padT;
+    int half;  // SST_F16 frames: copy the 16-bit samples as they are (no scale, no background)
 };
 
 // launch wrappers (sst_kernels.hip); each returns a hipError_t
 hipError_t launch_stats(const void* frames, int dtype, const float* scale, int n, int h, int w,
                         double* part, int nchunk, double* b, double* s2, float* b32, double* P,
-                        double* stats_dev, hipStream_t s);
+                        double* Pb, double* stats_dev, hipStream_t s);
 hipError_t launch_quantize(const float* frames, int n, int h, int w, int dtype, const float* offset,
                            float* part, int nchunk, float* scale, void* q, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_cov(const int* D, int ld, int n, int nv, int size, int* I, hipStream_t s);
 hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, int shape, hipStream_t s);
+// the frame scales into the records of every velocity block (ord: nblk
+// blocks of ord_stride ints, n + kRecPad records of rec ints each)
+hipError_t launch_rec_scale(int* ord, int nblk, long long ord_stride, int nrec, int rec, const float* scale,
+                            hipStream_t s);
 hipError_t launch_stack_batch(const BatchArgs& b, int groups, int shape, hipStream_t s);
 hipError_t launch_zero_i32(int* p, int count, hipStream_t s);
 hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int nslot, int kt, int k_max,

@@ -150,7 +150,8 @@ __global__ __launch_bounds__(kAux) void k_stats_partial(const void* __restrict__
 __global__ __launch_bounds__(kAux) void k_stats_final(const double* __restrict__ part, int nchunk, int n,
                                                          long long npx, double* __restrict__ b,
                                                          double* __restrict__ s2, float* __restrict__ b32,
-                                                         double* __restrict__ P, double* __restrict__ stats_dev) {
+                                                         double* __restrict__ P, double* __restrict__ Pb,
+                                                         double* __restrict__ stats_dev) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const double* p = part + (long long)i * nchunk * 3;
         double sum = 0.0;
@@ -179,6 +180,15 @@ __global__ __launch_bounds__(kAux) void k_stats_final(const double* __restrict__
             acc += s2[i];
             P[i + 1] = acc;
         }
+    } else if (threadIdx.x == kWave && Pb) {
+        // (another wave) the prefix of the means, for searches that subtract
+        // the backgrounds after the sum
+        double acc = 0.0;
+        Pb[0] = 0.0;
+        for (int i = 0; i < n; ++i) {
+            acc += b[i];
+            Pb[i + 1] = acc;
+        }
     }
 }
 
@@ -190,6 +200,31 @@ __global__ __launch_bounds__(kAux) void k_stats_final(const double* __restrict__
 // One thread per 16-byte chunk (row group, column) of a frame; consecutive
 // threads take consecutive columns, so the four row reads and the chunk
 // write are coalesced.
+// The 16-bit copy (IEEE half samples as stored, zero outside): the same
+// layout with 8-byte chunks, frame i at half index 2 i Hp Wp.
+__global__ __launch_bounds__(kAux) void k_prep_half(const PrepArgs a) {
+    const int i = blockIdx.y;
+    const unsigned q = blockIdx.x * kAux + threadIdx.x;
+    const unsigned ng = (unsigned)a.Hp / 4;
+    if (q >= ng * (unsigned)a.Wp) return;
+    const int g = (int)(q / (unsigned)a.Wp);
+    const int xp = (int)(q - (unsigned)g * (unsigned)a.Wp);
+    const int x = xp - a.padL;
+    unsigned o[4] = {0u, 0u, 0u, 0u};
+    if (x >= 0 && x < a.w) {
+        const uint16_t* f = static_cast<const uint16_t*>(a.frames);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int y = 4 * g + k - a.padT;
+            if (y >= 0 && y < a.h) o[k] = f[((long long)i * a.h + y) * a.w + x];
+        }
+    }
+    typedef unsigned u2v __attribute__((ext_vector_type(2)));
+    u2v* dst = reinterpret_cast<u2v*>(reinterpret_cast<uint16_t*>(a.pad) + 2 * (long long)i * a.Hp * a.Wp +
+                                      (long long)q * 4);
+    *dst = u2v{o[0] | (o[1] << 16), o[2] | (o[3] << 16)};
+}
+
 template <int DT>
 __global__ __launch_bounds__(kAux) void k_prep(const PrepArgs a) {
     const int i = blockIdx.y;
@@ -353,27 +388,50 @@ struct Case {
     static_assert(shared || 4 + cmax(g0, g1) <= 9, "separate reads span at most 5 row groups");
 };
 
+// four rows of one column: float32 samples, or 16-bit samples (row k of the
+// group in half k % 2 of dword k / 2)
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
 // G row groups of one column from p (group stride CW chunks) into v
-template <int G, int CW>
-__device__ __forceinline__ void read_groups(const f4* p, f4 (&v)[6]) {
+template <int G, int CW, typename T>
+__device__ __forceinline__ void read_groups(const T* p, T (&v)[6]) {
     static_assert(G <= 6, "at most 24 rows");
 #pragma unroll
     for (int j = 0; j < G; ++j) v[j] = p[j * CW];
 }
 
+// a[r] += sample r + F of the read (float32), or a[r] = fma(sample, sc,
+// a[r]) (16-bit: the sample widened exactly, times the frame's scale, added
+// with one rounding)
 template <int F>
-__device__ __forceinline__ void add_rows(const f4 (&v)[6], float (&a)[kRowsW]) {
+__device__ __forceinline__ void add_rows(const f4 (&v)[6], float, float (&a)[kRowsW]) {
     static_assert(F + kRowsW <= 24, "rows inside the read");
 #pragma unroll
     for (int r = 0; r < kRowsW; ++r) a[r] += v[(r + F) / 4][(r + F) % 4];
+}
+
+template <int F>
+__device__ __forceinline__ void add_rows(const u2 (&v)[6], float sc, float (&a)[kRowsW]) {
+    static_assert(F + kRowsW <= 24, "rows inside the read");
+#pragma unroll
+    for (int r = 0; r < kRowsW; ++r) {
+        const int k = r + F;
+        // (the dword selected into a scalar first: a bit_cast of a vector
+        // element expression reads element 0)
+        const unsigned d = ((k % 4) / 2) ? v[k / 4].y : v[k / 4].x;
+        const h2 pr = __builtin_bit_cast(h2, d);
+        const float x = (k % 2) ? (float)pr.y : (float)pr.x;
+        a[r] = __builtin_fmaf(x, sc, a[r]);
+    }
 }
 
 // Keeps the G groups of v live up to this point: a group's components that
 // no add uses would otherwise count as dead at once, and their registers be
 // handed to the next read while the load into them is still in flight
 // (costing a wait for every LDS read outstanding).
-template <int G>
-__device__ __forceinline__ void hold(const f4 (&v)[6]) {
+template <int G, typename T>
+__device__ __forceinline__ void hold(const T (&v)[6]) {
 #pragma unroll
     for (int j = 0; j < G; ++j) asm volatile("" ::"v"(v[j]));
 }
@@ -383,36 +441,36 @@ __device__ __forceinline__ void hold(const f4 (&v)[6]) {
 // column 0; go0, go1 = row-group offsets of the two y velocities (separate
 // patterns only).  The reads of the next x velocity are issued before the
 // adds of the current one.
-template <int C, int CW>
-__device__ __forceinline__ void add_frame(const f4* base, const int (&col)[kVPW], int go0, int go1,
+template <int C, int CW, typename T>
+__device__ __forceinline__ void add_frame(const T* base, const int (&col)[kVPW], int go0, int go1, float sc,
                                           float (&acc)[kVPW][kVYW][kRowsW]) {
     using K = Case<C>;
     static_assert(kVPW == 3, "three x velocities per wave");
-    f4 va[6], vb[6];
+    T va[6], vb[6];
     if constexpr (K::shared) {
         constexpr int G = K::gs;
         read_groups<G, CW>(base + col[0], va);
         read_groups<G, CW>(base + col[1], vb);
-        add_rows<K::f0>(va, acc[0][0]);
-        add_rows<K::f1>(va, acc[0][1]);
+        add_rows<K::f0>(va, sc, acc[0][0]);
+        add_rows<K::f1>(va, sc, acc[0][1]);
         hold<G>(va);
         read_groups<G, CW>(base + col[2], va);
-        add_rows<K::f0>(vb, acc[1][0]);
-        add_rows<K::f1>(vb, acc[1][1]);
+        add_rows<K::f0>(vb, sc, acc[1][0]);
+        add_rows<K::f1>(vb, sc, acc[1][1]);
         hold<G>(vb);
-        add_rows<K::f0>(va, acc[2][0]);
-        add_rows<K::f1>(va, acc[2][1]);
+        add_rows<K::f0>(va, sc, acc[2][0]);
+        add_rows<K::f1>(va, sc, acc[2][1]);
         hold<G>(va);
     } else {
-        const f4* b0 = base + go0 * CW;
-        const f4* b1 = base + go1 * CW;
+        const T* b0 = base + go0 * CW;
+        const T* b1 = base + go1 * CW;
 #pragma unroll
         for (int q = 0; q < kVPW; ++q) {
             read_groups<K::g0, CW>(b0 + col[q], va);
             read_groups<K::g1, CW>(b1 + col[q], vb);
-            add_rows<K::f0>(va, acc[q][0]);
+            add_rows<K::f0>(va, sc, acc[q][0]);
             hold<K::g0>(va);
-            add_rows<K::f1>(vb, acc[q][1]);
+            add_rows<K::f1>(vb, sc, acc[q][1]);
             hold<K::g1>(vb);
         }
     }
@@ -522,11 +580,29 @@ __device__ __forceinline__ float sn_direct(KArgs A, const double* P, int a, int 
     const int Wp = A->Wp, ldx = A->ldx, ldy = A->ldy, n = A->n;
     const int x0 = x + A->padL, y0 = y + A->padT;
     float acc = 0.f;
+    if (A->half) {
+        // 16-bit copy: fma of each sample with its frame's scale, then the
+        // backgrounds of the covering frames (the stacking loop's arithmetic)
+        typedef const __attribute__((address_space(1))) _Float16 GHalf;
+        typedef const __attribute__((address_space(1))) double GDouble;
+        GHalf* pad16 = (GHalf*)A->pad;
+        GFloat* sc = (GFloat*)A->scale;
 #pragma unroll 1
-    for (int k = 0; k < n; ++k) {
-        const int i = ordr[(long long)k * rec + 4];
-        const int dx = DX[(long long)i * ldx + a], dy = DY[(long long)i * ldy + b];
-        acc += pad[(long long)i * fstride + pad_at(y0 + dy, x0 + dx, Wp)];
+        for (int k = 0; k < n; ++k) {
+            const int i = ordr[(long long)k * rec + 4];
+            const int dx = DX[(long long)i * ldx + a], dy = DY[(long long)i * ldy + b];
+            const float v = (float)pad16[2 * (long long)i * fstride + pad_at(y0 + dy, x0 + dx, Wp)];
+            acc = __builtin_fmaf(v, sc[i], acc);
+        }
+        GDouble* Pb = (GDouble*)A->Pb;
+        acc -= (float)(Pb[hi + 1] - Pb[lo]);
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < n; ++k) {
+            const int i = ordr[(long long)k * rec + 4];
+            const int dx = DX[(long long)i * ldx + a], dy = DY[(long long)i * ldy + b];
+            acc += pad[(long long)i * fstride + pad_at(y0 + dy, x0 + dx, Wp)];
+        }
     }
     const double V = P[hi + 1] - P[lo];
     return V > 0.0 ? acc * rsqrtf((float)V) : 0.f;
@@ -723,10 +799,11 @@ __device__ __forceinline__ void for_cases(F& f, std::integer_sequence<int, Cs...
     (f(ic<Cs>{}), ...);
 }
 
-// LDS floats of a workgroup of shape SH: the staging ring, or after the frame
-// loop the epilogue's areas (candidate columns, exchanged boundary rows,
-// coverage and normaliser tables, variance prefix), whichever is larger, plus
-// one int for the batch kernel's work counter.
+// LDS floats of a workgroup of shape SH: the staging ring (float32 windows,
+// the larger), or after the frame loop the epilogue's areas (candidate
+// columns, exchanged boundary rows, coverage, normaliser and background
+// tables, variance prefix), whichever is larger, plus one int for the batch
+// kernel's work counter.
 template <int SH>
 struct Lds {
     static constexpr int NW = shape_waves(SH);
@@ -737,20 +814,27 @@ struct Lds {
     static constexpr int iy = ((kVYW * kRows + 1) * 2 + 3) / 4 * 4;  // (areas stay 16-byte aligned)
     static constexpr int rs = (kVYW * kRows + 1 + 3) / 4 * 4;
     static constexpr int rm = kVYW * kRows;
+    static constexpr int cb = kVYW * kRows;
     static constexpr int p = 2 * kPLds;  // doubles
-    static constexpr int epi = colf + xch + iy + rs + rm + p;
+    static constexpr int epi = colf + xch + iy + rs + rm + cb + p;
     static constexpr int total = (stage > epi ? stage : epi) + 4;
 };
 
 // One work item of the stacking kernels: tile and velocity block number
 // `logical` of the problem A describes (Ap: where a callee reads A); lds is
 // the workgroup's LDS array (Lds<SH>::total floats).
-template <bool DETECT, bool STAGED, int SH>
+template <bool DETECT, bool STAGED, int SH, bool HALF = false>
 __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int logical, float* lds) {
-    constexpr int NW = shape_waves(SH), VBX = shape_vbx(SH), CW = shape_cw_max(SH);
-    constexpr int NBUF = shape_nbuf(SH), NI = shape_ni_max(SH), REC = shape_rec_ints(SH);
-    constexpr int BUFF = Lds<SH>::buf;
+    static_assert(!HALF || (DETECT && STAGED), "16-bit samples: the staged search only");
+    constexpr int NW = shape_waves(SH), VBX = shape_vbx(SH);
+    constexpr int CW = HALF ? shape_cw_half(SH) : shape_cw_max(SH);  // window columns
+    constexpr int CB = HALF ? 8 : 16;  // bytes of four rows of one column
+    constexpr int NBUF = shape_nbuf(SH), REC = shape_rec_ints(SH);
+    constexpr int NI = HALF ? shape_ni_half(SH) : shape_ni_max(SH);
+    constexpr int BUFF = NI * kWave * 4;      // floats per staging buffer
+    static_assert(BUFF <= Lds<SH>::buf, "buffers inside the ring");
     constexpr int NSTX = (NI + NW - 1) / NW;  // most staging loads per wave and frame
+    using T = typename std::conditional<HALF, u2, f4>::type;
     static_assert(NI >= NW && NSTX * (NBUF - 2 > 0 ? NBUF - 2 : 1) < 16, "every wave stages; vmcnt field");
     static_assert(NBUF <= kRecPad, "records read ahead stay inside the block's list");
     const int tid = threadIdx.x;
@@ -784,24 +868,27 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
 
     if constexpr (STAGED) {
         // this wave's staging loads: instructions wave, wave + NW, ... of the
-        // NI per frame; lane l of instruction s copies chunk 64 s + l of the
-        // window (row group g = chunk / CW, column chunk % CW), lanes past the
+        // NI per frame; lane l of instruction s copies the 16 bytes 64 s + l
+        // of the window: 16 / CB columns from column k = (64 s + l) 16 / CB
+        // of the window (row group k / CW, column k % CW); lanes past the
         // window copy its first chunk into the buffer's slack
         const int nst = (NI - wave + NW - 1) / NW;
         int voff[NSTX];
 #pragma unroll
         for (int j = 0; j < NSTX; ++j) {
-            const int q = (wave + NW * j) * kWave + lane;
-            voff[j] = q < kRG * CW ? ((q / CW) * A.Wp + q % CW) * 16 : 0;
+            const int k = ((wave + NW * j) * kWave + lane) * (16 / CB);
+            voff[j] = k < kRG * CW ? ((k / CW) * A.Wp + k % CW) * CB : 0;
         }
-        const int toff = ((Y0 >> 2) * A.Wp + X0) * 16;  // bytes of the tile origin in a padded frame
-        const int fbytes = (int)(A.fstride * 4);        // < 2^31 on this path
+        const int toff = ((Y0 >> 2) * A.Wp + X0) * CB;  // bytes of the tile origin in a padded frame
+        const int fbytes = (int)(A.fstride * CB / 4);   // < 2^31 on this path
         // frame k of the block into its ring buffer (past the last frame: a
-        // repeat of it, never read); the frame's address and window offset
-        // from k's record
+        // repeat of it, never read); the frame's address and float32 window
+        // offset from k's record (16-bit copies sit at the same addresses
+        // with half the offsets)
         auto stage = [&](int k, int lo, int hi, int woff) __attribute__((always_inline)) {
             const float* fr = reinterpret_cast<const float*>(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-            stage_window<NW, NSTX>(fr, fbytes, voff, nst, woff + toff, lds + (k % NBUF) * BUFF, wave);
+            stage_window<NW, NSTX>(fr, fbytes, voff, nst, (HALF ? woff >> 1 : woff) + toff,
+                                   lds + (k % NBUF) * BUFF, wave);
         };
         // the first NBUF - 1 frames
 #pragma unroll
@@ -823,6 +910,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         CInt* rc = rec;
         int slo = rs[0], shi = rs[1], swoff = rs[2];
         int cgg = rc[3];
+        float csc = HALF ? __int_as_float(rc[kRecScale]) : 1.f;
         int ccol[kVPW];
 #pragma unroll
         for (int q = 0; q < kVPW; ++q) ccol[q] = rc[kRecCol + kVPW * xg + q];
@@ -832,8 +920,8 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             // frame k + NBUF - 1 into the buffer frame k - 1 used
             stage(k + NBUF - 1, slo, shi, swoff);
             if (busy) {
-                const f4* base = reinterpret_cast<const f4*>(lds + (k % NBUF) * BUFF) + 4 * h * CW + lane;
-                add_frame<C, CW>(base, ccol, cgg & 0xFFFF, cgg >> 16, acc);
+                const T* base = reinterpret_cast<const T*>(lds + (k % NBUF) * BUFF) + 4 * h * CW + lane;
+                add_frame<C, CW>(base, ccol, cgg & 0xFFFF, cgg >> 16, csc, acc);
             }
             // next records, loaded after the frame's LDS reads have been
             // used (scalar loads share their wait counter with LDS reads and
@@ -844,6 +932,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             rc += REC;
             const int nlo = rs[0], nhi = rs[1], nwoff = rs[2];
             const int ngg = rc[3];
+            const float nsc = HALF ? __int_as_float(rc[kRecScale]) : 1.f;
             int ncol[kVPW];
 #pragma unroll
             for (int q = 0; q < kVPW; ++q) ncol[q] = rc[kRecCol + kVPW * xg + q];
@@ -858,6 +947,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             shi = nhi;
             swoff = nwoff;
             cgg = ngg;
+            csc = nsc;
 #pragma unroll
             for (int q = 0; q < kVPW; ++q) ccol[q] = ncol[q];
             ++k;
@@ -914,7 +1004,8 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     int* const sIYa = reinterpret_cast<int*>(xch + L::xch);
     float* const sRSa = reinterpret_cast<float*>(sIYa + L::iy);
     float* const sRM = sRSa + L::rs;
-    double* const sP = reinterpret_cast<double*>(sRM + L::rm);
+    float* const sCB = sRM + L::rm;
+    double* const sP = reinterpret_cast<double*>(sCB + L::cb);
     int* const sIY = sIYa + 2;
     float* const sRS = sRSa + 1;
     const bool need_c = DETECT || A.mean || A.cov != nullptr;
@@ -950,16 +1041,44 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             }
             sRS[e] = rs;
             sRM[e] = (hi - lo + 1 >= A.cmin && hi >= lo) ? rs : __builtin_nanf("");
+            // 16-bit samples: the backgrounds of the row's frames, subtracted
+            // from sums whose x samples all lie inside
+            if constexpr (HALF) sCB[e] = hi >= lo ? (float)(A.Pb[hi + 1] - A.Pb[lo]) : 0.f;
         }
-        // publish the row next to the other half: row kRowsW - 1 of the upper
-        // half, row 0 of the lower one
+    }
+    // publish the row next to the other half: row kRowsW - 1 of the upper
+    // half, row 0 of the lower one (after the background of the 16-bit
+    // search, which needs the tables, is subtracted)
+    auto publish = [&]() __attribute__((always_inline)) {
         float* xo = xch + wave * (kVPW * kVYW * kWave);
 #pragma unroll
         for (int q = 0; q < kVPW; ++q)
 #pragma unroll
             for (int s = 0; s < kVYW; ++s) xo[(q * kVYW + s) * kWave + lane] = h ? acc[q][s][0] : acc[q][s][kRowsW - 1];
-    }
+    };
+    if constexpr (DETECT && !HALF) publish();
     if (need_c) __syncthreads();
+    // 16-bit samples: S' = sum of scale * sample - the covering frames'
+    // means, their sum from the prefix of the means (the S/N evaluation of
+    // a single pixel does the same); for a lane whose x samples all lie
+    // inside, the covering frames are the row's, whose sum is tabulated
+    auto bg_row = [&](int q, int e) __attribute__((always_inline)) -> float {
+        if (xlo[q] == 0 && xhi[q] == A.n - 1) return sCB[e];
+        int lo, hi;
+        const int cv = coverage(xlo[q], xhi[q], sIY[2 * e], sIY[2 * e + 1], lo, hi);
+        return cv > 0 ? (float)(A.Pb[hi + 1] - A.Pb[lo]) : 0.f;
+    };
+    if constexpr (HALF) {
+        float* xo = xch + wave * (kVPW * kVYW * kWave);
+#pragma unroll
+        for (int q = 0; q < kVPW; ++q)
+#pragma unroll
+            for (int s = 0; s < kVYW; ++s) {
+                const int r = h ? 0 : kRowsW - 1;
+                xo[(q * kVYW + s) * kWave + lane] = acc[q][s][r] - bg_row(q, s * kRows + h * kRowsW + r);
+            }
+        __syncthreads();
+    }
 
     if constexpr (!DETECT) {
         // plain stack: SUM or MEAN, optional coverage
@@ -1006,6 +1125,27 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             constexpr int q = decltype(qc)::value, s = decltype(sc)::value;
             const int bb = b0 + s;
             if (aw + q < A.nvx && bb < A.nvy) {
+                if constexpr (HALF) {
+                    const int e0 = s * kRows + h * kRowsW;
+                    if (__ballot(!(xlo[q] == 0 && xhi[q] == A.n - 1)) == 0) {
+                        const f4* cb = reinterpret_cast<const f4*>(sCB + e0);
+#pragma unroll
+                        for (int k = 0; k < kRowsW / 4; ++k) {
+                            const f4 t = cb[k];
+                            acc[q][s][4 * k] -= t.x;
+                            acc[q][s][4 * k + 1] -= t.y;
+                            acc[q][s][4 * k + 2] -= t.z;
+                            acc[q][s][4 * k + 3] -= t.w;
+                        }
+                    } else {
+                        // (a runtime loop through the wave's column area keeps
+                        // the registers few)
+#pragma unroll 1
+                        for (int r = 0; r < kRowsW; ++r) col[r * kWave + lane] = bg_row(q, e0 + r);
+#pragma unroll
+                        for (int r = 0; r < kRowsW; ++r) acc[q][s][r] -= col[r * kWave + lane];
+                    }
+                }
                 float rsm[kRowsW];  // this row half's multipliers (uniform)
                 const f4* src = reinterpret_cast<const f4*>(sRM + s * kRows + h * kRowsW);
 #pragma unroll
@@ -1039,12 +1179,12 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     }
 }
 
-template <bool DETECT, bool STAGED, int SH>
+template <bool DETECT, bool STAGED, int SH, bool HALF>
 __global__ __launch_bounds__(shape_waves(SH) * kWave) __attribute__((amdgpu_waves_per_eu(3)))
 void k_stack(const StackArgs A) {
     __shared__ __attribute__((aligned(16))) float lds[Lds<SH>::total];
-    stack_item<DETECT, STAGED, SH>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(),
-                                   xcd_remap(blockIdx.x, gridDim.x), lds);
+    stack_item<DETECT, STAGED, SH, HALF>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(),
+                                         xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
 // Persistent form for a batch of detect problems (all staged): each
@@ -1207,7 +1347,8 @@ __global__ __launch_bounds__(kAux) void k_merge(const int32_t* __restrict__ tcou
 
 // ------------------------------------------------------------- launchers
 hipError_t launch_stats(const void* frames, int dtype, const float* scale, int n, int h, int w, double* part,
-                        int nchunk, double* b, double* s2, float* b32, double* P, double* stats_dev, hipStream_t s) {
+                        int nchunk, double* b, double* s2, float* b32, double* P, double* Pb, double* stats_dev,
+                        hipStream_t s) {
     const long long npx = (long long)h * w;
     const dim3 grid(nchunk, n);
     if (dtype == SST_BF16)
@@ -1218,7 +1359,7 @@ hipError_t launch_stats(const void* frames, int dtype, const float* scale, int n
         hipLaunchKernelGGL(k_stats_partial<SST_F32>, grid, dim3(kAux), 0, s, frames, scale, npx, nchunk, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kAux), 0, s, part, nchunk, n, npx, b, s2, b32, P,
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kAux), 0, s, part, nchunk, n, npx, b, s2, b32, P, Pb,
                        stats_dev);
     return hipGetLastError();
 }
@@ -1243,7 +1384,9 @@ hipError_t launch_quantize(const float* frames, int n, int h, int w, int dtype, 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
     const long long chunks = (long long)(a.Hp / 4) * a.Wp;
     const dim3 grid((unsigned)((chunks + kAux - 1) / kAux), a.n);
-    if (a.dtype == SST_BF16)
+    if (a.half && a.dtype == SST_F16)
+        hipLaunchKernelGGL(k_prep_half, grid, dim3(kAux), 0, s, a);
+    else if (a.dtype == SST_BF16)
         hipLaunchKernelGGL(k_prep<SST_BF16>, grid, dim3(kAux), 0, s, a);
     else if (a.dtype == SST_F16)
         hipLaunchKernelGGL(k_prep<SST_F16>, grid, dim3(kAux), 0, s, a);
@@ -1261,15 +1404,17 @@ template <int SH>
 void launch_stack_shape(const StackArgs& a, bool detect, bool staged, dim3 grid, hipStream_t s) {
     const dim3 block(shape_waves(SH) * kWave);
     if (detect) {
-        if (staged)
-            hipLaunchKernelGGL((k_stack<true, true, SH>), grid, block, 0, s, a);
+        if (staged && a.half)
+            hipLaunchKernelGGL((k_stack<true, true, SH, true>), grid, block, 0, s, a);
+        else if (staged)
+            hipLaunchKernelGGL((k_stack<true, true, SH, false>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((k_stack<true, false, SH>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_stack<true, false, SH, false>), grid, block, 0, s, a);
     } else {
         if (staged)
-            hipLaunchKernelGGL((k_stack<false, true, SH>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_stack<false, true, SH, false>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((k_stack<false, false, SH>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_stack<false, false, SH, false>), grid, block, 0, s, a);
     }
 }
 
@@ -1281,6 +1426,25 @@ hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, int shape,
         launch_stack_shape<1>(a, detect, staged, grid, s);
     else
         launch_stack_shape<0>(a, detect, staged, grid, s);
+    return hipGetLastError();
+}
+
+// rec[kRecScale] = bits of scale[rec[4]] in every record
+__global__ __launch_bounds__(kAux) void k_rec_scale(int* ord, long long ord_stride, int nrec, long long total,
+                                                     int rec, const float* __restrict__ scale) {
+    const long long t = (long long)blockIdx.x * kAux + threadIdx.x;
+    if (t >= total) return;
+    const long long b = t / nrec, k = t - b * nrec;
+    int* r = ord + b * ord_stride + kCountInts + k * rec;
+    r[kRecScale] = __float_as_int(scale[r[4]]);
+}
+
+hipError_t launch_rec_scale(int* ord, int nblk, long long ord_stride, int nrec, int rec, const float* scale,
+                            hipStream_t s) {
+    const long long total = (long long)nblk * nrec;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rec_scale, dim3((unsigned)((total + kAux - 1) / kAux)), dim3(kAux), 0, s, ord, ord_stride,
+                       nrec, total, rec, scale);
     return hipGetLastError();
 }
 

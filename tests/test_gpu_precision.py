@@ -20,7 +20,7 @@ import pytest
 import oracle
 from oracle import sst_oracle as so
 import synth
-from parity import compare_velocity
+from parity import SAFETY, U, compare_velocity
 
 pytestmark = pytest.mark.gpu
 
@@ -96,26 +96,101 @@ def test_stats_and_stack_16bit(sst, kind):
         assert np.all(err <= 1e-5 * A + 1e-30), k
 
 
-@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def _half_extra(f, fd, ks):
+    """Extra flux bound of the search on IEEE-half samples, per velocity k.
+    That search adds fma(q, scale, S) in float32 (each step one rounding of
+    a partial sum bounded by sum |F'|, F' = scale q) and subtracts the
+    covering frames' means once at the end, so besides the float32 bound of
+    the oracle's own terms it may differ by (N + 2) u sum |F'| (the oracle's
+    F' are float32 products: one more u |F'| per term, and the final
+    subtraction)."""
+    dx = oracle.shift_table(f.t, f.t_ref, f.vx)
+    dy = oracle.shift_table(f.t, f.t_ref, f.vy)
+    out = {}
+    for k in ks:
+        a, bb = k % len(f.vx), k // len(f.vx)
+        A_raw = so.stack_velocity(fd, dx[:, a], dy[:, bb], absolute=True)[3]
+        out[k] = SAFETY * (f.n + 2) * U * A_raw
+    return out
+
+
+@pytest.mark.parametrize("kind", ["bf16", "f16", "f16-direct"])
 @pytest.mark.parametrize("center", [False, True])
 def test_detect_16bit(sst, kind, center):
+    direct = kind == "f16-direct"
+    kind = "f16" if direct else kind
     f = synth.small_case(42, 12, 97, 61, 6, 4, vmax=4.0, sky=100.0, sigma=2.0)
-    _say(f"case {f.name} {kind} center={center}")
+    _say(f"case {f.name} {kind} center={center} search on 16-bit samples: {direct}")
+    prev = sst.sst_set_half_search(direct)
     q, s, _ = oracle.quantize_frames(f.frames, kind, center=center)
     fd = oracle.dequantize_frames(q, s, kind)
-    cand, count = sst.sst_detect(_upload_q(q, kind), f.t, f.t_ref, f.vx, f.vy, 2.5, 0, 6,
-                                 scale=torch.from_numpy(s).to("cuda:0"))
-    torch.cuda.synchronize()
+    try:
+        cand, count = sst.sst_detect(_upload_q(q, kind), f.t, f.t_ref, f.vx, f.vy, 2.5, 0, 6,
+                                     scale=torch.from_numpy(s).to("cuda:0"))
+        torch.cuda.synchronize()
+    finally:
+        sst.sst_set_half_search(prev)
     got = sst.candidates_to_numpy(cand)
     cnt = count.cpu().numpy()
     nvx = len(f.vx)
     ks = list(range(nvx * len(f.vy)))
     ref = oracle.detect(fd, f.t, f.t_ref, f.vx, f.vy, 2.5, 0, 6, velocities=ks, keep_maps=True)
     b, _ = oracle.frame_stats(fd)
-    marg = sum(compare_velocity(got[k], int(cnt[k]), ref[k], f.n, float(np.abs(b).max()), 2.5, ref["c_min"], 6, f.w)
+    extra = _half_extra(f, fd, ks) if direct else {k: 0.0 for k in ks}
+    marg = sum(compare_velocity(got[k], int(cnt[k]), ref[k], f.n, float(np.abs(b).max()), 2.5, ref["c_min"], 6, f.w,
+                                extra_flux=extra[k])
                for k in ks)
     _say(f"  {int(cnt.sum())} candidates, {marg} marginal decisions")
     assert marg <= (4 if center else 16)
+
+
+@pytest.fixture
+def half_search(sst):
+    prev = sst.sst_set_half_search(True)
+    yield
+    sst.sst_set_half_search(prev)
+
+
+@pytest.mark.parametrize("shape", [0, 1])
+def test_half_search_random_cases(sst, shape, half_search):
+    """The search on IEEE-half samples (staged plans read the 16-bit copy,
+    scale each sample in a mixed-precision fma, subtract the backgrounds
+    through the prefix of the means) against the float64 oracle on the
+    dequantised frames: random small problems spanning several tiles and
+    ragged tails, centred and raw storage, both window widths, plus one
+    problem whose shifts are too spread for a staged window (the float32
+    copy)."""
+    rng = np.random.default_rng(900 + shape)
+    marg = listed = 0
+    for case in range(6):
+        n, h, w = int(rng.integers(3, 30)), int(rng.integers(20, 140)), int(rng.integers(30, 200))
+        nvx, nvy = int(rng.integers(1, 13)), int(rng.integers(1, 9))
+        vmax = 60.0 if case == 5 else float(rng.choice([0.5, 2.0, 5.0]))
+        f = synth.small_case(950 + 10 * shape + case, n, h, w, nvx, nvy, vmax=vmax, sky=float(rng.choice([0.0, 80.0])),
+                             sigma=3.0, ties=bool(case % 2))
+        center = bool(rng.integers(0, 2))
+        thr = float(rng.choice([1.5, 3.0]))
+        kmax = int(rng.choice([3, 16]))
+        q, s, _ = oracle.quantize_frames(f.frames, "f16", center=center)
+        fd = oracle.dequantize_frames(q, s, "f16")
+        plan = sst.sst_plan_detect(n, h, w, f.t, f.t_ref, f.vx, f.vy, thr, 0, kmax, shape=shape)
+        _say(f"case {case}: {f.name} f16 center={center} thr {thr} kmax {kmax} shape {shape} "
+             f"({'staged' if plan.staged else 'direct'})")
+        cand, count = plan.run(_upload_q(q, "f16"), scale=torch.from_numpy(s).to("cuda:0"))
+        torch.cuda.synchronize()
+        got = sst.candidates_to_numpy(cand)
+        cnt = count.cpu().numpy()
+        ks = list(range(nvx * nvy))
+        ref = oracle.detect(fd, f.t, f.t_ref, f.vx, f.vy, thr, 0, kmax, velocities=ks, keep_maps=True)
+        b, _ = oracle.frame_stats(fd)
+        extra = _half_extra(f, fd, ks)
+        for k in ks:
+            marg += compare_velocity(got[k], int(cnt[k]), ref[k], n, float(np.abs(b).max()), thr, ref["c_min"], kmax,
+                                     w, extra_flux=extra[k])
+            listed += min(int(ref[k]["count"]), kmax)
+        plan.close()
+    _say(f"  {marg} marginal decisions, {listed} listed entries")
+    assert marg <= 0.05 * listed + 8
 
 
 def test_16bit_frames_need_scale(sst):
@@ -125,7 +200,7 @@ def test_16bit_frames_need_scale(sst):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("kind", ["bf16", "f16"])
+@pytest.mark.parametrize("kind", ["bf16", "f16", "f16-direct"])
 @pytest.mark.parametrize("center", [False, True])
 def test_precision_full_field(sst, kind, center):
     """Full field stored in 16 bits.  Error of the background-subtracted
@@ -135,8 +210,10 @@ def test_precision_full_field(sst, kind, center):
     F - o carries one rounding of relative size <= u (the format's unit
     roundoff) and each frame's mean moves by at most u max|F - o|, so
     |dS'| <= 2 u sum_i max|F_i - o_i| plus float32 summation terms."""
+    direct = kind == "f16-direct"  # the search on the 16-bit samples themselves
+    kind = "f16" if direct else kind
     f = synth.config2()
-    _say(f"case {f.name} {kind} center={center}")
+    _say(f"case {f.name} {kind} center={center} search on 16-bit samples: {direct}")
     fr = torch.from_numpy(f.frames).to("cuda:0")
     q, s, o = sst.sst_quantize(fr, _tdtype(kind), center=center)
     u = KINDS[kind][1]
@@ -176,7 +253,13 @@ def test_precision_full_field(sst, kind, center):
     # original float32 frames, on the sampled velocities: every decision
     # outside a guard band of 6 times the measured rms S/N error of the
     # storage format (on top of the float32 bounds) must match
-    c16s, n16s = sst.sst_detect(q, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, scale=s)
+    prev = sst.sst_set_half_search(direct)
+    try:
+        c16s, n16s = sst.sst_detect(q, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, scale=s)
+        c16, n16 = sst.sst_detect(q, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, scale=s)
+        torch.cuda.synchronize()
+    finally:
+        sst.sst_set_half_search(prev)
     g16s, n16s = sst.candidates_to_numpy(c16s), n16s.cpu().numpy()
     ref = oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, velocities=ks,
                         keep_maps=True)
@@ -189,7 +272,6 @@ def test_precision_full_field(sst, kind, center):
          f"{marg} decisions inside the guard band")
     assert marg <= (4 if center else 16)
     # detections: 16-bit against float32 storage, whole grid
-    c16, n16 = sst.sst_detect(q, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max, scale=s)
     c32, n32 = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max)
     g16, g32 = sst.candidates_to_numpy(c16), sst.candidates_to_numpy(c32)
     n16, n32 = n16.cpu().numpy(), n32.cpu().numpy()
