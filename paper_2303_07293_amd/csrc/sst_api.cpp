@@ -573,6 +573,20 @@ struct sst_batch {
     std::vector<const sst_plan*> plans;
     std::vector<char> solo;
     std::vector<Round> rounds;
+    // the staged plans' preparation in groups of at most kPrepMax (plans:
+    // their batch indices), and per round the merges likewise
+    struct PrepGroup {
+        PrepBatch args{};
+        int blocks[3] = {0, 0, 0};
+        std::vector<int> plans;
+    };
+    struct MergeGroup {
+        MergeBatch args{};
+        int blocks = 0;
+        std::vector<int> plans;
+    };
+    std::vector<PrepGroup> prep;
+    std::vector<std::vector<MergeGroup>> merges;  // [round]
     // side streams (default priority) over which a run spreads the plans'
     // preparation kernels and merges, forked from and joined to the run's
     // stream by events
@@ -595,8 +609,20 @@ namespace {
 struct BatchLayout {
     std::vector<int> chunk, shape;  // per launch
     std::vector<size_t> o_tab, o_start, o_cnt;
+    std::vector<std::vector<int>> prep_groups;  // staged plans in groups of kPrepMax
+    std::vector<size_t> o_pjob, o_poff;         // per group
+    std::vector<std::vector<std::vector<int>>> merge_groups;  // [launch][group] plans
+    std::vector<std::vector<size_t>> o_mjob, o_moff;
     size_t total = 0;
 };
+
+// consecutive groups of at most kPrepMax of the given plan indices
+std::vector<std::vector<int>> groups_of(const std::vector<int>& v) {
+    std::vector<std::vector<int>> g;
+    for (size_t k = 0; k < v.size(); k += kPrepMax)
+        g.emplace_back(v.begin() + k, v.begin() + std::min(v.size(), k + (size_t)kPrepMax));
+    return g;
+}
 
 int plan_chunks(const Plan& p) { return (p.nvby + p.rows_per_chunk - 1) / p.rows_per_chunk; }
 
@@ -623,7 +649,25 @@ int batch_layout(const sst_plan* const* plans, int nplans, BatchLayout& L) {
             L.o_tab.push_back(take(cur, (size_t)np * sizeof(StackArgs)));
             L.o_start.push_back(take(cur, (size_t)(np + 1) * sizeof(int)));
             L.o_cnt.push_back(take(cur, kBatchQueues * sizeof(int)));
+            std::vector<int> in;
+            for (int j = 0; j < nplans; ++j)
+                if (in_round(plans[j]->p, r, sh)) in.push_back(j);
+            L.merge_groups.push_back(groups_of(in));
+            L.o_mjob.emplace_back();
+            L.o_moff.emplace_back();
+            for (const auto& g : L.merge_groups.back()) {
+                L.o_mjob.back().push_back(take(cur, g.size() * sizeof(MergeJob)));
+                L.o_moff.back().push_back(take(cur, (g.size() + 1) * sizeof(int)));
+            }
         }
+    std::vector<int> staged;
+    for (int j = 0; j < nplans; ++j)
+        if (plans[j]->p.staged) staged.push_back(j);
+    L.prep_groups = groups_of(staged);
+    for (const auto& g : L.prep_groups) {
+        L.o_pjob.push_back(take(cur, g.size() * sizeof(PrepJob)));
+        L.o_poff.push_back(take(cur, 3 * (g.size() + 1) * sizeof(int)));
+    }
     L.total = std::max<size_t>(cur, 256);
     return SST_OK;
 }
@@ -722,6 +766,107 @@ int sst_batch_create(const sst_plan* const* plans, int nplans, void* ws, size_t 
         std::memcpy(host.data() + L.o_tab[r], tab.data(), tab.size() * sizeof(StackArgs));
         std::memcpy(host.data() + L.o_start[r], start.data(), start.size() * sizeof(int));
     }
+    // preparation of the staged plans, in groups
+    for (size_t g = 0; g < L.prep_groups.size(); ++g) {
+        sst_batch::PrepGroup G;
+        G.plans = L.prep_groups[g];
+        const int np = (int)G.plans.size();
+        std::vector<PrepJob> jobs(np);
+        std::vector<long long> off(3 * (np + 1), 0);
+        for (int k = 0; k < np; ++k) {
+            const Plan& p = plans[G.plans[k]]->p;
+            void* w = plans[G.plans[k]]->ws;
+            PrepJob& J = jobs[k];
+            J.part = at<double>(w, p.o_part);
+            J.nchunk = p.nchunk;
+            J.npx = (long long)p.h * p.w;
+            J.b = at<double>(w, p.o_b);
+            J.s2 = at<double>(w, p.o_s2);
+            J.b32 = at<float>(w, p.o_b32);
+            J.P = at<double>(w, p.o_P);
+            J.Pb = at<double>(w, p.o_Pb);
+            J.pa.b32 = J.b32;
+            J.pa.pad = at<float>(w, p.o_pad);
+            J.pa.n = p.n;
+            J.pa.h = p.h;
+            J.pa.w = p.w;
+            J.pa.Hp = p.Hp;
+            J.pa.Wp = p.Wp;
+            J.pa.padL = p.padL;
+            J.pa.padT = p.padT;
+            J.prep_bx = (int)((((long long)p.Hp / 4) * p.Wp + kStatThreads - 1) / kStatThreads);
+            J.DX = at<int>(w, p.o_tab);
+            J.DY = at<int>(w, p.o_tab + (size_t)p.n * p.ldx * sizeof(int32_t));
+            J.ldx = p.ldx;
+            J.ldy = p.ldy;
+            J.nvx = p.nvx;
+            J.nvy = p.nvy;
+            J.w = p.w;
+            J.h = p.h;
+            J.IX = at<int>(w, p.o_ix);
+            J.IY = at<int>(w, p.o_iy);
+            off[k + 1] = off[k] + (long long)p.n * p.nchunk;
+            off[np + 1 + k + 1] = off[np + 1 + k] + (long long)p.n * J.prep_bx;
+            off[2 * (np + 1) + k + 1] = off[2 * (np + 1) + k] +
+                                        (long long)(p.w + kStatThreads - 1) / kStatThreads * p.nvx +
+                                        (long long)(p.h + kStatThreads - 1) / kStatThreads * p.nvy;
+        }
+        std::vector<int> off32(off.size());
+        for (size_t k = 0; k < off.size(); ++k) {
+            if (off[k] > 0x7FFFFFFFll) {
+                delete b;
+                return fail(SST_E_RANGE, "too many preparation workgroups in one batch group");
+            }
+            off32[k] = (int)off[k];
+        }
+        std::memcpy(host.data() + L.o_pjob[g], jobs.data(), jobs.size() * sizeof(PrepJob));
+        std::memcpy(host.data() + L.o_poff[g], off32.data(), off32.size() * sizeof(int));
+        G.args.jobs = at<PrepJob>(ws, L.o_pjob[g]);
+        G.args.off = at<int>(ws, L.o_poff[g]);
+        G.args.np = np;
+        G.blocks[0] = off32[np];
+        G.blocks[1] = off32[2 * np + 1];
+        G.blocks[2] = off32[3 * np + 2];
+        b->prep.push_back(std::move(G));
+    }
+    // merges of each round, in groups
+    b->merges.resize(b->rounds.size());
+    for (size_t r = 0; r < b->rounds.size(); ++r)
+        for (size_t g = 0; g < L.merge_groups[r].size(); ++g) {
+            sst_batch::MergeGroup M;
+            M.plans = L.merge_groups[r][g];
+            const int np = (int)M.plans.size();
+            std::vector<MergeJob> jobs(np);
+            std::vector<int> off(np + 1, 0);
+            for (int k = 0; k < np; ++k) {
+                const sst_plan* pl = plans[M.plans[k]];
+                const Plan& p = pl->p;
+                const int r0 = L.chunk[r] * p.rows_per_chunk, rows = std::min(p.rows_per_chunk, p.nvby - r0);
+                const int b_first = r0 * p.vby, b_last = std::min(p.nvy, (r0 + rows) * p.vby);
+                MergeJob& J = jobs[k];
+                J.tcount = at<int32_t>(pl->ws, p.o_tcount);
+                J.ent = at<Entry>(pl->ws, p.o_ent);
+                J.nslot = p.nslot;
+                J.kt = p.kt;
+                J.k_max = pl->k_max;
+                J.nvx = p.nvx;
+                J.w = p.w;
+                J.k_first = b_first * p.nvx;
+                const long long nk = (long long)(b_last - b_first) * p.nvx;
+                if (off[k] + nk > 0x7FFFFFFFll) {
+                    delete b;
+                    return fail(SST_E_RANGE, "too many velocities in one batch merge");
+                }
+                off[k + 1] = off[k] + (int)nk;
+            }
+            std::memcpy(host.data() + L.o_mjob[r][g], jobs.data(), jobs.size() * sizeof(MergeJob));
+            std::memcpy(host.data() + L.o_moff[r][g], off.data(), off.size() * sizeof(int));
+            M.args.jobs = at<MergeJob>(ws, L.o_mjob[r][g]);
+            M.args.off = at<int>(ws, L.o_moff[r][g]);
+            M.args.np = np;
+            M.blocks = off[np];
+            b->merges[r].push_back(std::move(M));
+        }
     hipStream_t s = static_cast<hipStream_t>(stream);
     e = hipMemcpyAsync(ws, host.data(), L.total, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -760,35 +905,50 @@ int sst_batch_run(const sst_batch* batch, const void* const* frames, const int* 
         }
         return e;
     };
-    auto on = [&](int k) { return k % (kS + 1) == 0 ? s : batch->side[k % (kS + 1) - 1]; };
-    hipError_t e = fork();
-    if (e != hipSuccess) return hip_fail(e, "batch fork");
-    for (int j = 0; j < np; ++j) {
-        const sst_plan* pl = batch->plans[j];
-        const float* sc = scales ? scales[j] : nullptr;
-        if (batch->solo[j])
-            rc = detect_enqueue(pl->p, pl->ws, frames[j], dtypes[j], sc, pl->threshold, pl->min_coverage, pl->k_max,
-                                cand[j], count[j], false, on(j));
-        else
-            rc = detect_prepare(pl->p, pl->ws, frames[j], dtypes[j], sc, false, false, on(j));
-        if (rc) return rc;
+    hipError_t e;
+    // plans too spread for a staged window run on their own, on the side
+    // streams, beside the batched work
+    bool any_solo = false;
+    for (int j = 0; j < np; ++j) any_solo = any_solo || batch->solo[j];
+    if (any_solo) {
+        if ((e = fork()) != hipSuccess) return hip_fail(e, "batch fork");
+        int k = 0;
+        for (int j = 0; j < np; ++j) {
+            if (!batch->solo[j]) continue;
+            const sst_plan* pl = batch->plans[j];
+            rc = detect_enqueue(pl->p, pl->ws, frames[j], dtypes[j], scales ? scales[j] : nullptr, pl->threshold,
+                                pl->min_coverage, pl->k_max, cand[j], count[j], false, batch->side[k++ % kS]);
+            if (rc) return rc;
+        }
     }
-    if ((e = join()) != hipSuccess) return hip_fail(e, "batch join");
+    // statistics, padded copies and coverage of the staged plans: one launch
+    // of each kernel per group
+    for (const auto& G : batch->prep) {
+        PrepBatch a = G.args;
+        for (int k = 0; k < a.np; ++k) {
+            const int j = G.plans[k];
+            a.frames[k] = frames[j];
+            a.dtype[k] = dtypes[j];
+            a.scale[k] = scales ? scales[j] : nullptr;
+        }
+        if ((e = launch_prep_batch(a, G.blocks, s)) != hipSuccess) return hip_fail(e, "batched preparation kernels");
+    }
     for (size_t r = 0; r < batch->rounds.size(); ++r) {
         const auto& R = batch->rounds[r];
         if ((e = launch_zero_i32(R.args.counter, kBatchQueues, s)) != hipSuccess)
             return hip_fail(e, "queue reset kernel");
         if ((e = launch_batch_profiled(R.args, R.groups, R.shape, s)) != hipSuccess)
             return hip_fail(e, "batch detect kernel");
-        if ((e = fork()) != hipSuccess) return hip_fail(e, "batch fork");
-        for (size_t k = 0; k < R.prob.size(); ++k) {
-            const sst_plan* pl = batch->plans[R.prob[k]];
-            const int j = R.prob[k];
-            const int r0 = R.chunk * pl->p.rows_per_chunk, rows = std::min(pl->p.rows_per_chunk, pl->p.nvby - r0);
-            if ((rc = detect_merge(pl->p, pl->ws, pl->k_max, r0, rows, cand[j], count[j], on((int)k)))) return rc;
+        for (const auto& M : batch->merges[r]) {
+            MergeBatch a = M.args;
+            for (int k = 0; k < a.np; ++k) {
+                a.cand[k] = cand[M.plans[k]];
+                a.count[k] = count[M.plans[k]];
+            }
+            if ((e = launch_merge_batch(a, M.blocks, s)) != hipSuccess) return hip_fail(e, "batched merge kernel");
         }
-        if ((e = join()) != hipSuccess) return hip_fail(e, "batch join");
     }
+    if (any_solo && (e = join()) != hipSuccess) return hip_fail(e, "batch join");
     return SST_OK;
 }
 

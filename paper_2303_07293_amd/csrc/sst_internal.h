@@ -181,6 +181,52 @@ struct PrepArgs {
     int half;  // SST_F16 frames: copy the 16-bit samples as they are (no scale, no background)
 };
 
+// Batched preparation: the statistics, padded-copy and coverage kernels of
+// up to kPrepMax plans in one launch each.  A plan's fixed arguments sit in a
+// device table; the frames, their dtype and scales (which change with every
+// run) travel in the launch arguments.  off holds three prefix arrays of
+// np + 1 ints: workgroups of the statistics, padded-copy and coverage grids.
+constexpr int kPrepMax = 64;
+struct PrepJob {
+    double* part;
+    int nchunk;
+    long long npx;
+    double* b;
+    double* s2;
+    float* b32;
+    double* P;
+    double* Pb;
+    PrepArgs pa;  // frames, dtype and scale set per run
+    int prep_bx;  // workgroups per frame of the padded copy
+    const int* DX;
+    const int* DY;
+    int ldx, ldy, nvx, nvy, w, h;
+    int* IX;
+    int* IY;
+};
+struct PrepBatch {
+    const PrepJob* jobs;
+    const int* off;
+    int np;
+    int dtype[kPrepMax];
+    const void* frames[kPrepMax];
+    const float* scale[kPrepMax];
+};
+// The merges of up to kPrepMax plans of one stacking round (off: np + 1
+// prefix of their velocity counts).
+struct MergeJob {
+    const int32_t* tcount;
+    const Entry* ent;
+    int nslot, kt, k_max, nvx, w, k_first;
+};
+struct MergeBatch {
+    const MergeJob* jobs;
+    const int* off;
+    int np;
+    sst_candidate* cand[kPrepMax];
+    int32_t* count[kPrepMax];
+};
+
 // launch wrappers (sst_kernels.hip); each returns a hipError_t
 hipError_t launch_stats(const void* frames, int dtype, const float* scale, int n, int h, int w,
                         double* part, int nchunk, double* b, double* s2, float* b32, double* P,
@@ -195,6 +241,9 @@ hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, int shape,
 hipError_t launch_rec_scale(int* ord, int nblk, long long ord_stride, int nrec, int rec, const float* scale,
                             hipStream_t s);
 hipError_t launch_stack_batch(const BatchArgs& b, int groups, int shape, hipStream_t s);
+// blocks: workgroups of the statistics, padded-copy and coverage grids
+hipError_t launch_prep_batch(const PrepBatch& b, const int* blocks, hipStream_t s);
+hipError_t launch_merge_batch(const MergeBatch& b, int blocks, hipStream_t s);
 hipError_t launch_zero_i32(int* p, int count, hipStream_t s);
 hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int nslot, int kt, int k_max,
                         int nvx, int w, int k_first, int nk, void* cand, int32_t* count,

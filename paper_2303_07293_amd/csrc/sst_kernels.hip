@@ -106,10 +106,8 @@ __device__ __forceinline__ void load_iv(const int* I, long long e, int& lo, int&
 // One workgroup per (chunk of kStatChunk pixels, frame): the chunk's sum and
 // sum of squared deviations from the chunk mean, both float64.
 template <int DT>
-__global__ __launch_bounds__(kAux) void k_stats_partial(const void* __restrict__ frames,
-                                                           const float* __restrict__ scale, long long npx,
-                                                           int nchunk, double* __restrict__ part) {
-    const int i = blockIdx.y, c = blockIdx.x;
+__device__ __forceinline__ void stats_partial(const void* __restrict__ frames, const float* __restrict__ scale,
+                                              long long npx, int nchunk, double* __restrict__ part, int i, int c) {
     const long long f0 = (long long)i * npx;
     const float sc = DT == SST_F32 ? 1.f : scale[i];
     const long long base = (long long)c * kStatChunk;
@@ -144,14 +142,20 @@ __global__ __launch_bounds__(kAux) void k_stats_partial(const void* __restrict__
     }
 }
 
+template <int DT>
+__global__ __launch_bounds__(kAux) void k_stats_partial(const void* __restrict__ frames,
+                                                           const float* __restrict__ scale, long long npx,
+                                                           int nchunk, double* __restrict__ part) {
+    stats_partial<DT>(frames, scale, npx, nchunk, part, blockIdx.y, blockIdx.x);
+}
+
 // Combine the chunks of each frame (pairwise-update formula for the sum of
 // squared deviations: M2 = sum_c [M2_c + n_c (mean_c - mean)^2]) and build the
 // prefix P[j] = sum_{i<j} s2_i used to normalise any contiguous frame range.
-__global__ __launch_bounds__(kAux) void k_stats_final(const double* __restrict__ part, int nchunk, int n,
-                                                         long long npx, double* __restrict__ b,
-                                                         double* __restrict__ s2, float* __restrict__ b32,
-                                                         double* __restrict__ P, double* __restrict__ Pb,
-                                                         double* __restrict__ stats_dev) {
+__device__ __forceinline__ void stats_final(const double* __restrict__ part, int nchunk, int n, long long npx,
+                                            double* __restrict__ b, double* __restrict__ s2,
+                                            float* __restrict__ b32, double* __restrict__ P,
+                                            double* __restrict__ Pb, double* __restrict__ stats_dev) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const double* p = part + (long long)i * nchunk * 3;
         double sum = 0.0;
@@ -192,6 +196,14 @@ __global__ __launch_bounds__(kAux) void k_stats_final(const double* __restrict__
     }
 }
 
+__global__ __launch_bounds__(kAux) void k_stats_final(const double* __restrict__ part, int nchunk, int n,
+                                                         long long npx, double* __restrict__ b,
+                                                         double* __restrict__ s2, float* __restrict__ b32,
+                                                         double* __restrict__ P, double* __restrict__ Pb,
+                                                         double* __restrict__ stats_dev) {
+    stats_final(part, nchunk, n, npx, b, s2, b32, P, Pb, stats_dev);
+}
+
 // ------------------------------------------------------------ padded copy
 // pad[i] = F_i(x - padL, y - padT) - b32[i] inside the frame, 0 outside, in
 // row groups: element (y, x) at float ((y / 4) * Wp + x) * 4 + y % 4.  Out-of-
@@ -226,11 +238,10 @@ __global__ __launch_bounds__(kAux) void k_prep_half(const PrepArgs a) {
 }
 
 template <int DT>
-__global__ __launch_bounds__(kAux) void k_prep(const PrepArgs a) {
-    const int i = blockIdx.y;
+__device__ __forceinline__ void prep(const PrepArgs& a, int i, int bx) {
     // (a padded frame has fewer than 2^31 bytes on the staged path and far
     // fewer than 2^32 chunks on any path: sides are at most about 3 x 16384)
-    const unsigned q = blockIdx.x * kAux + threadIdx.x;
+    const unsigned q = bx * kAux + threadIdx.x;
     const unsigned ng = (unsigned)a.Hp / 4;
     if (q >= ng * (unsigned)a.Wp) return;
     const int g = (int)(q / (unsigned)a.Wp);
@@ -248,6 +259,11 @@ __global__ __launch_bounds__(kAux) void k_prep(const PrepArgs a) {
     }
     f4* dst = reinterpret_cast<f4*>(a.pad + (long long)i * a.Hp * a.Wp + (long long)q * 4);
     *dst = f4{o[0], o[1], o[2], o[3]};
+}
+
+template <int DT>
+__global__ __launch_bounds__(kAux) void k_prep(const PrepArgs a) {
+    prep<DT>(a, blockIdx.y, blockIdx.x);
 }
 
 // -------------------------------------------------------------- quantiser
@@ -312,10 +328,9 @@ __global__ __launch_bounds__(kAux) void k_quantize(const float* __restrict__ fra
 // monotone in i (the timestamps are sorted), so the in-frame frames form one
 // interval and the 2-D coverage of a pixel is the intersection of its x and
 // y intervals.  Empty: (n, -1).
-__global__ __launch_bounds__(kAux) void k_cov(const int* __restrict__ D, int ld, int n, int size,
-                                                 int* __restrict__ I) {
-    const int x = blockIdx.x * kAux + threadIdx.x;
-    const int a = blockIdx.y;
+__device__ __forceinline__ void cov(const int* __restrict__ D, int ld, int n, int size, int* __restrict__ I,
+                                    int a, int bx) {
+    const int x = bx * kAux + threadIdx.x;
     if (x >= size) return;
     int lo = n, hi = -1;
     for (int i = 0; i < n; ++i) {
@@ -327,6 +342,11 @@ __global__ __launch_bounds__(kAux) void k_cov(const int* __restrict__ D, int ld,
     }
     I[2 * ((long long)a * size + x)] = lo;
     I[2 * ((long long)a * size + x) + 1] = hi;
+}
+
+__global__ __launch_bounds__(kAux) void k_cov(const int* __restrict__ D, int ld, int n, int size,
+                                                 int* __restrict__ I) {
+    cov(D, ld, n, size, I, blockIdx.y, blockIdx.x);
 }
 
 __device__ __forceinline__ int coverage(int xlo, int xhi, int ylo, int yhi, int& lo, int& hi) {
@@ -1235,10 +1255,9 @@ __global__ __launch_bounds__(kAux) void k_zero_i32(int* __restrict__ p, int coun
 // ------------------------------------------------------------------ merge
 // One workgroup per velocity: gather the entries kept by every tile, rank
 // them by key and write the first k_max in order; count = all candidates.
-__global__ __launch_bounds__(kAux) void k_merge(const int32_t* __restrict__ tcount, const Entry* __restrict__ ent,
-                                                   int nslot, int kt, int k_max, int nvx, int w, int k_first,
-                                                   sst_candidate* __restrict__ cand, int32_t* __restrict__ count) {
-    const int kc = blockIdx.x;
+__device__ __forceinline__ void merge(const int32_t* __restrict__ tcount, const Entry* __restrict__ ent, int nslot,
+                                      int kt, int k_max, int nvx, int w, int k_first, sst_candidate* __restrict__ cand,
+                                      int32_t* __restrict__ count, int kc) {
     const int k = k_first + kc;
     __shared__ unsigned long long keys[kMergeLds];
     __shared__ int idx[kMergeLds];
@@ -1343,6 +1362,108 @@ __global__ __launch_bounds__(kAux) void k_merge(const int32_t* __restrict__ tcou
         out[r] = o;
     }
     if (threadIdx.x == 0) count[k] = (int32_t)min(tot, (long long)INT_MAX);
+}
+
+__global__ __launch_bounds__(kAux) void k_merge(const int32_t* __restrict__ tcount, const Entry* __restrict__ ent,
+                                                   int nslot, int kt, int k_max, int nvx, int w, int k_first,
+                                                   sst_candidate* __restrict__ cand, int32_t* __restrict__ count) {
+    merge(tcount, ent, nslot, kt, k_max, nvx, w, k_first, cand, count, blockIdx.x);
+}
+
+// ------------------------------------------------- batched preparation
+// The same kernels for every plan of a batch in one launch each: workgroup
+// t belongs to the job j with off[j] <= t < off[j + 1] and runs that job's
+// workgroup t - off[j] (in the order of the single-plan grid, x fastest).
+__device__ __forceinline__ int job_of(const int* __restrict__ off, int np, int t) {
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kAux) void k_stats_partial_batch(const PrepBatch B) {
+    const int t = blockIdx.x;
+    const int j = job_of(B.off, B.np, t);
+    const PrepJob& J = B.jobs[j];
+    const int l = t - B.off[j];
+    const int i = l / J.nchunk, c = l - i * J.nchunk;
+    if (B.dtype[j] == SST_BF16)
+        stats_partial<SST_BF16>(B.frames[j], B.scale[j], J.npx, J.nchunk, J.part, i, c);
+    else if (B.dtype[j] == SST_F16)
+        stats_partial<SST_F16>(B.frames[j], B.scale[j], J.npx, J.nchunk, J.part, i, c);
+    else
+        stats_partial<SST_F32>(B.frames[j], B.scale[j], J.npx, J.nchunk, J.part, i, c);
+}
+
+__global__ __launch_bounds__(kAux) void k_stats_final_batch(const PrepBatch B) {
+    const PrepJob& J = B.jobs[blockIdx.x];
+    stats_final(J.part, J.nchunk, J.pa.n, J.npx, J.b, J.s2, J.b32, J.P, J.Pb, nullptr);
+}
+
+__global__ __launch_bounds__(kAux) void k_prep_batch(const PrepBatch B) {
+    const int t = blockIdx.x;
+    const int j = job_of(B.off + (B.np + 1), B.np, t);
+    const PrepJob& J = B.jobs[j];
+    const int l = t - B.off[(B.np + 1) + j];
+    const int i = l / J.prep_bx, bx = l - i * J.prep_bx;
+    PrepArgs a = J.pa;
+    a.frames = B.frames[j];
+    a.dtype = B.dtype[j];
+    a.scale = B.scale[j];
+    if (a.dtype == SST_BF16)
+        prep<SST_BF16>(a, i, bx);
+    else if (a.dtype == SST_F16)
+        prep<SST_F16>(a, i, bx);
+    else
+        prep<SST_F32>(a, i, bx);
+}
+
+// both coverage tables of every job: x (nvx rows of w) then y (nvy rows of h)
+__global__ __launch_bounds__(kAux) void k_cov_batch(const PrepBatch B) {
+    const int t = blockIdx.x;
+    const int j = job_of(B.off + 2 * (B.np + 1), B.np, t);
+    const PrepJob& J = B.jobs[j];
+    int l = t - B.off[2 * (B.np + 1) + j];
+    const int bxx = (J.w + kAux - 1) / kAux, bxy = (J.h + kAux - 1) / kAux;
+    if (l < bxx * J.nvx) {
+        const int a = l / bxx;
+        cov(J.DX, J.ldx, J.pa.n, J.w, J.IX, a, l - a * bxx);
+    } else {
+        l -= bxx * J.nvx;
+        const int b = l / bxy;
+        cov(J.DY, J.ldy, J.pa.n, J.h, J.IY, b, l - b * bxy);
+    }
+}
+
+__global__ __launch_bounds__(kAux) void k_merge_batch(const MergeBatch B) {
+    const int t = blockIdx.x;
+    const int j = job_of(B.off, B.np, t);
+    const MergeJob& J = B.jobs[j];
+    merge(J.tcount, J.ent, J.nslot, J.kt, J.k_max, J.nvx, J.w, J.k_first, B.cand[j], B.count[j], t - B.off[j]);
+}
+
+hipError_t launch_prep_batch(const PrepBatch& b, const int* blocks, hipStream_t s) {
+    if (b.np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stats_partial_batch, dim3((unsigned)blocks[0]), dim3(kAux), 0, s, b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stats_final_batch, dim3((unsigned)b.np), dim3(kAux), 0, s, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prep_batch, dim3((unsigned)blocks[1]), dim3(kAux), 0, s, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cov_batch, dim3((unsigned)blocks[2]), dim3(kAux), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_batch(const MergeBatch& b, int blocks, hipStream_t s) {
+    if (b.np <= 0 || blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge_batch, dim3((unsigned)blocks), dim3(kAux), 0, s, b);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------- launchers
