@@ -357,6 +357,18 @@ int sst_bin2x2(const float* frames, int n, int h, int w, float* out, void* strea
  * full-field search (about 21 ms against 18 ms).  Not used by batches. */
 int sst_set_half_search(int on);
 
+/* Candidate entries each (tile, row half, velocity) of a detect launch
+ * keeps, at most (process-wide, for plans and calls prepared from now on;
+ * 0 restores the automatic choice; returns the previous setting).  The
+ * automatic choice keeps k_max when the whole grid's slots fit 256 MiB,
+ * else what fits, but at least 4 (the full field, 81 x 81 velocities over
+ * 1024 x 1024 pixels, keeps 4).  A velocity whose kept entries may miss one
+ * of its k_max best (a slot found more candidates than it kept, and the
+ * last kept ranks among the list's first k_max) is recomputed exactly after
+ * the merge, so the setting changes memory and time, never the lists; it
+ * exists to test and tune that path. */
+int sst_set_slot_keep(int kt);
+
 /* Kernel timing for measurements.  Between sst_profile_begin() and
  * sst_profile_end(), every launch of the stacking kernel (the dominant cost
  * of sst_stack and sst_detect) is bracketed by HIP events recorded on the

@@ -37,6 +37,7 @@ from .binding import (  # noqa: F401
     sst_quantize,
     sst_refine,
     sst_set_half_search,
+    sst_set_slot_keep,
     sst_shapes,
     sst_shift_table,
     sst_stack,

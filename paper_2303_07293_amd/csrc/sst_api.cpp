@@ -42,10 +42,16 @@ constexpr int kMaxFrames = 65535;
 constexpr int kMaxSide = 16384;
 constexpr int kMaxGrid = 65535;
 constexpr double kMaxShift = 1073741824.0;  // 2^30
-// Device memory for the candidate slots of one stacking launch: velocity-
-// block rows beyond it run in further launches (64-entry lists of an 81 x 81
-// grid over 1024 x 1024 frames need 7.1 GB, one launch).
-constexpr size_t kEntryBudget = size_t(8) << 30;
+// Candidate slots.  Each (tile, row half, velocity) keeps its best kt
+// candidates and counts all of them; kt is k_max when the slots of the
+// whole grid fit kSlotBudget, else what fits, but at least kKeepMin.  A
+// velocity whose kept entries may miss one of its k_max best is recomputed
+// exactly after the merge, so kt changes time, never lists.  Velocity-block
+// rows whose slots exceed kEntryBudget run in further launches.
+constexpr size_t kSlotBudget = size_t(256) << 20;
+constexpr int kKeepMin = 4;
+constexpr size_t kEntryBudget = size_t(512) << 20;
+std::atomic<int> g_keep{0};  // sst_set_slot_keep: cap on kt for plans made from now on (0: none)
 
 int check_dims(int n, int h, int w) {
     if (n < 1 || n > kMaxFrames) return fail(SST_E_ARG, "n = %d frames: need 1..%d", n, kMaxFrames);
@@ -117,6 +123,7 @@ struct Plan {
     size_t ord_stride = 0;
     // workspace offsets (bytes)
     size_t o_geom = 0, o_tab = 0, o_part = 0, o_b = 0, o_s2 = 0, o_P = 0, o_Pb = 0, o_b32 = 0, o_sdev = 0;
+    size_t o_flag = 0, flag_bytes = 0;  // list of velocities to recompute (detect)
     size_t o_ix = 0, o_iy = 0, o_pad = 0, o_tcount = 0, o_ent = 0, o_qpart = 0, o_dt = 0, total = 0;
 };
 
@@ -267,6 +274,12 @@ int make_plan_shape(int op, int n, int h, int w, const double* t, double t_ref, 
 
     p.o_tab = take(cur, ((size_t)n * p.ldx + (size_t)n * p.ldy) * sizeof(int32_t));
     p.o_geom = take(cur, p.G.size() * sizeof(int32_t));
+    if (detect) {
+        // (uploaded as zeros with the tables: the list starts empty, and
+        // each run's recomputation leaves it empty)
+        p.flag_bytes = ((size_t)kFlagHead + (size_t)p.ldy * nvx) * sizeof(int32_t);
+        p.o_flag = take(cur, p.flag_bytes);
+    }
     p.o_b32 = take(cur, (size_t)n * sizeof(float));
     p.o_ix = take(cur, (size_t)nvx * w * 2 * sizeof(int32_t));
     p.o_iy = take(cur, (size_t)nvy * h * 2 * sizeof(int32_t));
@@ -278,7 +291,10 @@ int make_plan_shape(int op, int n, int h, int w, const double* t, double t_ref, 
         p.o_P = take(cur, (size_t)(n + 1) * sizeof(double));
         p.o_Pb = take(cur, (size_t)(n + 1) * sizeof(double));
         p.o_sdev = take(cur, (size_t)n * 2 * sizeof(double));
-        p.kt = k_max;
+        const size_t per_kept = (size_t)p.ldy * nvx * p.nslot * sizeof(Entry);  // one entry in every slot
+        p.kt = (int)std::max<size_t>(kKeepMin, std::min<size_t>(k_max, kSlotBudget / per_kept));
+        p.kt = std::min(p.kt, k_max);
+        if (g_keep.load() > 0) p.kt = std::min(p.kt, g_keep.load());
         const size_t per_row = (size_t)p.vby * nvx * p.nslot * ((size_t)p.kt * sizeof(Entry) + sizeof(int32_t));
         // as few launches as the budget allows, with their rows balanced
         const int max_rows = (int)std::max<size_t>(1, std::min<size_t>(p.nvby, kEntryBudget / per_row));
@@ -356,7 +372,7 @@ int upload_tables(const Plan& p, const double* bg, void* ws, hipStream_t s) {
                 r[1] = (int32_t)(uint32_t)(a >> 32);
             }
     }
-    size_t bytes = p.o_geom - p.o_tab + p.G.size() * sizeof(int32_t);
+    size_t bytes = (p.o_flag ? p.o_flag + p.flag_bytes : p.o_geom + p.G.size() * sizeof(int32_t)) - p.o_tab;
     if (bg) {
         float* f = reinterpret_cast<float*>(host.data() + (p.o_b32 - p.o_tab));
         for (int i = 0; i < p.n; ++i) f[i] = (float)bg[i];
@@ -515,14 +531,42 @@ int detect_prepare(const Plan& p, void* ws, const void* frames, int dtype, const
 }
 
 // Merge of the slots of velocity-block rows [r0, r0 + rows) into the lists.
-int detect_merge(const Plan& p, void* ws, int k_max, int r0, int rows, sst_candidate* cand, int32_t* count,
-                 hipStream_t s) {
+// Workgroups of a recomputation launch (each takes listed velocities until
+// none is left; a launch with none listed ends at once).
+constexpr int kFixGroups = 512;
+
+// The merge job of velocity-block rows [r0, r0 + rows) of plan p (args: the
+// launch's arguments in device memory, or null for the single-plan form).
+MergeJob merge_job(const Plan& p, void* ws, int k_max, int r0, int rows, const StackArgs* args) {
+    MergeJob J{};
+    J.tcount = at<int32_t>(ws, p.o_tcount);
+    J.ent = at<Entry>(ws, p.o_ent);
+    J.nslot = p.nslot;
+    J.kt = p.kt;
+    J.k_max = k_max;
+    J.nvx = p.nvx;
+    J.w = p.w;
+    J.k_first = r0 * p.vby * p.nvx;
+    J.args = args;
+    J.flag = at<int>(ws, p.o_flag);
+    J.vbx = p.vbx;
+    J.rec = shape_rec_ints(p.shape);
+    (void)rows;
+    return J;
+}
+
+// Merge of the slots of the launch a (velocity-block rows [r0, r0 + rows))
+// into the lists, then the exact recomputation of the velocities listed.
+int detect_merge(const Plan& p, void* ws, const StackArgs& a, int k_max, int r0, int rows, sst_candidate* cand,
+                 int32_t* count, hipStream_t s) {
     const int b_first = r0 * p.vby;
     const int b_last = std::min(p.nvy, (r0 + rows) * p.vby);
     const int nk = (b_last - b_first) * p.nvx;
-    const hipError_t e = launch_merge(at<int32_t>(ws, p.o_tcount), at<Entry>(ws, p.o_ent), p.nslot, p.kt, k_max,
-                                      p.nvx, p.w, b_first * p.nvx, nk, cand, count, s);
-    return e != hipSuccess ? hip_fail(e, "merge kernel") : SST_OK;
+    hipError_t e = launch_merge(at<int32_t>(ws, p.o_tcount), at<Entry>(ws, p.o_ent), p.nslot, p.kt, k_max, p.nvx,
+                                p.w, b_first * p.nvx, nk, cand, count, at<int>(ws, p.o_flag), s);
+    if (e != hipSuccess) return hip_fail(e, "merge kernel");
+    e = launch_fixup(a, merge_job(p, ws, k_max, r0, rows, nullptr), cand, count, std::min(kFixGroups, nk), s);
+    return e != hipSuccess ? hip_fail(e, "recomputation kernel") : SST_OK;
 }
 
 // Everything a detect call enqueues after the shift tables are in the
@@ -542,7 +586,7 @@ int detect_enqueue(const Plan& p, void* ws, const void* frames, int dtype, const
         }
         const hipError_t e = launch_stack_profiled(a, true, p.staged, p.shape, s);
         if (e != hipSuccess) return hip_fail(e, "detect kernel");
-        if ((rc = detect_merge(p, ws, k_max, r0, rows, cand, count, s))) return rc;
+        if ((rc = detect_merge(p, ws, a, k_max, r0, rows, cand, count, s))) return rc;
     }
     return SST_OK;
 }
@@ -843,15 +887,11 @@ int sst_batch_create(const sst_plan* const* plans, int nplans, void* ws, size_t 
                 const Plan& p = pl->p;
                 const int r0 = L.chunk[r] * p.rows_per_chunk, rows = std::min(p.rows_per_chunk, p.nvby - r0);
                 const int b_first = r0 * p.vby, b_last = std::min(p.nvy, (r0 + rows) * p.vby);
+                // (the plan's arguments in this round's table: the merge
+                // groups take the round's problems in order)
+                const StackArgs* args = at<StackArgs>(ws, L.o_tab[r]) + (g * kPrepMax + k);
                 MergeJob& J = jobs[k];
-                J.tcount = at<int32_t>(pl->ws, p.o_tcount);
-                J.ent = at<Entry>(pl->ws, p.o_ent);
-                J.nslot = p.nslot;
-                J.kt = p.kt;
-                J.k_max = pl->k_max;
-                J.nvx = p.nvx;
-                J.w = p.w;
-                J.k_first = b_first * p.nvx;
+                J = merge_job(p, pl->ws, pl->k_max, r0, rows, args);
                 const long long nk = (long long)(b_last - b_first) * p.nvx;
                 if (off[k] + nk > 0x7FFFFFFFll) {
                     delete b;
@@ -946,6 +986,8 @@ int sst_batch_run(const sst_batch* batch, const void* const* frames, const int* 
                 a.count[k] = count[M.plans[k]];
             }
             if ((e = launch_merge_batch(a, M.blocks, s)) != hipSuccess) return hip_fail(e, "batched merge kernel");
+            if ((e = launch_fixup_batch(a, std::min(kFixGroups, M.blocks), s)) != hipSuccess)
+                return hip_fail(e, "batched recomputation kernel");
         }
     }
     if (any_solo && (e = join()) != hipSuccess) return hip_fail(e, "batch join");
@@ -955,6 +997,8 @@ int sst_batch_run(const sst_batch* batch, const void* const* frames, const int* 
 void sst_batch_destroy(sst_batch* batch) { delete batch; }
 
 int sst_set_half_search(int on) { return g_half_search.exchange(on ? 1 : 0); }
+
+int sst_set_slot_keep(int kt) { return g_keep.exchange(kt > 0 ? kt : 0); }
 
 int sst_profile_begin(void) {
     g_err.clear();

@@ -187,6 +187,10 @@ struct PrepArgs {
 // run) travel in the launch arguments.  off holds three prefix arrays of
 // np + 1 ints: workgroups of the statistics, padded-copy and coverage grids.
 constexpr int kPrepMax = 64;
+// velocity list of the exact recomputation: [0] velocities listed, [1]
+// taken, [2] workgroups finished (first job of a launch), [3] unused; then
+// the list
+constexpr int kFlagHead = 4;
 struct PrepJob {
     double* part;
     int nchunk;
@@ -218,6 +222,13 @@ struct MergeJob {
     const int32_t* tcount;
     const Entry* ent;
     int nslot, kt, k_max, nvx, w, k_first;
+    // exact recomputation of the velocities whose kept entries may miss one
+    // of the k_max best: the launch's arguments (device copy), the list of
+    // such velocities (kFlagHead counters, then the velocity indices), and
+    // the block shape (x velocities per block, ints per frame record)
+    const StackArgs* args;
+    int* flag;
+    int vbx, rec;
 };
 struct MergeBatch {
     const MergeJob* jobs;
@@ -246,8 +257,15 @@ hipError_t launch_prep_batch(const PrepBatch& b, const int* blocks, hipStream_t 
 hipError_t launch_merge_batch(const MergeBatch& b, int blocks, hipStream_t s);
 hipError_t launch_zero_i32(int* p, int count, hipStream_t s);
 hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int nslot, int kt, int k_max,
-                        int nvx, int w, int k_first, int nk, void* cand, int32_t* count,
+                        int nvx, int w, int k_first, int nk, void* cand, int32_t* count, int* flag,
                         hipStream_t s);
+// Exact lists of the velocities a merge listed (groups workgroups, each
+// taking listed velocities until none is left; the last one to finish
+// clears the list for the next run).  The single-plan form takes the launch
+// arguments by value, the batched form from the jobs.
+hipError_t launch_fixup(const StackArgs& a, const MergeJob& job, void* cand, int32_t* count, int groups,
+                        hipStream_t s);
+hipError_t launch_fixup_batch(const MergeBatch& b, int groups, hipStream_t s);
 
 // The body of sst_detect on a given workspace (sst_api.cpp), shared with
 // the entry point that uses the library's static scratch (sst_noalloc.hip),

@@ -1257,15 +1257,21 @@ __global__ __launch_bounds__(kAux) void k_zero_i32(int* __restrict__ p, int coun
 // them by key and write the first k_max in order; count = all candidates.
 __device__ __forceinline__ void merge(const int32_t* __restrict__ tcount, const Entry* __restrict__ ent, int nslot,
                                       int kt, int k_max, int nvx, int w, int k_first, sst_candidate* __restrict__ cand,
-                                      int32_t* __restrict__ count, int kc) {
+                                      int32_t* __restrict__ count, int* __restrict__ flag, int kc) {
     const int k = k_first + kc;
     __shared__ unsigned long long keys[kMergeLds];
     __shared__ int idx[kMergeLds];
     __shared__ int nst;
+    __shared__ unsigned long long last;  // key of the list's k_max-th entry (0: fewer than k_max)
+    __shared__ int inexact;
     __shared__ long long shl[4];
     __shared__ unsigned long long bk[4];
     __shared__ long long bi[4];
-    if (threadIdx.x == 0) nst = 0;
+    if (threadIdx.x == 0) {
+        nst = 0;
+        last = 0;
+        inexact = 0;
+    }
     __syncthreads();
     const int32_t* tc = tcount + (long long)kc * nslot;
     const Entry* E = ent + (long long)kc * nslot * kt;
@@ -1306,6 +1312,7 @@ __device__ __forceinline__ void merge(const int32_t* __restrict__ tcount, const 
             int r = 0;
             for (int f = 0; f < m; ++f) r += keys[f] > ke ? 1 : 0;
             if (r < k_max) emit(E[idx[e]], r);
+            if (r == k_max - 1) last = ke;
         }
     } else {
         unsigned long long prev = ~0ull;
@@ -1348,7 +1355,20 @@ __device__ __forceinline__ void merge(const int32_t* __restrict__ tcount, const 
             prev = gb;
             __syncthreads();
         }
+        if (threadIdx.x == 0 && nout == k_max) last = prev;
     }
+    // A slot that found more candidates than it kept dropped only keys below
+    // its last kept one; the list is exact unless such a key could rank
+    // among the first k_max.  Otherwise the velocity is listed for an exact
+    // recomputation.
+    __syncthreads();
+    for (int t = threadIdx.x; t < nslot; t += kAux)
+        if (tc[t] > kt) {
+            const Entry en = E[(long long)t * kt + kt - 1];
+            if (cand_key(en.sn, en.raster) > last) inexact = 1;
+        }
+    __syncthreads();
+    if (threadIdx.x == 0 && inexact) flag[kFlagHead + atomicAdd(flag, 1)] = kc;
     for (int r = nout + threadIdx.x; r < k_max; r += kAux) {
         sst_candidate o;
         o.ivx = ivx;
@@ -1366,8 +1386,9 @@ __device__ __forceinline__ void merge(const int32_t* __restrict__ tcount, const 
 
 __global__ __launch_bounds__(kAux) void k_merge(const int32_t* __restrict__ tcount, const Entry* __restrict__ ent,
                                                    int nslot, int kt, int k_max, int nvx, int w, int k_first,
-                                                   sst_candidate* __restrict__ cand, int32_t* __restrict__ count) {
-    merge(tcount, ent, nslot, kt, k_max, nvx, w, k_first, cand, count, blockIdx.x);
+                                                   sst_candidate* __restrict__ cand, int32_t* __restrict__ count,
+                                                   int* __restrict__ flag) {
+    merge(tcount, ent, nslot, kt, k_max, nvx, w, k_first, cand, count, flag, blockIdx.x);
 }
 
 // ------------------------------------------------- batched preparation
@@ -1444,7 +1465,8 @@ __global__ __launch_bounds__(kAux) void k_merge_batch(const MergeBatch B) {
     const int t = blockIdx.x;
     const int j = job_of(B.off, B.np, t);
     const MergeJob& J = B.jobs[j];
-    merge(J.tcount, J.ent, J.nslot, J.kt, J.k_max, J.nvx, J.w, J.k_first, B.cand[j], B.count[j], t - B.off[j]);
+    merge(J.tcount, J.ent, J.nslot, J.kt, J.k_max, J.nvx, J.w, J.k_first, B.cand[j], B.count[j], J.flag,
+          t - B.off[j]);
 }
 
 hipError_t launch_prep_batch(const PrepBatch& b, const int* blocks, hipStream_t s) {
@@ -1463,6 +1485,294 @@ hipError_t launch_prep_batch(const PrepBatch& b, const int* blocks, hipStream_t 
 hipError_t launch_merge_batch(const MergeBatch& b, int blocks, hipStream_t s) {
     if (b.np <= 0 || blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_merge_batch, dim3((unsigned)blocks), dim3(kAux), 0, s, b);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------ exact recomputation
+// For a listed velocity (its slots kept fewer entries than the k_max best
+// may need): a list of the best keys so far in LDS, fed with the kept
+// entries of every slot that kept all its candidates and with the
+// candidates of every other slot recomputed from the padded copy (the
+// stacking loop's float32 sums in the block's frame order, then the same
+// S/N, threshold, coverage and 8-neighbour rules on the slot's 16 x 64
+// pixels with a border of one), then written over the velocity's list.
+constexpr int kFixCap = 2048;         // list entries in LDS
+constexpr int kFixRows = kRowsW + 2;  // slot rows with their border
+constexpr int kFixCols = kTileW + 2;
+constexpr int kFixPix = kFixRows * kFixCols;
+constexpr int kFixPer = (kFixPix + kAux - 1) / kAux;  // pixels per thread
+constexpr int kSlotMax = (kRowsW / 2) * (kTileW / 2);  // candidates a slot can hold (no two adjacent)
+
+struct FixLds {
+    unsigned long long key[kFixCap];
+    float flux[kFixCap];
+    int cov[kFixCap];
+    float sn[kFixPix];
+    float acc[kFixPix];
+    int c[kFixPix];
+    int m;
+    int item;
+};
+
+// Sort the list descending by key and keep its first `keep` entries.
+__device__ void fix_compact(FixLds& L, int keep) {
+    __syncthreads();
+    const int m = L.m;
+    int N = 1;
+    while (N < m) N <<= 1;
+    for (int i = m + threadIdx.x; i < N; i += kAux) L.key[i] = 0;
+    __syncthreads();
+    for (int k = 2; k <= N; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < N; i += kAux) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long a = L.key[i], b = L.key[l];
+                    if ((i & k) == 0 ? a < b : a > b) {
+                        L.key[i] = b;
+                        L.key[l] = a;
+                        const float f = L.flux[i];
+                        L.flux[i] = L.flux[l];
+                        L.flux[l] = f;
+                        const int c = L.cov[i];
+                        L.cov[i] = L.cov[l];
+                        L.cov[l] = c;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    if (threadIdx.x == 0) L.m = min(m, keep);
+    __syncthreads();
+}
+
+__device__ __forceinline__ void fix_append(FixLds& L, unsigned long long key, float flux, int cov) {
+    const int p = atomicAdd(&L.m, 1);
+    L.key[p] = key;
+    L.flux[p] = flux;
+    L.cov[p] = cov;
+}
+
+// The candidates of slot t of velocity (a, b), appended to the list (which
+// has room for kSlotMax more).
+__device__ void fix_slot(KArgs A, FixLds& L, int a, int b, int t, int vbx, int rec) {
+    const int tile = t >> 1, hh = t & 1;
+    const int X0 = (tile % A->tiles_x) * kTileW, Y0 = (tile / A->tiles_x) * kRows;
+    const int xr = X0 - 1, yr = Y0 + kRowsW * hh - 1;  // pixel of border entry (0, 0)
+    const int n = A->n, w = A->w, h = A->h;
+    typedef const __attribute__((address_space(1))) float GFloat;
+    typedef const __attribute__((address_space(1))) _Float16 GHalf;
+    typedef const __attribute__((address_space(1))) int GInt;
+    typedef const __attribute__((address_space(1))) double GDouble;
+    GInt* ordr = (GInt*)(A->ord + (long long)((b / kVYW) * A->nvbx + a / vbx) * A->ord_stride + kCountInts);
+    GInt* DX = (GInt*)A->DX;
+    GInt* DY = (GInt*)A->DY;
+    const long long fstride = A->fstride;
+    float acc[kFixPer];
+    int px[kFixPer], py[kFixPer];
+    bool in[kFixPer];
+#pragma unroll
+    for (int q = 0; q < kFixPer; ++q) {
+        const int p = threadIdx.x + q * kAux;
+        px[q] = xr + p % kFixCols;
+        py[q] = yr + p / kFixCols;
+        in[q] = p < kFixPix && px[q] >= 0 && px[q] < w && py[q] >= 0 && py[q] < h;
+        acc[q] = 0.f;
+    }
+    // the sums, frame by frame in the block's order
+    for (int k = 0; k < n; ++k) {
+        const int i = ordr[(long long)k * rec + 4];
+        const int dx = DX[(long long)i * A->ldx + a] + A->padL, dy = DY[(long long)i * A->ldy + b] + A->padT;
+        if (A->half) {
+            GHalf* pad16 = (GHalf*)A->pad + 2 * (long long)i * fstride;
+            const float sc = ((GFloat*)A->scale)[i];
+#pragma unroll
+            for (int q = 0; q < kFixPer; ++q)
+                if (in[q]) acc[q] = __builtin_fmaf((float)pad16[pad_at(py[q] + dy, px[q] + dx, A->Wp)], sc, acc[q]);
+        } else {
+            GFloat* pad = (GFloat*)A->pad + (long long)i * fstride;
+#pragma unroll
+            for (int q = 0; q < kFixPer; ++q)
+                if (in[q]) acc[q] += pad[pad_at(py[q] + dy, px[q] + dx, A->Wp)];
+        }
+    }
+    // S/N and coverage, as the stacking kernel forms them
+    const double* P = A->P;
+#pragma unroll
+    for (int q = 0; q < kFixPer; ++q) {
+        const int p = threadIdx.x + q * kAux;
+        if (p >= kFixPix) continue;
+        float sn = -INFINITY, v = acc[q];
+        int cov = 0;
+        if (in[q]) {
+            int xlo, xhi, ylo, yhi, lo, hi;
+            load_iv(A->IX, (long long)a * w + px[q], xlo, xhi);
+            load_iv(A->IY, (long long)b * h + py[q], ylo, yhi);
+            cov = coverage(xlo, xhi, ylo, yhi, lo, hi);
+            if (cov > 0) {
+                if (A->half) v -= (float)(((GDouble*)A->Pb)[hi + 1] - ((GDouble*)A->Pb)[lo]);
+                const double V = P[hi + 1] - P[lo];
+                if (xlo == 0 && xhi == n - 1) {
+                    sn = v * (V > 0.0 ? rsqrtf((float)V) : 0.f);
+                } else {
+                    sn = V > 0.0 ? v * rsqrtf((float)V) : 0.f;
+                }
+            }
+        }
+        L.sn[p] = sn;
+        L.acc[p] = v;
+        L.c[p] = cov;
+    }
+    __syncthreads();
+    // peaks of the slot's own pixels (border entries 1 .. kFixRows - 2 and
+    // 1 .. kFixCols - 2): above threshold with enough coverage, above every
+    // earlier neighbour in raster order and not below any later one
+    for (int e = threadIdx.x; e < kRowsW * kTileW; e += kAux) {
+        const int r = 1 + e / kTileW, cc = 1 + e % kTileW;
+        const int p = r * kFixCols + cc;
+        const float sv = L.sn[p];
+        if (!(L.c[p] >= A->cmin && sv > A->thr)) continue;
+        bool ok = true;
+        for (int k = 0; k < 9 && ok; ++k) {
+            if (k == 4) continue;
+            const int dy = k / 3 - 1, dx = k % 3 - 1;
+            const float sq = L.sn[p + dy * kFixCols + dx];
+            ok = (dy < 0 || (dy == 0 && dx < 0)) ? sv > sq : sv >= sq;
+        }
+        if (ok) {
+            const int x = xr + cc, y = yr + r;
+            fix_append(L, cand_key(sv, y * w + x), L.acc[p], L.c[p]);
+        }
+    }
+    __syncthreads();
+}
+
+// Exact list of velocity kc of a merge job (A: the launch's arguments).
+__device__ void fix_velocity(KArgs A, const MergeJob& J, sst_candidate* cand, FixLds& L, int kc) {
+    const int k = J.k_first + kc;
+    const int a = k % J.nvx, b = k / J.nvx;
+    const int32_t* tc = J.tcount + (long long)kc * J.nslot;
+    const Entry* E = J.ent + (long long)kc * J.nslot * J.kt;
+    if (threadIdx.x == 0) L.m = 0;
+    __syncthreads();
+    for (int t = 0; t < J.nslot; ++t) {
+        const int c = tc[t];  // (uniform)
+        if (c == 0) continue;
+        const int add = c <= J.kt ? c : kSlotMax;
+        if (L.m + add > kFixCap) fix_compact(L, J.k_max);
+        if (c <= J.kt) {
+            for (int e = threadIdx.x; e < c; e += kAux) {
+                const Entry en = E[(long long)t * J.kt + e];
+                fix_append(L, cand_key(en.sn, en.raster), en.flux, en.cov);
+            }
+            __syncthreads();
+        } else {
+            fix_slot(A, L, a, b, t, J.vbx, J.rec);
+        }
+    }
+    fix_compact(L, J.k_max);
+    sst_candidate* out = cand + (long long)k * J.k_max;
+    for (int r = threadIdx.x; r < J.k_max; r += kAux) {
+        sst_candidate o;
+        o.ivx = a;
+        o.ivy = b;
+        if (r < L.m) {
+            const unsigned long long key = L.key[r];
+            unsigned u = (unsigned)(key >> 32);
+            u ^= (u & 0x80000000u) ? 0x80000000u : 0xFFFFFFFFu;
+            const int raster = (int)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFull));
+            o.x = raster % J.w;
+            o.y = raster / J.w;
+            o.snr = __uint_as_float(u);
+            o.flux = L.flux[r];
+            o.coverage = L.cov[r];
+            o.rank = r;
+        } else {
+            o.x = -1;
+            o.y = -1;
+            o.snr = -INFINITY;
+            o.flux = 0.f;
+            o.coverage = 0;
+            o.rank = -1;
+        }
+        out[r] = o;
+    }
+    __syncthreads();
+}
+
+// The listed velocities of jobs [0, njobs), taken one at a time; the last
+// workgroup to finish clears every job's list.
+template <typename GetJob>
+__device__ void fix_loop(int njobs, GetJob get) {
+    __shared__ FixLds L;
+    __shared__ int listed;
+    int* head = get(0).flag;
+    if (threadIdx.x == 0) {
+        int any = 0;
+        for (int j = 0; j < njobs; ++j) any |= atomicAdd(get(j).flag, 0);
+        listed = any;
+    }
+    __syncthreads();
+    if (listed == 0) return;  // no velocity listed by these merges (the same in every workgroup)
+    for (int j = 0; j < njobs; ++j) {
+        KArgs A;
+        sst_candidate* cand;
+        const MergeJob& J = get(j, &A, &cand);
+        for (;;) {
+            if (threadIdx.x == 0) {
+                const int it = atomicAdd(J.flag + 1, 1);
+                L.item = it < atomicAdd(J.flag, 0) ? J.flag[kFlagHead + it] : -1;
+            }
+            __syncthreads();
+            const int kc = L.item;
+            __syncthreads();
+            if (kc < 0) break;
+            fix_velocity(A, J, cand, L, kc);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && atomicAdd(head + 2, 1) == (int)gridDim.x - 1) {
+        for (int j = 0; j < njobs; ++j) {
+            int* f = get(j).flag;
+            f[0] = 0;
+            f[1] = 0;
+        }
+        __threadfence();
+        head[2] = 0;
+    }
+}
+
+struct FixOne {
+    MergeJob job;
+    sst_candidate* cand;
+};
+
+__global__ __launch_bounds__(kAux) void k_fixup(const StackArgs A, const FixOne F) {
+    const KArgs Ap = (KArgs)__builtin_amdgcn_kernarg_segment_ptr();
+    fix_loop(1, [&](int, KArgs* a = nullptr, sst_candidate** c = nullptr) -> const MergeJob& {
+        if (a) *a = Ap;
+        if (c) *c = F.cand;
+        return F.job;
+    });
+}
+
+__global__ __launch_bounds__(kAux) void k_fixup_batch(const MergeBatch B) {
+    fix_loop(B.np, [&](int j, KArgs* a = nullptr, sst_candidate** c = nullptr) -> const MergeJob& {
+        if (a) *a = B.jobs[j].args;
+        if (c) *c = B.cand[j];
+        return B.jobs[j];
+    });
+}
+
+hipError_t launch_fixup(const StackArgs& a, const MergeJob& job, void* cand, int32_t*, int groups, hipStream_t s) {
+    FixOne f{job, static_cast<sst_candidate*>(cand)};
+    hipLaunchKernelGGL(k_fixup, dim3((unsigned)groups), dim3(kAux), 0, s, a, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_fixup_batch(const MergeBatch& b, int groups, hipStream_t s) {
+    if (b.np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fixup_batch, dim3((unsigned)groups), dim3(kAux), 0, s, b);
     return hipGetLastError();
 }
 
@@ -1585,9 +1895,9 @@ hipError_t launch_zero_i32(int* p, int count, hipStream_t s) {
 }
 
 hipError_t launch_merge(const int32_t* tcount, const Entry* ent, int nslot, int kt, int k_max, int nvx, int w,
-                        int k_first, int nk, void* cand, int32_t* count, hipStream_t s) {
+                        int k_first, int nk, void* cand, int32_t* count, int* flag, hipStream_t s) {
     hipLaunchKernelGGL(k_merge, dim3(nk), dim3(kAux), 0, s, tcount, ent, nslot, kt, k_max, nvx, w, k_first,
-                       static_cast<sst_candidate*>(cand), count);
+                       static_cast<sst_candidate*>(cand), count, flag);
     return hipGetLastError();
 }
 

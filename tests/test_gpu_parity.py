@@ -252,6 +252,58 @@ def test_detect_many_candidates_truncation_and_merge(sst):
     _check_detect(sst, f, -100.0, 0, 1024, max_marginal=120)
 
 
+@pytest.mark.parametrize("keep", [1, 3])
+def test_recomputation_of_truncated_slots(sst, keep):
+    """Slots that keep only 1 or 3 candidates: nearly every velocity of a
+    flood is listed after the merge and recomputed exactly (kept entries of
+    the complete slots plus the other slots' candidates from the padded
+    copy), and the lists must be those of the oracle, and bit for bit those
+    of slots that keep everything; tile borders, edge lanes, both shapes,
+    the batch form and the search on 16-bit samples go through it too."""
+    prev = sst.sst_set_slot_keep(keep)
+    try:
+        f = synth.pure_noise(3, 6, 300, 420, sigma=1.0, sky=3.0)
+        f.vx = np.array([0.0, 1.0])
+        f.vy = np.array([-1.0, 0.0])
+        _say(f"case flood, slots keep {keep}")
+        _check_detect(sst, f, -100.0, 0, 40, max_marginal=50)
+        _check_detect(sst, f, -100.0, 0, 1024, max_marginal=120)
+        g = synth.tile_border_case()
+        _say(f"case {g.name}, slots keep {keep}")
+        _check_detect(sst, g, g.threshold, g.min_coverage, g.k_max, max_marginal=2 * len(synth.BORDER_TIES) + 2)
+        cases = [synth.small_case(60 + c, int(n), int(h), int(w), 7, 5, vmax=vm, sky=10.0, sigma=2.0)
+                 for c, (n, h, w, vm) in enumerate([(9, 70, 150, 2.0), (14, 40, 90, 6.0), (5, 100, 64, 0.5)])]
+        for c in cases:
+            _say(f"case {c.name}, slots keep {keep}")
+            _check_detect(sst, c, 1.0, 0, 16, max_marginal=20)
+    finally:
+        sst.sst_set_slot_keep(prev)
+    # bit for bit against slots that keep everything (plans of each shape,
+    # single runs and one batch)
+    for c in cases:
+        fr = _dev(c.frames)
+        ref = sst.sst_detect(fr, c.t, c.t_ref, c.vx, c.vy, 1.0, 0, 16)
+        prev = sst.sst_set_slot_keep(keep)
+        try:
+            plans = [sst.sst_plan_detect(c.n, c.h, c.w, c.t, c.t_ref, c.vx, c.vy, 1.0, 0, 16, shape=sh)
+                     for sh in range(len(sst.sst_shapes()))]
+        finally:
+            sst.sst_set_slot_keep(prev)
+        for pl in plans:
+            got = pl.run(fr)
+            torch.cuda.synchronize()
+            assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), (c.name, pl.shape)
+        batch = sst.SstBatch(plans)
+        cands, counts = batch.run([fr] * len(plans))
+        torch.cuda.synchronize()
+        for k in range(len(plans)):
+            assert torch.equal(cands[k], ref[0]) and torch.equal(counts[k], ref[1]), (c.name, "batch", k)
+        batch.close()
+        for pl in plans:
+            pl.close()
+    _say("  plans of every shape and a batch match slots that keep everything")
+
+
 def test_detect_constant_frames(sst):
     """Zero-variance frames: V = 0 gives S/N 0 everywhere; with threshold -1
     the only candidate is the raster-first pixel of the flat plateau."""

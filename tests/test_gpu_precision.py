@@ -151,8 +151,8 @@ def half_search(sst):
     sst.sst_set_half_search(prev)
 
 
-@pytest.mark.parametrize("shape", [0, 1])
-def test_half_search_random_cases(sst, shape, half_search):
+@pytest.mark.parametrize("shape,keep", [(0, 0), (1, 0), (0, 2)])
+def test_half_search_random_cases(sst, shape, keep, half_search):
     """The search on IEEE-half samples (staged plans read the 16-bit copy,
     scale each sample in a mixed-precision fma, subtract the backgrounds
     through the prefix of the means) against the float64 oracle on the
@@ -160,7 +160,7 @@ def test_half_search_random_cases(sst, shape, half_search):
     ragged tails, centred and raw storage, both window widths, plus one
     problem whose shifts are too spread for a staged window (the float32
     copy)."""
-    rng = np.random.default_rng(900 + shape)
+    rng = np.random.default_rng(900 + shape + 7 * keep)
     marg = listed = 0
     for case in range(6):
         n, h, w = int(rng.integers(3, 30)), int(rng.integers(20, 140)), int(rng.integers(30, 200))
@@ -173,7 +173,11 @@ def test_half_search_random_cases(sst, shape, half_search):
         kmax = int(rng.choice([3, 16]))
         q, s, _ = oracle.quantize_frames(f.frames, "f16", center=center)
         fd = oracle.dequantize_frames(q, s, "f16")
-        plan = sst.sst_plan_detect(n, h, w, f.t, f.t_ref, f.vx, f.vy, thr, 0, kmax, shape=shape)
+        prev = sst.sst_set_slot_keep(keep)  # 2: most velocities recomputed after the merge
+        try:
+            plan = sst.sst_plan_detect(n, h, w, f.t, f.t_ref, f.vx, f.vy, thr, 0, kmax, shape=shape)
+        finally:
+            sst.sst_set_slot_keep(prev)
         _say(f"case {case}: {f.name} f16 center={center} thr {thr} kmax {kmax} shape {shape} "
              f"({'staged' if plan.staged else 'direct'})")
         cand, count = plan.run(_upload_q(q, "f16"), scale=torch.from_numpy(s).to("cuda:0"))
