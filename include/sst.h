@@ -25,7 +25,12 @@
  *  - Memory: "dev" pointers are device memory of the current HIP device,
  *    "host" pointers are host memory.  The caller owns every buffer; the
  *    library keeps no per-call state and allocates no device memory (all
- *    scratch space is the caller's workspace `ws`).
+ *    scratch space is the caller's workspace `ws`).  The one-shot
+ *    sst_stack and sst_detect copy their host-built shift tables into `ws`
+ *    through one process-wide pinned host buffer (allocated on first use,
+ *    grown when needed, kept until the process ends), so they return
+ *    without waiting for that copy; they are not for graph capture (use a
+ *    plan).
  *  - Layout: frames are C-contiguous [n][h][w]; velocity index k = b*nvx + a
  *    (vy major); stacks are [nvy][nvx][h][w].
  *  - Streams: work is enqueued on `stream` (a hipStream_t; NULL = the null

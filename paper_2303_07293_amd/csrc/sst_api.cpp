@@ -351,8 +351,71 @@ T* at(void* ws, size_t off) {
     return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
+// Pinned staging buffer of the one-shot calls' table uploads: one per
+// process, grown when needed, reused once the stream has consumed the last
+// copy from it (an event marks that), so a call does not wait for its own
+// upload.
+struct Staging {
+    std::mutex mu;
+    void* host = nullptr;
+    size_t bytes = 0;
+    int device = -1;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+Staging g_stage;
+
+// Copy bytes from src to device dst on stream s through the pinned staging
+// buffer; returns false (nothing enqueued) if it cannot be used.
+bool upload_pinned(const void* src, size_t bytes, void* dst, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_stage.mu);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (g_stage.device != dev) {
+        // (first use, or another device: start over on this one)
+        if (g_stage.pending && hipEventSynchronize(g_stage.done) != hipSuccess) return false;
+        if (g_stage.done) (void)hipEventDestroy(g_stage.done);
+        if (g_stage.host) (void)hipHostFree(g_stage.host);
+        g_stage.host = nullptr;
+        g_stage.bytes = 0;
+        g_stage.done = nullptr;
+        g_stage.pending = false;
+        if (hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming) != hipSuccess) {
+            g_stage.done = nullptr;
+            return false;
+        }
+        g_stage.device = dev;
+    }
+    if (g_stage.pending) {
+        if (hipEventSynchronize(g_stage.done) != hipSuccess) return false;
+        g_stage.pending = false;
+    }
+    if (bytes > g_stage.bytes) {
+        if (g_stage.host) (void)hipHostFree(g_stage.host);
+        g_stage.host = nullptr;
+        g_stage.bytes = 0;
+        if (hipHostMalloc(&g_stage.host, bytes, hipHostMallocDefault) != hipSuccess) {
+            g_stage.host = nullptr;
+            return false;
+        }
+        g_stage.bytes = bytes;
+    }
+    std::memcpy(g_stage.host, src, bytes);
+    if (hipMemcpyAsync(dst, g_stage.host, bytes, hipMemcpyHostToDevice, s) != hipSuccess) return false;
+    if (hipEventRecord(g_stage.done, s) != hipSuccess) {
+        // (the copy is enqueued: wait for it before the buffer is reused)
+        (void)hipStreamSynchronize(s);
+        return true;
+    }
+    g_stage.pending = true;
+    return true;
+}
+
 // Upload the shift tables (and optional per-frame floats) in one copy.
-int upload_tables(const Plan& p, const double* bg, void* ws, hipStream_t s) {
+// pinned: through the pinned staging buffer, without waiting (the tables
+// are consumed on stream s only); else from pageable memory, waiting for the
+// copy (no host allocation: the entry point that allocates nothing).
+int upload_tables(const Plan& p, const double* bg, void* ws, hipStream_t s, bool pinned) {
     const size_t nx = (size_t)p.n * p.ldx, ny = (size_t)p.n * p.ldy;
     std::vector<char> host(p.o_b32 - p.o_tab + (size_t)p.n * sizeof(float), 0);
     std::memcpy(host.data(), p.DX.data(), nx * sizeof(int32_t));
@@ -378,6 +441,8 @@ int upload_tables(const Plan& p, const double* bg, void* ws, hipStream_t s) {
         for (int i = 0; i < p.n; ++i) f[i] = (float)bg[i];
         bytes = host.size();
     }
+    if (pinned && upload_pinned(host.data(), bytes, at<char>(ws, p.o_tab), s)) return SST_OK;
+    (void)hipGetLastError();  // (a failed pinned path falls back to the pageable copy)
     hipError_t e = hipMemcpyAsync(at<char>(ws, p.o_tab), host.data(), bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(shift tables)");
     // the copy is from pageable memory; make sure it has been consumed before
@@ -1247,7 +1312,7 @@ int sst_stack(const void* frames, int dtype, const float* scale, int n, int h, i
     if ((rc = make_plan(SST_OP_STACK, n, h, w, t, t_ref, vx, nvx, vy, nvy, 0, p))) return rc;
     if ((rc = check_ws(p, ws, ws_bytes))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((rc = upload_tables(p, bg, ws, s))) return rc;
+    if ((rc = upload_tables(p, bg, ws, s, true))) return rc;
     if ((rc = prep_and_cov(p, frames, dtype, scale, bg ? at<float>(ws, p.o_b32) : nullptr, ws, s))) return rc;
     StackArgs a = stack_args(p, ws);
     a.out = out;
@@ -1263,7 +1328,7 @@ int sst_detect(const void* frames, int dtype, const float* scale, int n, int h, 
                sst_candidate* cand, int32_t* count, double* frame_stats, void* ws, size_t ws_bytes, void* stream) {
     g_err.clear();
     return sst::detect_call(frames, dtype, scale, n, h, w, t, t_ref, vx, nvx, vy, nvy, threshold, min_coverage, k_max,
-                            cand, count, frame_stats, ws, ws_bytes, stream);
+                            cand, count, frame_stats, ws, ws_bytes, stream, true);
 }
 
 }  // extern "C"
@@ -1275,7 +1340,7 @@ int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 int detect_call(const void* frames, int dtype, const float* scale, int n, int h, int w, const double* t,
                 double t_ref, const double* vx, int nvx, const double* vy, int nvy, float threshold,
                 int min_coverage, int k_max, sst_candidate* cand, int32_t* count, double* frame_stats, void* ws,
-                size_t ws_bytes, void* stream) {
+                size_t ws_bytes, void* stream, bool pinned_upload) {
     int rc = check_frames(frames, dtype, scale);
     if (rc) return rc;
     if (!cand || !count) return fail(SST_E_ARG, "cand/count is NULL");
@@ -1284,7 +1349,7 @@ int detect_call(const void* frames, int dtype, const float* scale, int n, int h,
     if ((rc = make_plan(SST_OP_DETECT, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p))) return rc;
     if ((rc = check_ws(p, ws, ws_bytes))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((rc = upload_tables(p, nullptr, ws, s))) return rc;
+    if ((rc = upload_tables(p, nullptr, ws, s, pinned_upload))) return rc;
     if ((rc = detect_enqueue(p, ws, frames, dtype, scale, threshold, min_coverage, k_max, cand, count,
                              frame_stats != nullptr, s)))
         return rc;
@@ -1323,7 +1388,7 @@ int sst_plan_detect_shape(int shape, int n, int h, int w, const double* t, doubl
     if (!pl) return fail(SST_E_DEVICE, "out of host memory");
     int rc = make_plan(SST_OP_DETECT, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, pl->p, shape);
     if (!rc) rc = check_ws(pl->p, ws, ws_bytes);
-    if (!rc) rc = upload_tables(pl->p, nullptr, ws, static_cast<hipStream_t>(stream));
+    if (!rc) rc = upload_tables(pl->p, nullptr, ws, static_cast<hipStream_t>(stream), false);
     if (rc) {
         delete pl;
         return rc;

@@ -273,7 +273,7 @@ hipError_t launch_fixup_batch(const MergeBatch& b, int groups, hipStream_t s);
 int detect_call(const void* frames, int dtype, const float* scale, int n, int h, int w, const double* t,
                 double t_ref, const double* vx, int nvx, const double* vy, int nvy, float threshold,
                 int min_coverage, int k_max, sst_candidate* cand, int32_t* count, double* frame_stats, void* ws,
-                size_t ws_bytes, void* stream);
+                size_t ws_bytes, void* stream, bool pinned_upload);
 int set_error(int code, const char* msg);
 
 // sub-pixel refinement (sst_refine.hip)

@@ -62,7 +62,7 @@ int sst_detect_noalloc(const void* frames, int dtype, const float* scale, int n,
     const size_t need = sst_workspace_bytes(SST_OP_DETECT, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max);
     if (need == 0)  // an argument error: the full call reports it (and enqueues nothing)
         return sst::detect_call(frames, dtype, scale, n, h, w, t, t_ref, vx, nvx, vy, nvy, threshold, min_coverage,
-                                k_max, cand, count, frame_stats, nullptr, 0, stream);
+                                k_max, cand, count, frame_stats, nullptr, 0, stream, false);
     if (need > kScratchBytes) {
         char msg[256];
         snprintf(msg, sizeof msg, "problem needs %zu bytes of workspace; the static scratch holds %zu", need,
@@ -73,7 +73,7 @@ int sst_detect_noalloc(const void* frames, int dtype, const float* scale, int n,
     void* ws = scratch_of_current_device(&rc);
     if (!ws) return rc;
     return sst::detect_call(frames, dtype, scale, n, h, w, t, t_ref, vx, nvx, vy, nvy, threshold, min_coverage, k_max,
-                            cand, count, frame_stats, ws, kScratchBytes, stream);
+                            cand, count, frame_stats, ws, kScratchBytes, stream, false);
 }
 
 }  // extern "C"
