@@ -64,7 +64,9 @@ extern "C" {
  * the frame value is the float32 product s_i * (stored value), and every
  * later step (statistics, stacking, S/N) works on those float32 values
  * exactly as on float32 frames; sums stay float32.  Storage only: the
- * search itself is not computed in 16 bits. */
+ * search itself is not computed in 16 bits (with sst_set_half_search on,
+ * staged searches of SST_F16 frames read the 16-bit samples and scale each
+ * in a mixed-precision FMA into float32 sums). */
 #define SST_F32 0
 #define SST_BF16 1
 #define SST_F16 2
