@@ -1102,6 +1102,96 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
 
     if constexpr (!DETECT) {
         // plain stack: SUM or MEAN, optional coverage
+        auto value = [&](int q, int s, int r, int& c) __attribute__((always_inline)) -> float {
+            float v = acc[q][s][r];
+            c = 0;
+            if (need_c) {
+                int lo, hi;
+                const int tr = h * kRowsW + r;
+                c = max(0, coverage(xlo[q], xhi[q], sIY[2 * (s * kRows + tr)], sIY[2 * (s * kRows + tr) + 1], lo, hi));
+            }
+            if (A.mean) v = c > 0 ? v / (float)c : 0.f;
+            return v;
+        };
+        // A tile inside the frame's columns (row length a multiple of four,
+        // outputs 16-byte aligned) writes each velocity's 16 x 64 block of
+        // the wave through the wave's LDS column area, so that a lane stores
+        // four adjacent columns of one row with one 16-byte store: four times
+        // fewer store instructions, which keeps the stores from holding the
+        // workgroup long after its frame loop.  Streaming stores: the stacks
+        // are not read again by this kernel, the staged frames are.
+        const bool wide = X0 + kTileW <= A.w && (A.w & 3) == 0 && ((uintptr_t)A.out & 15) == 0 &&
+                          ((uintptr_t)A.cov & 15) == 0;
+        if (wide) {
+            float* tb = colarea + wave * (kColRows * kWave);
+            const int rr = lane >> 4, cc = (lane & 15) * 4;
+            if (!need_c) {
+                // SUM without coverage (its own loop: no per-element
+                // coverage code to schedule around)
+#pragma unroll
+                for (int q = 0; q < kVPW; ++q) {
+#pragma unroll
+                    for (int s = 0; s < kVYW; ++s) {
+                        const int a = aw + q, bb = b0 + s;
+                        if (a < A.nvx && bb < A.nvy) {
+                            const long long base = ((long long)bb * A.nvx + a) * A.h;
+#pragma unroll
+                            for (int r = 0; r < kRowsW; ++r) tb[r * kWave + lane] = acc[q][s][r];
+#pragma unroll
+                            for (int j = 0; j < kRowsW / 4; ++j) {
+                                const int y = Y0 + h * kRowsW + 4 * j + rr;
+                                const f4 v = *reinterpret_cast<const f4*>(tb + (4 * j + rr) * kWave + cc);
+                                if (y < A.h)
+                                    __builtin_nontemporal_store(
+                                        v, reinterpret_cast<f4*>(A.out + (base + y) * A.w + X0 + cc));
+                            }
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+                return;
+            }
+#pragma unroll
+            for (int q = 0; q < kVPW; ++q) {
+#pragma unroll
+                for (int s = 0; s < kVYW; ++s) {
+                    const int a = aw + q, bb = b0 + s;
+                    if (a < A.nvx && bb < A.nvy) {
+                        const long long base = ((long long)bb * A.nvx + a) * A.h;
+#pragma unroll
+                        for (int r = 0; r < kRowsW; ++r) {
+                            int c;
+                            tb[r * kWave + lane] = value(q, s, r, c);
+                        }
+#pragma unroll
+                        for (int j = 0; j < kRowsW / 4; ++j) {
+                            const int y = Y0 + h * kRowsW + 4 * j + rr;
+                            const f4 v = *reinterpret_cast<const f4*>(tb + (4 * j + rr) * kWave + cc);
+                            if (y < A.h)
+                                __builtin_nontemporal_store(v, reinterpret_cast<f4*>(A.out + (base + y) * A.w + X0 + cc));
+                        }
+                        if (A.cov) {
+#pragma unroll
+                            for (int r = 0; r < kRowsW; ++r) {
+                                int c;
+                                (void)value(q, s, r, c);
+                                tb[r * kWave + lane] = __int_as_float(c);
+                            }
+#pragma unroll
+                            for (int j = 0; j < kRowsW / 4; ++j) {
+                                const int y = Y0 + h * kRowsW + 4 * j + rr;
+                                const i4 c = *reinterpret_cast<const i4*>(tb + (4 * j + rr) * kWave + cc);
+                                if (y < A.h)
+                                    __builtin_nontemporal_store(
+                                        c, reinterpret_cast<i4*>(A.cov + (base + y) * A.w + X0 + cc));
+                            }
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            return;
+        }
         if (!xin) return;
 #pragma unroll
         for (int q = 0; q < kVPW; ++q) {
@@ -1110,22 +1200,13 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
                 const int a = aw + q, bb = b0 + s;
                 if (a < A.nvx && bb < A.nvy) {
                     const long long kk = (long long)bb * A.nvx + a;
-                    const int* IYr = sIY + s * kRows * 2;
 #pragma unroll
                     for (int r = 0; r < kRowsW; ++r) {
-                        const int tr = h * kRowsW + r;
-                        const int y = Y0 + tr;
+                        const int y = Y0 + h * kRowsW + r;
                         if (y < A.h) {
-                            float v = acc[q][s][r];
-                            int c = 0;
-                            if (need_c) {
-                                int lo, hi;
-                                c = max(0, coverage(xlo[q], xhi[q], IYr[2 * tr], IYr[2 * tr + 1], lo, hi));
-                            }
-                            if (A.mean) v = c > 0 ? v / (float)c : 0.f;
+                            int c;
+                            const float v = value(q, s, r, c);
                             const long long o = (kk * A.h + y) * A.w + x;
-                            // streaming stores: the stacks are not read
-                            // again by this kernel, the staged frames are
                             __builtin_nontemporal_store(v, A.out + o);
                             if (A.cov) __builtin_nontemporal_store(c, A.cov + o);
                         }

@@ -114,6 +114,37 @@ def test_stack_small_cases(sst, seed, n, h, w, nvx, nvy, vmax):
     _check_stack(sst, f, bg=rng.normal(20.0, 2.0, size=n), mode="mean")
 
 
+@pytest.mark.parametrize("w", [200, 130, 128])
+@pytest.mark.parametrize("mode", ["sum", "mean"])
+def test_stack_store_forms(sst, w, mode):
+    """The plain stack's two store forms give the same stacks: tiles inside
+    the frame's columns with 16-byte aligned outputs and a row length that is
+    a multiple of four store four columns per lane (through LDS), the others
+    (ragged last tile, odd row length, an output that is not 16-byte aligned)
+    one column per lane.  Outputs with and without coverage, and at an
+    offset of one element, must agree bit for bit; the coverage run is the
+    one checked against the oracle by the other stack tests, and here the
+    first velocities are checked against it too."""
+    f = synth.small_case(77 + w, 9, 70, w, 7, 3, vmax=3.0)
+    _say(f"case {f.name} {mode}")
+    m = sst.SST_MEAN if mode == "mean" else sst.SST_SUM
+    fr = _dev(f.frames)
+    nvx, nvy = len(f.vx), len(f.vy)
+    ref, cov = sst.sst_stack(fr, f.t, f.t_ref, f.vx, f.vy, mode=m, with_coverage=True)
+    plain = sst.sst_stack(fr, f.t, f.t_ref, f.vx, f.vy, mode=m)
+    # outputs one float (and one int) past a 16-byte boundary
+    big = torch.empty(nvy * nvx * f.h * w + 1, dtype=torch.float32, device="cuda:0")
+    bigc = torch.empty(nvy * nvx * f.h * w + 1, dtype=torch.int32, device="cuda:0")
+    off = big[1:].view(nvy, nvx, f.h, w)
+    offc = bigc[1:].view(nvy, nvx, f.h, w)
+    sst.sst_stack(fr, f.t, f.t_ref, f.vx, f.vy, mode=m, with_coverage=True, out=off, cov=offc)
+    torch.cuda.synchronize()
+    assert torch.equal(plain, ref)
+    assert torch.equal(off, ref)
+    assert torch.equal(offc, cov)
+    _check_stack(sst, f, mode=mode, velocities=[0, 1, nvx + 2])
+
+
 def test_stack_direct_path(sst):
     """Velocity steps of 25 px/h over 2 h spread a block's shifts beyond the
     LDS window, which sends the whole call down the direct (L2) path."""
