@@ -110,10 +110,11 @@ size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double 
 /* Velocity-block shapes.  The stacking kernels are compiled for several
  * blocks of VBX x VBY trial velocities per workgroup (the velocity grid is
  * padded to whole blocks; a block's frame window is widened by the spread
- * of its x shifts).  Shape 0 (6 x 2, three workgroups per compute unit)
- * has the narrower window; shape 1 (18 x 2, one workgroup of 12 waves per
- * compute unit) holds x shifts that spread about three times as far per
- * velocity step.  The one-shot calls, sst_workspace_bytes and
+ * of its x shifts).  Both shapes are 6 x 2 velocities (workgroups of 4
+ * waves, three per compute unit) and differ in the window's width: shape 0
+ * holds an x-shift spread of up to 25 px over a block's 6 x velocities,
+ * shape 1 one of up to 80 px (grids whose shifts grow faster per velocity
+ * step).  The one-shot calls, sst_workspace_bytes and
  * sst_plan_detect take the first shape whose window holds the grid's
  * shifts (shape 0 if none does).  sst_shape_info writes the block size of
  * `shape` (vbx/vby may be NULL) and returns the number of shapes, or

@@ -867,8 +867,8 @@ int sst_batch_create(const sst_plan* const* plans, int nplans, void* ws, size_t 
         R.args.start = at<int>(ws, L.o_start[r]);
         R.args.nprob = np;
         R.args.counter = at<int>(ws, L.o_cnt[r]);
-        // as many workgroups as fit on the CUs at once (one per CU of 12
-        // waves, two of 6), at least one per queue, the same number per queue
+        // as many workgroups as fit on the CUs at once (three per CU of the
+        // 4-wave shapes), at least one per queue, the same number per queue
         const int per_cu = kMaxWaves / shape_waves(R.shape);
         const int want = std::max(1, std::min(start[np], std::max(ncu * per_cu, kBatchQueues)));
         R.groups = (want + kBatchQueues - 1) / kBatchQueues * kBatchQueues;
