@@ -107,14 +107,17 @@ int sst_shift_table(const double* t, int n, double t_ref, const double* v, int n
 size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double t_ref,
                            const double* vx, int nvx, const double* vy, int nvy, int k_max);
 
-/* Velocity-block shapes.  The stacking kernels are compiled for several
- * blocks of VBX x VBY trial velocities per workgroup (the velocity grid is
- * padded to whole blocks; a block's frame window is widened by the spread
- * of its x shifts).  Both shapes are 6 x 2 velocities (workgroups of 4
- * waves, three per compute unit) and differ in the window's width: shape 0
- * holds an x-shift spread of up to 25 px over a block's 6 x velocities,
- * shape 1 one of up to 80 px (grids whose shifts grow faster per velocity
- * step).  The one-shot calls, sst_workspace_bytes and
+/* Work-item shapes.  The stacking kernels are compiled for several
+ * shapes of the work of one workgroup (4 waves, three per compute unit): a
+ * tile of 64 x 32 pixels or one 64 x 16 row half of it, and a block of
+ * VBX x VBY trial velocities (the velocity grid is padded to whole blocks;
+ * a block's frame window is widened by the spread of its x shifts).
+ * Shape 0: whole tiles, 6 x 2 velocities, x-shift spread up to 25 px over
+ * the block; shape 1: the same with a window for spreads up to 80 px (grids
+ * whose shifts grow faster per velocity step); shape 2: row halves, 12 x 2
+ * velocities, spreads up to 48 px (a lower window shared by more
+ * velocities, and more border pixels evaluated on their own).  Every shape
+ * gives the same lists and stacks.  The one-shot calls, sst_workspace_bytes and
  * sst_plan_detect take the first shape whose window holds the grid's
  * shifts (shape 0 if none does).  sst_shape_info writes the block size of
  * `shape` (vbx/vby may be NULL) and returns the number of shapes, or

@@ -245,8 +245,8 @@ int make_plan_shape(int op, int n, int h, int w, const double* t, double t_ref, 
                     cas[i] = std::min(f0, f1) * 9 + (f1 - f0 + 4);
                 } else {
                     cas[i] = kNShared + (e0 & 3) * 4 + (e1 & 3);
-                    // a separate read ends at row group G + 4 + 4 of the window
-                    if (std::max((e0 >> 2) - gy, (e1 >> 2) - gy) > kRG - 9) p.staged = false;
+                    // a separate read must end inside the shape's window
+                    if (std::max((e0 >> 2) - gy, (e1 >> 2) - gy) > shape_max_sep(shape)) p.staged = false;
                 }
                 blk[cas[i]]++;
             }
@@ -834,7 +834,7 @@ int sst_batch_create(const sst_plan* const* plans, int nplans, void* ws, size_t 
             if (!in_round(p, R.chunk, R.shape)) continue;
             const int r0 = R.chunk * p.rows_per_chunk, rows = std::min(p.rows_per_chunk, p.nvby - r0);
             tab.push_back(detect_args(p, plans[j]->ws, plans[j]->threshold, plans[j]->min_coverage, r0, rows));
-            const long long items = (long long)p.tiles_x * p.tiles_y * p.nvbx * rows;
+            const long long items = (long long)p.tiles_x * p.tiles_y * shape_items_per_tile(p.shape) * p.nvbx * rows;
             if (start.back() + items > 0x7FFFFFFFll) {
                 delete b;
                 return fail(SST_E_RANGE, "too many work items in one batch round");

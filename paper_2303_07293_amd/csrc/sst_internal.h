@@ -30,34 +30,56 @@ constexpr int kRows = 32;
 constexpr int kRowsW = kRows / 2;  // rows per wave
 constexpr int kVPW = 3;  // x velocities per wave
 constexpr int kVYW = 2;  // y velocities per block (one pair)
-// Velocity-block shapes (chosen per plan).  Workgroups of 4 waves, 6 x
-// velocities per block, three workgroups per CU (one waiting at its
-// per-frame barrier leaves the SIMDs to the other two; workgroups of 6 or
-// 12 waves with windows this size get a CU to themselves and lose that).
-// The shapes differ in the width of the staged window: shape 0 holds an x
-// shift spread of 25 px over a block's 6 velocities in three ring buffers,
-// shape 1 one of 80 px in two (for grids whose shifts grow faster per
-// velocity step), both within the LDS that three workgroups may share.
-constexpr int kNShapes = 2;
+// Work-item shapes (chosen per plan).  Workgroups of 4 waves, three per CU
+// (one waiting at its per-frame barrier leaves the SIMDs to the other two;
+// workgroups of 6 or 12 waves with windows this size get a CU to
+// themselves and lose that).  Shapes 0 and 1: a work item is a whole tile
+// and a block of 6 x velocities (waves: 2 row halves x 2 groups of 3 x
+// velocities); they differ in the width of the staged window: shape 0 holds
+// an x shift spread of 25 px over the block in three ring buffers, shape 1
+// one of 80 px in two (for grids whose shifts grow faster per velocity
+// step).  Shape 2 splits the tile: a work item is one row half of a tile and
+// a block of 12 x velocities (waves: 4 groups of 3), so each staged window
+// is 6 row groups high and serves twice as many velocities per row, at the
+// cost of a wider x spread (up to 48 px over the block).  All fit the LDS
+// that three workgroups may share.
+constexpr int kNShapes = 3;
 constexpr int kMaxWaves = 12;  // waves per CU at the kernels' register use
 __host__ __device__ constexpr int shape_waves(int) { return 4; }
-__host__ __device__ constexpr int shape_vbx(int sh) { return kVPW * shape_waves(sh) / 2; }
+// work items of shape sh cover one row half of a tile (else the whole tile)
+__host__ __device__ constexpr bool shape_split(int sh) { return sh == 2; }
+__host__ __device__ constexpr int shape_vbx(int sh) {
+    return kVPW * (shape_split(sh) ? shape_waves(sh) : shape_waves(sh) / 2);
+}
 __host__ __device__ constexpr int shape_vby(int) { return kVYW; }
+// work items per tile and velocity block
+__host__ __device__ constexpr int shape_items_per_tile(int sh) { return shape_split(sh) ? 2 : 1; }
 // LDS staging.  The padded copy of every frame is stored in groups of four
 // rows: element (y, x) of a frame at float ((y / 4) * Wp + x) * 4 + y % 4, so
 // that one 16-byte chunk holds four consecutive rows of one column.  Per
 // frame a window of kRG row groups by cw columns (the tile widened by the
 // block's x-shift spread) is staged into LDS with the same layout, and a
 // lane reads four rows of its column with one 16-byte LDS read.
-constexpr int kRG = 10;  // row groups (40 rows) of the staged window
-__host__ __device__ constexpr int shape_cw_max(int sh) { return sh == 0 ? 89 : 144; }
-__host__ __device__ constexpr int shape_nbuf(int sh) { return sh == 0 ? 3 : 2; }
+constexpr int kRG = 10;  // row groups (40 rows) of the staged window of a whole tile
+// row groups of a shape's window: a whole tile, or one row half (16 rows,
+// the pair's row spread and a phase fit 6 groups)
+__host__ __device__ constexpr int shape_rg(int sh) { return shape_split(sh) ? 6 : kRG; }
+__host__ __device__ constexpr int shape_cw_max(int sh) { return sh == 0 ? 89 : (sh == 1 ? 144 : 112); }
+__host__ __device__ constexpr int shape_nbuf(int sh) { return sh == 1 ? 2 : 3; }
 // staging instructions (64 chunks each) of the largest window
-__host__ __device__ constexpr int shape_ni_max(int sh) { return (kRG * shape_cw_max(sh) + kWave - 1) / kWave; }
+__host__ __device__ constexpr int shape_ni_max(int sh) {
+    return (shape_rg(sh) * shape_cw_max(sh) + kWave - 1) / kWave;
+}
 // The same window of 16-bit samples: four rows of a column in 8 bytes, so a
 // 16-byte staging chunk holds two columns and the window width is even.
 __host__ __device__ constexpr int shape_cw_half(int sh) { return (shape_cw_max(sh) + 1) / 2 * 2; }
-__host__ __device__ constexpr int shape_ni_half(int sh) { return (kRG * shape_cw_half(sh) / 2 + kWave - 1) / kWave; }
+__host__ __device__ constexpr int shape_ni_half(int sh) {
+    return (shape_rg(sh) * shape_cw_half(sh) / 2 + kWave - 1) / kWave;
+}
+// Separate reads (below) span 5 row groups from a group offset G past the
+// window's first group, plus 4 for the lower half of a whole tile: the
+// largest G a shape's window allows
+__host__ __device__ constexpr int shape_max_sep(int sh) { return shape_rg(sh) - (shape_split(sh) ? 5 : 9); }
 // Frame order.  Within the window the rows of the pair's two y velocities
 // start at row offsets f0, f1 of the window's first row group; the pattern
 // (f0, f1) of a frame is one of kNCase read cases: 36 where the two start

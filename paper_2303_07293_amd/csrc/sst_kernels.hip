@@ -402,9 +402,11 @@ struct Case {
     static constexpr int g0 = (f0 + kRowsW - 1) / 4 + 1;
     static constexpr int g1 = (f1 + kRowsW - 1) / 4 + 1;
     static constexpr int gs = (cmax(f0, f1) + kRowsW - 1) / 4 + 1;
-    // the lower row half reads from row group 4 of the window on; a separate
-    // read may start up to kRG - 9 groups further (the host checks that)
+    // the lower row half of a whole tile reads from row group 4 of the
+    // window on (a split item's window starts at its half); a separate read
+    // may start up to shape_max_sep groups further (the host checks that)
     static_assert(!shared || 4 + gs <= kRG, "a shared read stays inside the window");
+    static_assert(!shared || gs <= 6, "a shared read stays inside a split item's window");
     static_assert(shared || 4 + cmax(g0, g1) <= 9, "separate reads span at most 5 row groups");
 };
 
@@ -631,12 +633,14 @@ __device__ __forceinline__ float sn_direct(KArgs A, const double* P, int a, int 
 // Peak test and candidate output for one (tile, velocity, row half) whose
 // column sums are parked in LDS: col[r * 64 + lane] = S' of column row r.
 // fl marks the rows (1 .. kColRows - 2) that pass threshold and coverage;
-// orow is the column row outside the tile (0 or kColRows - 1).  The
-// (tile, velocity, row half) writes its count and kept entries to slot.
+// bit r of omask marks column row r (0 or kColRows - 1) as outside the
+// work item (the next tile's row, or for an item of one row half also the
+// other half's).  The (tile, velocity, row half) writes its count and kept
+// entries to slot.
 __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* RSr, const double* P,
                                                     int xlo, int xhi, int a, int b, long long slot,
                                                     LFloat* col, unsigned fl, int lane, int x, int Yc,
-                                                    int orow, int vbx, int rec) {
+                                                    unsigned omask, int vbx, int rec) {
     SnCtx c;
     c.IYr = IYr;
     c.RSr = RSr;
@@ -651,7 +655,7 @@ __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* 
     // -infinity for now.
     auto sn_col = [&](int r) __attribute__((always_inline)) {
         int cv;
-        return r == orow ? -INFINITY : sn_row(c, col[r * kWave + lane], r, cv);
+        return ((omask >> r) & 1u) ? -INFINITY : sn_row(c, col[r * kWave + lane], r, cv);
     };
     // the left and right neighbours' values by whole-wave DPP shifts (lane 0
     // and lane 63 have none: -infinity)
@@ -685,8 +689,9 @@ __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* 
         R0 = Rp;
     }
     // pixels next to the tile's border: test the outside neighbours
-    const int erow = orow == 0 ? 1 : kColRows - 2;  // the own row next to the outside row
-    unsigned todo = cm & ((lane == 0 || lane == kWave - 1) ? kEmitRows : (1u << erow));
+    // (own rows next to an outside row)
+    const unsigned erows = ((omask & 1u) ? 2u : 0u) | (((omask >> (kColRows - 1)) & 1u) << (kColRows - 2));
+    unsigned todo = cm & ((lane == 0 || lane == kWave - 1) ? kEmitRows : erows);
 #pragma unroll 1
     while (todo != 0) {
         const int r = __builtin_ctz(todo);
@@ -697,7 +702,7 @@ __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* 
 #pragma unroll 1
         for (int k = 0; k < 9 && ok; ++k) {
             const int dy = k / 3 - 1, dx = k % 3 - 1;
-            const bool outside = lane + dx < 0 || lane + dx >= kWave || r + dy == orow;
+            const bool outside = lane + dx < 0 || lane + dx >= kWave || ((omask >> (r + dy)) & 1u);
             if (k == 4 || !outside) continue;
             const float sq = sn_direct(A, P, a, b, x + dx, Yc + r + dy, vbx, rec);
             const bool earlier = dy < 0 || (dy == 0 && dx < 0);
@@ -754,7 +759,10 @@ __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* 
 // row r if that row can hold a candidate (inside the grid, coverage >= c_min),
 // else NaN, so that acc * rsm[r] > threshold is exactly the threshold and
 // coverage test (NaN compares false).  xrow is the other row half's boundary
-// row of the same velocity; IYr and RSr start at column row 0 (tile row R0).
+// row of the same velocity (NULL for an item of one row half, whose both
+// boundary rows lie outside it); IYr and RSr start at column row 0 (tile
+// row R0).
+template <bool SPLIT>
 __device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, const float (&acc)[kRowsW],
                                                 const float (&rsm)[kRowsW], int a, int b, int x, bool xin, int lane,
                                                 int h, int Y0, int tile, float* col, const float* xrow,
@@ -805,9 +813,10 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, co
     float* own = col + kWave;
 #pragma unroll
     for (int r = 0; r < kRowsW; ++r) own[r * kWave + lane] = acc[r];
-    col[(h ? 0 : kColRows - 1) * kWave + lane] = xrow[lane];
+    if constexpr (!SPLIT) col[(h ? 0 : kColRows - 1) * kWave + lane] = xrow[lane];
+    const unsigned omask = SPLIT ? (1u << (kColRows - 1)) | 1u : (h ? (1u << (kColRows - 1)) : 1u);
     candidates_from_column(Ap, (LInt*)IYr, (LFloat*)RSr, P, xlo, xhi, a, b, slot, (LFloat*)col, fl, lane, x,
-                           Y0 + kRowsW * h - 1, h ? kColRows - 1 : 0, vbx, rec);
+                           Y0 + kRowsW * h - 1, omask, vbx, rec);
 }
 
 template <int V>
@@ -857,18 +866,22 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     using T = typename std::conditional<HALF, u2, f4>::type;
     static_assert(NI >= NW && NSTX * (NBUF - 2 > 0 ? NBUF - 2 : 1) < 16, "every wave stages; vmcnt field");
     static_assert(NBUF <= kRecPad, "records read ahead stay inside the block's list");
+    constexpr bool SPLIT = shape_split(SH);  // the item is one row half of the tile
+    constexpr int RG = shape_rg(SH);         // row groups of the window
+    static_assert(!SPLIT || RG >= 6, "a split item's window holds every shared read");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nvb = A.nvbx * A.nvby;
-    const int tile = logical / nvb;
-    const int vb = logical - tile * nvb;
+    const int titem = logical / nvb;
+    const int vb = logical - titem * nvb;
+    const int tile = SPLIT ? titem >> 1 : titem;
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
     const int bxi = vb % A.nvbx, byi = A.vby0 + vb / A.nvbx;
     const int a0 = bxi * VBX;
     const int b0 = byi * kVYW;  // the pair's first y velocity
-    const int xg = wave >> 1;   // which kVPW-group of the block's x velocities
-    const int h = wave & 1;     // row half
+    const int xg = SPLIT ? wave : wave >> 1;  // which kVPW-group of the block's x velocities
+    const int h = SPLIT ? (titem & 1) : (wave & 1);  // row half
     const int aw = a0 + kVPW * xg;  // this wave's first x velocity
     const int X0 = tx * kTileW;
     const int Y0 = ty * kRows;
@@ -897,9 +910,11 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
 #pragma unroll
         for (int j = 0; j < NSTX; ++j) {
             const int k = ((wave + NW * j) * kWave + lane) * (16 / CB);
-            voff[j] = k < kRG * CW ? ((k / CW) * A.Wp + k % CW) * CB : 0;
+            voff[j] = k < RG * CW ? ((k / CW) * A.Wp + k % CW) * CB : 0;
         }
-        const int toff = ((Y0 >> 2) * A.Wp + X0) * CB;  // bytes of the tile origin in a padded frame
+        // bytes of the item's origin in a padded frame (a split item's
+        // window starts at its row half)
+        const int toff = (((Y0 >> 2) + (SPLIT ? 4 * h : 0)) * A.Wp + X0) * CB;
         const int fbytes = (int)(A.fstride * CB / 4);   // < 2^31 on this path
         // frame k of the block into its ring buffer (past the last frame: a
         // repeat of it, never read); the frame's address and float32 window
@@ -940,7 +955,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             // frame k + NBUF - 1 into the buffer frame k - 1 used
             stage(k + NBUF - 1, slo, shi, swoff);
             if (busy) {
-                const T* base = reinterpret_cast<const T*>(lds + (k % NBUF) * BUFF) + 4 * h * CW + lane;
+                const T* base = reinterpret_cast<const T*>(lds + (k % NBUF) * BUFF) + (SPLIT ? 0 : 4 * h * CW) + lane;
                 add_frame<C, CW>(base, ccol, cgg & 0xFFFF, cgg >> 16, csc, acc);
             }
             // next records, loaded after the frame's LDS reads have been
@@ -1076,7 +1091,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
 #pragma unroll
             for (int s = 0; s < kVYW; ++s) xo[(q * kVYW + s) * kWave + lane] = h ? acc[q][s][0] : acc[q][s][kRowsW - 1];
     };
-    if constexpr (DETECT && !HALF) publish();
+    if constexpr (DETECT && !HALF && !SPLIT) publish();
     if (need_c) __syncthreads();
     // 16-bit samples: S' = sum of scale * sample - the covering frames'
     // means, their sum from the prefix of the means (the S/N evaluation of
@@ -1088,7 +1103,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         const int cv = coverage(xlo[q], xhi[q], sIY[2 * e], sIY[2 * e + 1], lo, hi);
         return cv > 0 ? (float)(A.Pb[hi + 1] - A.Pb[lo]) : 0.f;
     };
-    if constexpr (HALF) {
+    if constexpr (HALF && !SPLIT) {
         float* xo = xch + wave * (kVPW * kVYW * kWave);
 #pragma unroll
         for (int q = 0; q < kVPW; ++q)
@@ -1220,7 +1235,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         // written out per velocity (not a loop) so that acc stays in
         // registers: the epilogue is too large for the unroller to replicate
         float* col = colarea + wave * (kColRows * kWave);
-        const float* xin_rows = xch + (wave ^ 1) * (kVPW * kVYW * kWave);
+        const float* xin_rows = SPLIT ? nullptr : xch + (wave ^ 1) * (kVPW * kVYW * kWave);
         const int R0 = kRowsW * h - 1;
         auto one = [&](auto qc, auto sc, const double* P) __attribute__((always_inline)) {
             constexpr int q = decltype(qc)::value, s = decltype(sc)::value;
@@ -1257,8 +1272,9 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
                     rsm[4 * k + 2] = t.z;
                     rsm[4 * k + 3] = t.w;
                 }
-                detect_epilogue(A, Ap, acc[q][s], rsm, aw + q, bb, x, xin, lane, h, Y0, tile, col,
-                                xin_rows + (q * kVYW + s) * kWave, sIY + (s * kRows + R0) * 2, sRS + s * kRows + R0,
+                detect_epilogue<SPLIT>(A, Ap, acc[q][s], rsm, aw + q, bb, x, xin, lane, h, Y0, tile, col,
+                                SPLIT ? nullptr : xin_rows + (q * kVYW + s) * kWave, sIY + (s * kRows + R0) * 2,
+                                sRS + s * kRows + R0,
                                 P, xlo[q], xhi[q], VBX, REC);
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -1931,10 +1947,12 @@ void launch_stack_shape(const StackArgs& a, bool detect, bool staged, dim3 grid,
 }
 
 hipError_t launch_stack(const StackArgs& a, bool detect, bool staged, int shape, hipStream_t s) {
-    const long long groups = (long long)a.tiles_x * a.tiles_y * a.nvbx * a.nvby;
+    const long long groups = (long long)a.tiles_x * a.tiles_y * shape_items_per_tile(shape) * a.nvbx * a.nvby;
     const dim3 grid((unsigned)groups);
-    static_assert(kNShapes == 2, "one instantiation per shape");
-    if (shape == 1)
+    static_assert(kNShapes == 3, "one instantiation per shape");
+    if (shape == 2)
+        launch_stack_shape<2>(a, detect, staged, grid, s);
+    else if (shape == 1)
         launch_stack_shape<1>(a, detect, staged, grid, s);
     else
         launch_stack_shape<0>(a, detect, staged, grid, s);
@@ -1962,7 +1980,9 @@ hipError_t launch_rec_scale(int* ord, int nblk, long long ord_stride, int nrec, 
 
 hipError_t launch_stack_batch(const BatchArgs& b, int groups, int shape, hipStream_t s) {
     if (groups <= 0) return hipSuccess;
-    if (shape == 1)
+    if (shape == 2)
+        hipLaunchKernelGGL(k_stack_batch<2>, dim3((unsigned)groups), dim3(shape_waves(2) * kWave), 0, s, b);
+    else if (shape == 1)
         hipLaunchKernelGGL(k_stack_batch<1>, dim3((unsigned)groups), dim3(shape_waves(1) * kWave), 0, s, b);
     else
         hipLaunchKernelGGL(k_stack_batch<0>, dim3((unsigned)groups), dim3(shape_waves(0) * kWave), 0, s, b);

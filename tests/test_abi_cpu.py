@@ -297,7 +297,8 @@ def test_batch_argument_errors(lib):
 def test_shape_argument_errors(lib):
     vbx, vby = ctypes.c_int(0), ctypes.c_int(0)
     nsh = lib.sst_shape_info(0, ctypes.byref(vbx), ctypes.byref(vby))
-    assert nsh >= 2 and (vbx.value, vby.value) == (6, 2)
+    assert nsh >= 3 and (vbx.value, vby.value) == (6, 2)
+    assert lib.sst_shape_info(2, ctypes.byref(vbx), ctypes.byref(vby)) == nsh and (vbx.value, vby.value) == (12, 2)
     assert lib.sst_shape_info(nsh, None, None) == B.SST_E_ARG
     assert lib.sst_shape_info(-1, None, None) == B.SST_E_ARG
     t = np.arange(4, dtype=np.float64)

@@ -268,6 +268,40 @@ def test_random_cases(sst):
     assert marg <= 0.05 * listed + 20
 
 
+def test_random_cases_split_items(sst):
+    """The shape whose work items are one row half of a tile (12 x 2
+    velocities per block; both boundary rows of an item lie outside it):
+    seeded random problems against the oracle, with tile rows that end
+    inside the frame, exact rounding ties and low thresholds that put
+    candidates on the row-half borders."""
+    rng = np.random.default_rng(2025)
+    marg = listed = 0
+    for case in range(14):
+        n, h, w = int(rng.integers(2, 40)), int(rng.integers(1, 130)), int(rng.integers(1, 200))
+        nvx, nvy = int(rng.integers(1, 30)), int(rng.integers(1, 9))
+        vmax = float(rng.choice([0.3, 2.0, 6.0]))
+        f = synth.small_case(1700 + case, n, h, w, nvx, nvy, vmax=vmax, sky=float(rng.choice([0.0, 10.0])),
+                             sigma=2.0, ties=bool(case % 2))
+        thr = float(rng.choice([-50.0, 1.0, 2.5]))
+        cmin = int(rng.choice([0, max(1, n // 2)]))
+        kmax = int(rng.choice([1, 5, 64]))
+        plan = sst.sst_plan_detect(n, h, w, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax, shape=2)
+        _say(f"case {case}: {f.name} vmax {vmax} thr {thr} cmin {cmin} kmax {kmax} "
+             f"({'staged' if plan.staged else 'direct'})")
+        cand, count = plan.run(_dev(f.frames))
+        torch.cuda.synchronize()
+        got = sst.candidates_to_numpy(cand)
+        cnt = count.cpu().numpy()
+        ref = oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax, keep_maps=True)
+        bmax = float(np.abs(oracle.frame_stats(f.frames)[0]).max())
+        for k in range(nvx * nvy):
+            marg += compare_velocity(got[k], int(cnt[k]), ref[k], n, bmax, thr, ref["c_min"], kmax, w)
+            listed += min(int(ref[k]["count"]), kmax)
+        plan.close()
+    _say(f"  {marg} marginal decisions, {listed} listed entries over 14 cases")
+    assert marg <= 0.05 * listed + 20
+
+
 def test_detect_many_candidates_truncation_and_merge(sst):
     """A threshold far below the noise makes almost every local maximum a
     candidate: tiles hold more candidates than they keep (kt), and each

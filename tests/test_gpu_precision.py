@@ -151,7 +151,7 @@ def half_search(sst):
     sst.sst_set_half_search(prev)
 
 
-@pytest.mark.parametrize("shape,keep", [(0, 0), (1, 0), (0, 2)])
+@pytest.mark.parametrize("shape,keep", [(0, 0), (1, 0), (2, 0), (0, 2)])
 def test_half_search_random_cases(sst, shape, keep, half_search):
     """The search on IEEE-half samples (staged plans read the 16-bit copy,
     scale each sample in a mixed-precision fma, subtract the backgrounds
