@@ -40,7 +40,7 @@ EXPORTS = ("sst_shift_table", "sst_workspace_bytes", "sst_quantize", "sst_median
            "sst_plan_destroy", "sst_batch_workspace_bytes", "sst_batch_create", "sst_batch_run", "sst_batch_destroy",
            "sst_shape_info", "sst_workspace_bytes_shape", "sst_plan_detect_shape", "sst_plan_info",
            "sst_profile_begin", "sst_profile_end", "sst_last_error", "sst_version", "sst_detect_noalloc",
-           "sst_noalloc_scratch_bytes", "sst_set_half_search", "sst_set_slot_keep")
+           "sst_noalloc_scratch_bytes", "sst_set_half_search", "sst_set_slot_keep", "sst_set_stack_shape")
 
 
 class SstError(RuntimeError):
@@ -121,6 +121,8 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.sst_set_slot_keep.restype = _i
     lib.sst_set_half_search.argtypes = [_i]
     lib.sst_set_half_search.restype = _i
+    lib.sst_set_stack_shape.argtypes = [_i]
+    lib.sst_set_stack_shape.restype = _i
     lib.sst_profile_end.argtypes = [_p, _p]
     lib.sst_profile_end.restype = _i
     lib.sst_last_error.argtypes = []
@@ -537,6 +539,15 @@ def sst_set_half_search(on: bool) -> bool:
     """Search IEEE-half frames on their 16-bit samples (True) or on a
     float32 copy (False, the default); returns the previous setting."""
     return bool(load().sst_set_half_search(1 if on else 0))
+
+
+def sst_set_stack_shape(shape: int) -> int:
+    """Work-item shape of sst_stack (-1: automatic); returns the previous
+    setting.  Every shape writes the same stacks."""
+    rc = int(load().sst_set_stack_shape(int(shape)))
+    if rc < -1:
+        _check(rc)
+    return rc
 
 
 def sst_set_slot_keep(kt: int) -> int:

@@ -309,18 +309,25 @@ int make_plan_shape(int op, int n, int h, int w, const double* t, double t_ref, 
 }
 
 constexpr int kShapeAuto = -1;
+std::atomic<int> g_stack_shape{kShapeAuto};  // sst_set_stack_shape
 
-// make_plan_shape with the velocity-block shape given, or (kShapeAuto) the
-// first shape whose window holds the grid's shift spread (the direct path
-// with the first shape if none does).
+// make_plan_shape with the work-item shape given, or (kShapeAuto) the first
+// shape in order of preference whose window holds the grid's shift spread
+// (the direct path with the first if none does).  Plain stacks prefer
+// shape 2, whose plain-stack kernel fits four workgroups per CU (its
+// registers allow it; the search's epilogue does not), searches shape 0.
 int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
               const double* vy, int nvy, int k_max, Plan& p, int shape = kShapeAuto) {
+    if (shape == kShapeAuto && op == SST_OP_STACK) shape = g_stack_shape.load();
     if (shape != kShapeAuto) return make_plan_shape(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p, shape);
-    int rc = make_plan_shape(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p, 0);
+    static_assert(kNShapes == 3, "an order of preference per operation");
+    static const int kOrderStack[kNShapes] = {2, 0, 1}, kOrderDetect[kNShapes] = {0, 1, 2};
+    const int* order = op == SST_OP_STACK ? kOrderStack : kOrderDetect;
+    int rc = make_plan_shape(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p, order[0]);
     if (rc || p.staged || (op != SST_OP_STACK && op != SST_OP_DETECT)) return rc;
-    for (int sh = 1; sh < kNShapes; ++sh) {
+    for (int j = 1; j < kNShapes; ++j) {
         Plan q;
-        if (make_plan_shape(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, q, sh) == SST_OK && q.staged) {
+        if (make_plan_shape(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, q, order[j]) == SST_OK && q.staged) {
             p = std::move(q);
             break;
         }
@@ -1062,6 +1069,13 @@ int sst_batch_run(const sst_batch* batch, const void* const* frames, const int* 
 void sst_batch_destroy(sst_batch* batch) { delete batch; }
 
 int sst_set_half_search(int on) { return g_half_search.exchange(on ? 1 : 0); }
+
+int sst_set_stack_shape(int shape) {
+    g_err.clear();
+    if (shape < kShapeAuto || shape >= kNShapes)
+        return fail(SST_E_ARG, "work-item shape %d: need -1..%d", shape, kNShapes - 1);
+    return g_stack_shape.exchange(shape);
+}
 
 int sst_set_slot_keep(int kt) { return g_keep.exchange(kt > 0 ? kt : 0); }
 

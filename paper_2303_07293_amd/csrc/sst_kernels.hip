@@ -498,6 +498,37 @@ __device__ __forceinline__ void add_frame(const T* base, const int (&col)[kVPW],
     }
 }
 
+// add_frame with one read in flight at a time: fewer registers (the plain
+// stack of shape 2, at four waves per SIMD)
+template <int C, int CW, typename T>
+__device__ __forceinline__ void add_frame1(const T* base, const int (&col)[kVPW], int go0, int go1, float sc,
+                                           float (&acc)[kVPW][kVYW][kRowsW]) {
+    using K = Case<C>;
+    T va[6], vb[6];
+    if constexpr (K::shared) {
+        constexpr int G = K::gs;
+#pragma unroll
+        for (int q = 0; q < kVPW; ++q) {
+            read_groups<G, CW>(base + col[q], va);
+            add_rows<K::f0>(va, sc, acc[q][0]);
+            add_rows<K::f1>(va, sc, acc[q][1]);
+            hold<G>(va);
+        }
+    } else {
+        const T* b0 = base + go0 * CW;
+        const T* b1 = base + go1 * CW;
+#pragma unroll
+        for (int q = 0; q < kVPW; ++q) {
+            read_groups<K::g0, CW>(b0 + col[q], va);
+            add_rows<K::f0>(va, sc, acc[q][0]);
+            hold<K::g0>(va);
+            read_groups<K::g1, CW>(b1 + col[q], vb);
+            add_rows<K::f1>(vb, sc, acc[q][1]);
+            hold<K::g1>(vb);
+        }
+    }
+}
+
 // This wave's share of one frame's staging: its loads j < nst (instruction
 // wave + NW j of the frame), each 64 lanes x 16 bytes from the padded frame
 // at byte offsets voff[j] + soff into buf + 64 (wave + NW j) chunks.
@@ -956,7 +987,10 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             stage(k + NBUF - 1, slo, shi, swoff);
             if (busy) {
                 const T* base = reinterpret_cast<const T*>(lds + (k % NBUF) * BUFF) + (SPLIT ? 0 : 4 * h * CW) + lane;
-                add_frame<C, CW>(base, ccol, cgg & 0xFFFF, cgg >> 16, csc, acc);
+                if constexpr (!DETECT && SH == 2)
+                    add_frame1<C, CW>(base, ccol, cgg & 0xFFFF, cgg >> 16, csc, acc);
+                else
+                    add_frame<C, CW>(base, ccol, cgg & 0xFFFF, cgg >> 16, csc, acc);
             }
             // next records, loaded after the frame's LDS reads have been
             // used (scalar loads share their wait counter with LDS reads and
@@ -1296,8 +1330,10 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     }
 }
 
+// (the plain stack of shape 2 fits the registers of four waves per SIMD,
+// which lets four workgroups share a CU)
 template <bool DETECT, bool STAGED, int SH, bool HALF>
-__global__ __launch_bounds__(shape_waves(SH) * kWave) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(shape_waves(SH) * kWave) __attribute__((amdgpu_waves_per_eu(!DETECT && SH == 2 ? 4 : 3)))
 void k_stack(const StackArgs A) {
     __shared__ __attribute__((aligned(16))) float lds[Lds<SH>::total];
     stack_item<DETECT, STAGED, SH, HALF>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(),

@@ -294,6 +294,18 @@ def test_batch_argument_errors(lib):
     lib.sst_batch_destroy(None)
 
 
+def test_stack_shape_switch(lib):
+    prev = lib.sst_set_stack_shape(0)
+    try:
+        assert prev == -1
+        assert lib.sst_set_stack_shape(2) == 0
+        assert lib.sst_set_stack_shape(-2) == B.SST_E_ARG
+        assert lib.sst_set_stack_shape(3) == B.SST_E_ARG
+        assert lib.sst_set_stack_shape(-1) == 2
+    finally:
+        lib.sst_set_stack_shape(-1)
+
+
 def test_shape_argument_errors(lib):
     vbx, vby = ctypes.c_int(0), ctypes.c_int(0)
     nsh = lib.sst_shape_info(0, ctypes.byref(vbx), ctypes.byref(vby))

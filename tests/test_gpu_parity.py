@@ -114,9 +114,18 @@ def test_stack_small_cases(sst, seed, n, h, w, nvx, nvy, vmax):
     _check_stack(sst, f, bg=rng.normal(20.0, 2.0, size=n), mode="mean")
 
 
+@pytest.fixture(params=[-1, 0, 1])
+def stack_shape(sst, request):
+    """sst_stack on the automatic work-item shape (shape 2 where staged), and
+    forced to the whole-tile shapes"""
+    prev = sst.sst_set_stack_shape(request.param)
+    yield request.param
+    sst.sst_set_stack_shape(prev)
+
+
 @pytest.mark.parametrize("w", [200, 130, 128])
 @pytest.mark.parametrize("mode", ["sum", "mean"])
-def test_stack_store_forms(sst, w, mode):
+def test_stack_store_forms(sst, w, mode, stack_shape):
     """The plain stack's two store forms give the same stacks: tiles inside
     the frame's columns with 16-byte aligned outputs and a row length that is
     a multiple of four store four columns per lane (through LDS), the others
@@ -126,7 +135,7 @@ def test_stack_store_forms(sst, w, mode):
     one checked against the oracle by the other stack tests, and here the
     first velocities are checked against it too."""
     f = synth.small_case(77 + w, 9, 70, w, 7, 3, vmax=3.0)
-    _say(f"case {f.name} {mode}")
+    _say(f"case {f.name} {mode} stack shape {stack_shape}")
     m = sst.SST_MEAN if mode == "mean" else sst.SST_SUM
     fr = _dev(f.frames)
     nvx, nvy = len(f.vx), len(f.vy)
