@@ -438,6 +438,8 @@ def main():
     ap.add_argument("--cpu-velocities", type=int, default=8,
                     help="oracle sample: velocities per host core (a few seconds per core at the full field; "
                          "0: skip)")
+    ap.add_argument("--half-search", action="store_true",
+                    help="with --storage f16: search the 16-bit samples themselves (sst_set_half_search)")
     ap.add_argument("--no-extras", action="store_true",
                     help="full workload: skip the 16-bit storage and plain-stack measurements")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -478,6 +480,11 @@ def main():
         frames, scale, _ = sst.sst_quantize(frames, torch.bfloat16 if args.storage == "bf16" else torch.float16,
                                             center=True)
         torch.cuda.synchronize()
+    if args.half_search:
+        if args.storage != "f16":
+            print("--half-search needs --storage f16", file=sys.stderr)
+            sys.exit(2)
+        sst.sst_set_half_search(True)
     n, h, w = f.frames.shape
     nk = len(f.vx) * len(f.vy)
     dt, kern_ms_step, launches, cands = time_detect(torch, sst, f, frames, scale, args.steps, args.warmup)
@@ -489,7 +496,8 @@ def main():
         "metric": "frame*pixel*velocity updates/s", "value": value, "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f.name, "storage": args.storage, "frames": n, "height": h, "width": w, "velocities": nk,
+        "config": {"workload": f.name, "storage": args.storage + ("-searched-16bit" if args.half_search else ""),
+                   "frames": n, "height": h, "width": w, "velocities": nk,
                    "threshold": f.threshold, "k_max": f.k_max, "candidates_last_step": cands},
         "roofline": roofline(updates, kern_ms_step, launches, traffic),
     }
