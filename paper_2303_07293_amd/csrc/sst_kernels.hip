@@ -664,14 +664,17 @@ __device__ __forceinline__ float sn_direct(KArgs A, const double* P, int a, int 
 // Peak test and candidate output for one (tile, velocity, row half) whose
 // column sums are parked in LDS: col[r * 64 + lane] = S' of column row r.
 // fl marks the rows (1 .. kColRows - 2) that pass threshold and coverage;
-// bit r of omask marks column row r (0 or kColRows - 1) as outside the
-// work item (the next tile's row, or for an item of one row half also the
-// other half's).  The (tile, velocity, row half) writes its count and kept
-// entries to slot.
+// orow is the column row outside the tile (0 or kColRows - 1); for an item
+// of one row half (SPLIT) both rows 0 and kColRows - 1 lie outside it.  The
+// (tile, velocity, row half) writes its count and kept entries to slot.
+template <bool SPLIT>
 __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* RSr, const double* P,
                                                     int xlo, int xhi, int a, int b, long long slot,
                                                     LFloat* col, unsigned fl, int lane, int x, int Yc,
-                                                    unsigned omask, int vbx, int rec) {
+                                                    int orow, int vbx, int rec) {
+    auto outside_row = [&](int r) __attribute__((always_inline)) {
+        return SPLIT ? (r == 0 || r == kColRows - 1) : r == orow;
+    };
     SnCtx c;
     c.IYr = IYr;
     c.RSr = RSr;
@@ -686,7 +689,7 @@ __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* 
     // -infinity for now.
     auto sn_col = [&](int r) __attribute__((always_inline)) {
         int cv;
-        return ((omask >> r) & 1u) ? -INFINITY : sn_row(c, col[r * kWave + lane], r, cv);
+        return outside_row(r) ? -INFINITY : sn_row(c, col[r * kWave + lane], r, cv);
     };
     // the left and right neighbours' values by whole-wave DPP shifts (lane 0
     // and lane 63 have none: -infinity)
@@ -721,7 +724,7 @@ __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* 
     }
     // pixels next to the tile's border: test the outside neighbours
     // (own rows next to an outside row)
-    const unsigned erows = ((omask & 1u) ? 2u : 0u) | (((omask >> (kColRows - 1)) & 1u) << (kColRows - 2));
+    const unsigned erows = SPLIT ? (2u | (1u << (kColRows - 2))) : (1u << (orow == 0 ? 1 : kColRows - 2));
     unsigned todo = cm & ((lane == 0 || lane == kWave - 1) ? kEmitRows : erows);
 #pragma unroll 1
     while (todo != 0) {
@@ -733,7 +736,7 @@ __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* 
 #pragma unroll 1
         for (int k = 0; k < 9 && ok; ++k) {
             const int dy = k / 3 - 1, dx = k % 3 - 1;
-            const bool outside = lane + dx < 0 || lane + dx >= kWave || ((omask >> (r + dy)) & 1u);
+            const bool outside = lane + dx < 0 || lane + dx >= kWave || outside_row(r + dy);
             if (k == 4 || !outside) continue;
             const float sq = sn_direct(A, P, a, b, x + dx, Yc + r + dy, vbx, rec);
             const bool earlier = dy < 0 || (dy == 0 && dx < 0);
@@ -845,9 +848,8 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, co
 #pragma unroll
     for (int r = 0; r < kRowsW; ++r) own[r * kWave + lane] = acc[r];
     if constexpr (!SPLIT) col[(h ? 0 : kColRows - 1) * kWave + lane] = xrow[lane];
-    const unsigned omask = SPLIT ? (1u << (kColRows - 1)) | 1u : (h ? (1u << (kColRows - 1)) : 1u);
-    candidates_from_column(Ap, (LInt*)IYr, (LFloat*)RSr, P, xlo, xhi, a, b, slot, (LFloat*)col, fl, lane, x,
-                           Y0 + kRowsW * h - 1, omask, vbx, rec);
+    candidates_from_column<SPLIT>(Ap, (LInt*)IYr, (LFloat*)RSr, P, xlo, xhi, a, b, slot, (LFloat*)col, fl, lane, x,
+                                  Y0 + kRowsW * h - 1, h ? kColRows - 1 : 0, vbx, rec);
 }
 
 template <int V>
