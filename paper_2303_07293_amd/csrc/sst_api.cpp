@@ -313,16 +313,17 @@ std::atomic<int> g_stack_shape{kShapeAuto};  // sst_set_stack_shape
 
 // make_plan_shape with the work-item shape given, or (kShapeAuto) the first
 // shape in order of preference whose window holds the grid's shift spread
-// (the direct path with the first if none does).  Plain stacks prefer
-// shape 2, whose plain-stack kernel fits four workgroups per CU (its
-// registers allow it; the search's epilogue does not), searches shape 0.
+// (the direct path with the first if none does).  Shape 2 comes first: its
+// plain-stack kernel fits four workgroups per CU, and its search waits at a
+// barrier every second frame (a tuner may still prefer shape 0 for
+// searches that list millions of candidates, whose border pixels shape 2
+// evaluates on their own twice as often).
 int make_plan(int op, int n, int h, int w, const double* t, double t_ref, const double* vx, int nvx,
               const double* vy, int nvy, int k_max, Plan& p, int shape = kShapeAuto) {
     if (shape == kShapeAuto && op == SST_OP_STACK) shape = g_stack_shape.load();
     if (shape != kShapeAuto) return make_plan_shape(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p, shape);
-    static_assert(kNShapes == 3, "an order of preference per operation");
-    static const int kOrderStack[kNShapes] = {2, 0, 1}, kOrderDetect[kNShapes] = {0, 1, 2};
-    const int* order = op == SST_OP_STACK ? kOrderStack : kOrderDetect;
+    static_assert(kNShapes == 3, "an order of preference over every shape");
+    static const int order[kNShapes] = {2, 0, 1};
     int rc = make_plan_shape(op, n, h, w, t, t_ref, vx, nvx, vy, nvy, k_max, p, order[0]);
     if (rc || p.staged || (op != SST_OP_STACK && op != SST_OP_DETECT)) return rc;
     for (int j = 1; j < kNShapes; ++j) {

@@ -66,6 +66,10 @@ constexpr int kRG = 10;  // row groups (40 rows) of the staged window of a whole
 __host__ __device__ constexpr int shape_rg(int sh) { return shape_split(sh) ? 6 : kRG; }
 __host__ __device__ constexpr int shape_cw_max(int sh) { return sh == 0 ? 89 : (sh == 1 ? 144 : 112); }
 __host__ __device__ constexpr int shape_nbuf(int sh) { return sh == 1 ? 2 : 3; }
+// Staging buffers of a kernel: the search of shape 2 keeps four (and waits
+// at a barrier every second frame); its plain stack keeps three, so that
+// four of its workgroups share a CU's LDS.
+__host__ __device__ constexpr int ring_bufs(int sh, bool detect) { return sh == 2 && detect ? 4 : shape_nbuf(sh); }
 // staging instructions (64 chunks each) of the largest window
 __host__ __device__ constexpr int shape_ni_max(int sh) {
     return (shape_rg(sh) * shape_cw_max(sh) + kWave - 1) / kWave;

@@ -866,11 +866,11 @@ __device__ __forceinline__ void for_cases(F& f, std::integer_sequence<int, Cs...
 // columns, exchanged boundary rows, coverage, normaliser and background
 // tables, variance prefix), whichever is larger, plus one int for the batch
 // kernel's work counter.
-template <int SH>
+template <int SH, bool DETECT>
 struct Lds {
     static constexpr int NW = shape_waves(SH);
     static constexpr int buf = shape_ni_max(SH) * kWave * 4;  // floats per staging buffer
-    static constexpr int stage = shape_nbuf(SH) * buf;
+    static constexpr int stage = ring_bufs(SH, DETECT) * buf;
     static constexpr int colf = NW * kColRows * kWave;
     static constexpr int xch = NW * kVPW * kVYW * kWave;
     static constexpr int iy = ((kVYW * kRows + 1) * 2 + 3) / 4 * 4;  // (areas stay 16-byte aligned)
@@ -884,17 +884,20 @@ struct Lds {
 
 // One work item of the stacking kernels: tile and velocity block number
 // `logical` of the problem A describes (Ap: where a callee reads A); lds is
-// the workgroup's LDS array (Lds<SH>::total floats).
+// the workgroup's LDS array (Lds<SH, DETECT>::total floats).
 template <bool DETECT, bool STAGED, int SH, bool HALF = false>
 __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int logical, float* lds) {
     static_assert(!HALF || (DETECT && STAGED), "16-bit samples: the staged search only");
     constexpr int NW = shape_waves(SH), VBX = shape_vbx(SH);
     constexpr int CW = HALF ? shape_cw_half(SH) : shape_cw_max(SH);  // window columns
     constexpr int CB = HALF ? 8 : 16;  // bytes of four rows of one column
-    constexpr int NBUF = shape_nbuf(SH), REC = shape_rec_ints(SH);
+    // the search of shape 2 waits at a barrier every second frame (PAIR)
+    constexpr bool PAIR = SH == 2 && DETECT;
+    constexpr int NBUF = ring_bufs(SH, DETECT), REC = shape_rec_ints(SH);
+    static_assert(!PAIR || NBUF == 4, "two frames in flight while two are added");
     constexpr int NI = HALF ? shape_ni_half(SH) : shape_ni_max(SH);
     constexpr int BUFF = NI * kWave * 4;      // floats per staging buffer
-    static_assert(BUFF <= Lds<SH>::buf, "buffers inside the ring");
+    static_assert(BUFF <= Lds<SH, DETECT>::buf, "buffers inside the ring");
     constexpr int NSTX = (NI + NW - 1) / NW;  // most staging loads per wave and frame
     using T = typename std::conditional<HALF, u2, f4>::type;
     static_assert(NI >= NW && NSTX * (NBUF - 2 > 0 ? NBUF - 2 : 1) < 16, "every wave stages; vmcnt field");
@@ -958,14 +961,17 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             stage_window<NW, NSTX>(fr, fbytes, voff, nst, (HALF ? woff >> 1 : woff) + toff,
                                    lds + (k % NBUF) * BUFF, wave);
         };
-        // the first NBUF - 1 frames
+        // the first NBUF - 1 frames (PAIR: the first two)
+        constexpr int NPRO = PAIR ? 2 : NBUF - 1;
 #pragma unroll
-        for (int k = 0; k < NBUF - 1; ++k) {
+        for (int k = 0; k < NPRO; ++k) {
             const int lo = rec[k * REC], hi = rec[k * REC + 1], woff = rec[k * REC + 2];
             stage(k, lo, hi, woff);
         }
-        // this wave's loads of frame 0 have landed
-        if (nst == NSTX)
+        // this wave's loads of frame 0 (PAIR: of frames 0 and 1) have landed
+        if constexpr (PAIR)
+            wait_loads<0>();
+        else if (nst == NSTX)
             wait_loads<NSTX * (NBUF - 2)>();
         else
             wait_loads<(NSTX - 1) * (NBUF - 2)>();
@@ -974,9 +980,11 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         // (rc), read one frame ahead (scalar loads, first used after the
         // frame's LDS reads); the block's list has copies of its last record
         // past its end
-        CInt* rs = rec + (NBUF - 1) * REC;
+        CInt* rs = rec + NPRO * REC;
         CInt* rc = rec;
         int slo = rs[0], shi = rs[1], swoff = rs[2];
+        // (PAIR: the record of the second frame an even frame stages)
+        int s1lo = PAIR ? rs[REC] : 0, s1hi = PAIR ? rs[REC + 1] : 0, s1woff = PAIR ? rs[REC + 2] : 0;
         int cgg = rc[3];
         float csc = HALF ? __int_as_float(rc[kRecScale]) : 1.f;
         int ccol[kVPW];
@@ -985,8 +993,18 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         int k = 0;
         auto frame = [&](auto cc) __attribute__((always_inline)) {
             constexpr int C = decltype(cc)::value;
-            // frame k + NBUF - 1 into the buffer frame k - 1 used
-            stage(k + NBUF - 1, slo, shi, swoff);
+            // frame k + NBUF - 1 into the buffer frame k - 1 used (PAIR:
+            // each even frame stages frames k + 2 and k + 3 into the buffers
+            // of frames k - 2 and k - 1, which every wave finished before
+            // the barrier that ended frame k - 1)
+            if constexpr (PAIR) {
+                if ((k & 1) == 0) {
+                    stage(k + 2, slo, shi, swoff);
+                    stage(k + 3, s1lo, s1hi, s1woff);
+                }
+            } else {
+                stage(k + NBUF - 1, slo, shi, swoff);
+            }
             if (busy) {
                 const T* base = reinterpret_cast<const T*>(lds + (k % NBUF) * BUFF) + (SPLIT ? 0 : 4 * h * CW) + lane;
                 if constexpr (!DETECT && SH == 2)
@@ -999,24 +1017,43 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             // return out of order: issued earlier, they would turn the
             // partial waits on LDS reads into full ones)
             __builtin_amdgcn_sched_barrier(0);
-            rs += REC;
             rc += REC;
-            const int nlo = rs[0], nhi = rs[1], nwoff = rs[2];
             const int ngg = rc[3];
             const float nsc = HALF ? __int_as_float(rc[kRecScale]) : 1.f;
             int ncol[kVPW];
 #pragma unroll
             for (int q = 0; q < kVPW; ++q) ncol[q] = rc[kRecCol + kVPW * xg + q];
-            // this wave's loads of frame k + 1 have landed; after the
-            // barrier, everyone's have
-            if (nst == NSTX)
-                wait_loads<NSTX * (NBUF - 2)>();
-            else
-                wait_loads<(NSTX - 1) * (NBUF - 2)>();
-            barrier_no_fence();
-            slo = nlo;
-            shi = nhi;
-            swoff = nwoff;
+            if constexpr (PAIR) {
+                if (k & 1) {
+                    // records of the two frames the next frame stages; this
+                    // wave's loads of frames k + 1 and k + 2 have landed, and
+                    // after the barrier everyone's have
+                    rs += 2 * REC;
+                    const int nlo = rs[0], nhi = rs[1], nwoff = rs[2];
+                    const int n1lo = rs[REC], n1hi = rs[REC + 1], n1woff = rs[REC + 2];
+                    wait_loads<0>();
+                    barrier_no_fence();
+                    slo = nlo;
+                    shi = nhi;
+                    swoff = nwoff;
+                    s1lo = n1lo;
+                    s1hi = n1hi;
+                    s1woff = n1woff;
+                }
+            } else {
+                rs += REC;
+                const int nlo = rs[0], nhi = rs[1], nwoff = rs[2];
+                // this wave's loads of frame k + 1 have landed; after the
+                // barrier, everyone's have
+                if (nst == NSTX)
+                    wait_loads<NSTX * (NBUF - 2)>();
+                else
+                    wait_loads<(NSTX - 1) * (NBUF - 2)>();
+                barrier_no_fence();
+                slo = nlo;
+                shi = nhi;
+                swoff = nwoff;
+            }
             cgg = ngg;
             csc = nsc;
 #pragma unroll
@@ -1069,7 +1106,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     // (when it fits) and each lane's x intervals.  (sIY and sRS have one row
     // before tile row 0 of the first velocity row, so that a column starting
     // at tile row -1 has a valid base.)
-    using L = Lds<SH>;
+    using L = Lds<SH, DETECT>;
     float* const colarea = lds;
     float* const xch = lds + L::colf;
     int* const sIYa = reinterpret_cast<int*>(xch + L::xch);
@@ -1337,7 +1374,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
 template <bool DETECT, bool STAGED, int SH, bool HALF>
 __global__ __launch_bounds__(shape_waves(SH) * kWave) __attribute__((amdgpu_waves_per_eu(!DETECT && SH == 2 ? 4 : 3)))
 void k_stack(const StackArgs A) {
-    __shared__ __attribute__((aligned(16))) float lds[Lds<SH>::total];
+    __shared__ __attribute__((aligned(16))) float lds[Lds<SH, DETECT>::total];
     stack_item<DETECT, STAGED, SH, HALF>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(),
                                          xcd_remap(blockIdx.x, gridDim.x), lds);
 }
@@ -1352,8 +1389,8 @@ void k_stack_batch(const BatchArgs B) {
     // the table is read-only during the launch: read it through the constant
     // address space, so that the (uniform) loads are scalar
     typedef const __attribute__((address_space(4))) StackArgs CArgs;
-    __shared__ __attribute__((aligned(16))) float lds[Lds<SH>::total];
-    int* const s_item = reinterpret_cast<int*>(lds + Lds<SH>::total - 4);
+    __shared__ __attribute__((aligned(16))) float lds[Lds<SH, true>::total];
+    int* const s_item = reinterpret_cast<int*>(lds + Lds<SH, true>::total - 4);
     const int q0 = blockIdx.x % kBatchQueues;
     // the workgroup's own queue first, then (for the tail of the launch)
     // the other queues in turn; every queue ends, so every workgroup exits

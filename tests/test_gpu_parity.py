@@ -255,11 +255,10 @@ def test_random_cases(sst):
         shape = int(rng.integers(0, 2))
         _say(f"case {case}: {f.name} vmax {vmax} thr {thr} cmin {cmin} kmax {kmax} shape {shape}")
         fr = _dev(f.frames)
-        if shape == 0:
-            cand, count = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax)
-        else:
-            plan = sst.sst_plan_detect(n, h, w, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax, shape=1)
-            cand, count = plan.run(fr)
+        # (the whole-tile shapes; the automatic choice and shape 2 are
+        # covered by the other tests and by the row-half random cases)
+        plan = sst.sst_plan_detect(n, h, w, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax, shape=shape)
+        cand, count = plan.run(fr)
         torch.cuda.synchronize()
         got = sst.candidates_to_numpy(cand)
         cnt = count.cpu().numpy()
