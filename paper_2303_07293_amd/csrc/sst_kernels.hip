@@ -909,15 +909,16 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nvb = A.nvbx * A.nvby;
-    const int titem = logical / nvb;
-    const int vb = logical - titem * nvb;
-    const int tile = SPLIT ? titem >> 1 : titem;
+    // (SPLIT: the two row halves of a (tile, block) are consecutive items)
+    const int titem = SPLIT ? logical >> 1 : logical / nvb;
+    const int vb = SPLIT ? titem % nvb : logical - titem * nvb;
+    const int tile = SPLIT ? titem / nvb : titem;
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
     const int bxi = vb % A.nvbx, byi = A.vby0 + vb / A.nvbx;
     const int a0 = bxi * VBX;
     const int b0 = byi * kVYW;  // the pair's first y velocity
     const int xg = SPLIT ? wave : wave >> 1;  // which kVPW-group of the block's x velocities
-    const int h = SPLIT ? (titem & 1) : (wave & 1);  // row half
+    const int h = SPLIT ? (logical & 1) : (wave & 1);  // row half
     const int aw = a0 + kVPW * xg;  // this wave's first x velocity
     const int X0 = tx * kTileW;
     const int Y0 = ty * kRows;
