@@ -31,18 +31,19 @@ constexpr int kRowsW = kRows / 2;  // rows per wave
 constexpr int kVPW = 3;  // x velocities per wave
 constexpr int kVYW = 2;  // y velocities per block (one pair)
 // Work-item shapes (chosen per plan).  Workgroups of 4 waves, three per CU
-// (one waiting at its per-frame barrier leaves the SIMDs to the other two;
-// workgroups of 6 or 12 waves with windows this size get a CU to
-// themselves and lose that).  Shapes 0 and 1: a work item is a whole tile
-// and a block of 6 x velocities (waves: 2 row halves x 2 groups of 3 x
-// velocities); they differ in the width of the staged window: shape 0 holds
-// an x shift spread of 25 px over the block in three ring buffers, shape 1
-// one of 80 px in two (for grids whose shifts grow faster per velocity
-// step).  Shape 2 splits the tile: a work item is one row half of a tile and
-// a block of 12 x velocities (waves: 4 groups of 3), so each staged window
-// is 6 row groups high and serves twice as many velocities per row, at the
-// cost of a wider x spread (up to 48 px over the block).  All fit the LDS
-// that three workgroups may share.
+// (one waiting at its barrier leaves the SIMDs to the other two; workgroups
+// of 6 or 12 waves with windows this size get a CU to themselves and lose
+// that).  Shapes 0 and 1: a work item is a whole tile and a block of 6 x
+// velocities (waves: 2 row halves x 2 groups of 3 x velocities); they
+// differ in the width of the staged window: shape 0 holds an x shift spread
+// of 25 px over the block in three ring buffers, shape 1 one of 80 px in two
+// (for grids whose shifts grow faster per velocity step).  Shape 2 (tried
+// first) splits the tile: a work item is one row half of a tile and a block
+// of 12 x velocities (waves: 4 groups of 3), so each staged window is 6 row
+// groups high and serves twice as many velocities per row, at the cost of a
+// wider x spread (up to 48 px over the block); its search keeps four ring
+// buffers and its plain stack runs four workgroups per CU (ring_bufs).  All
+// fit the LDS that three workgroups may share.
 constexpr int kNShapes = 3;
 constexpr int kMaxWaves = 12;  // waves per CU at the kernels' register use
 __host__ __device__ constexpr int shape_waves(int) { return 4; }
