@@ -373,11 +373,12 @@ int sst_set_half_search(int on);
 /* Work-item shape of sst_stack and its sst_workspace_bytes (process-wide;
  * -1, the default, chooses automatically: shape 2 when its window holds the
  * grid's shifts, whose plain-stack kernel runs four workgroups per compute
- * unit, else shape 0, else 1; returns the previous setting, or SST_E_ARG for
- * a shape outside -1 .. number of shapes - 1).  Every shape writes the same
+ * unit, else shape 0, else 1).  Writes the previous setting to *previous
+ * (if not NULL) and returns SST_OK, or SST_E_ARG (setting unchanged) for a
+ * shape outside -1 .. number of shapes - 1.  Every shape writes the same
  * stacks; the setting exists to test and time each.  Set it before sizing
  * the workspace of the calls it applies to. */
-int sst_set_stack_shape(int shape);
+int sst_set_stack_shape(int shape, int* previous);
 
 /* Candidate entries each (tile, row half, velocity) of a detect launch
  * keeps, at most (process-wide, for plans and calls prepared from now on;

@@ -121,7 +121,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.sst_set_slot_keep.restype = _i
     lib.sst_set_half_search.argtypes = [_i]
     lib.sst_set_half_search.restype = _i
-    lib.sst_set_stack_shape.argtypes = [_i]
+    lib.sst_set_stack_shape.argtypes = [_i, _p]
     lib.sst_set_stack_shape.restype = _i
     lib.sst_profile_end.argtypes = [_p, _p]
     lib.sst_profile_end.restype = _i
@@ -544,10 +544,9 @@ def sst_set_half_search(on: bool) -> bool:
 def sst_set_stack_shape(shape: int) -> int:
     """Work-item shape of sst_stack (-1: automatic); returns the previous
     setting.  Every shape writes the same stacks."""
-    rc = int(load().sst_set_stack_shape(int(shape)))
-    if rc < -1:
-        _check(rc)
-    return rc
+    prev = ctypes.c_int(0)
+    _check(load().sst_set_stack_shape(int(shape), ctypes.byref(prev)))
+    return prev.value
 
 
 def sst_set_slot_keep(kt: int) -> int:

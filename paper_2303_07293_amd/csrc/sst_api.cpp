@@ -1071,11 +1071,13 @@ void sst_batch_destroy(sst_batch* batch) { delete batch; }
 
 int sst_set_half_search(int on) { return g_half_search.exchange(on ? 1 : 0); }
 
-int sst_set_stack_shape(int shape) {
+int sst_set_stack_shape(int shape, int* previous) {
     g_err.clear();
     if (shape < kShapeAuto || shape >= kNShapes)
         return fail(SST_E_ARG, "work-item shape %d: need -1..%d", shape, kNShapes - 1);
-    return g_stack_shape.exchange(shape);
+    const int prev = g_stack_shape.exchange(shape);
+    if (previous) *previous = prev;
+    return SST_OK;
 }
 
 int sst_set_slot_keep(int kt) { return g_keep.exchange(kt > 0 ? kt : 0); }

@@ -295,15 +295,16 @@ def test_batch_argument_errors(lib):
 
 
 def test_stack_shape_switch(lib):
-    prev = lib.sst_set_stack_shape(0)
+    prev = ctypes.c_int(99)
     try:
-        assert prev == -1
-        assert lib.sst_set_stack_shape(2) == 0
-        assert lib.sst_set_stack_shape(-2) == B.SST_E_ARG
-        assert lib.sst_set_stack_shape(3) == B.SST_E_ARG
-        assert lib.sst_set_stack_shape(-1) == 2
+        assert lib.sst_set_stack_shape(0, ctypes.byref(prev)) == B.SST_OK and prev.value == -1
+        assert lib.sst_set_stack_shape(2, ctypes.byref(prev)) == B.SST_OK and prev.value == 0
+        # invalid shapes leave the setting unchanged
+        assert lib.sst_set_stack_shape(-2, ctypes.byref(prev)) == B.SST_E_ARG
+        assert lib.sst_set_stack_shape(3, None) == B.SST_E_ARG
+        assert lib.sst_set_stack_shape(-1, ctypes.byref(prev)) == B.SST_OK and prev.value == 2
     finally:
-        lib.sst_set_stack_shape(-1)
+        lib.sst_set_stack_shape(-1, None)
 
 
 def test_shape_argument_errors(lib):
