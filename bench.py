@@ -178,7 +178,7 @@ def refine_bench(torch, sst, args):
     call.  Reported: candidates x steps per second and bilinear samples per
     second (21 evaluations per candidate, each 64 x 33 x 33 samples)."""
     import synth
-    f = synth.config2()
+    f = synth.full_field()
     fr = torch.from_numpy(f.frames).to("cuda:0")
     cand, count = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max)
     g = sst.candidates_to_numpy(cand)
@@ -224,9 +224,9 @@ def batch_bench(torch, sst, args):
     import synth
     dev = torch.device("cuda:0")
     if args.workload == "batch":
-        specs = synth.config3()
+        specs = synth.uneven_batch()
     else:
-        base = synth.config1(noise=False)
+        base = synth.tiny_field(noise=False)
         specs = [synth.FieldSpec(f"tiny{k}", synth.SEED_BASE + 400 + k, base.n, base.h, len(base.vx), base.t, 3)
                  for k in range(64)]
     fields = []
@@ -376,7 +376,7 @@ def stack_bench(torch, sst, args):
     as updates/s, and as compulsory HBM bytes (frames read once, stacks
     written once) per step time against the HBM peak."""
     import synth
-    f = synth.config_diagnostic() if args.workload == "stack" else synth.config2()
+    f = synth.diagnostic_field() if args.workload == "stack" else synth.full_field()
     r = time_plain_stack(torch, sst, f, args.steps, args.warmup)
     print(json.dumps({
         "metric": "frame*pixel*velocity updates/s", "value": r["updates_per_s"], "unit": "updates/s", "n_gpus": 1,
@@ -471,7 +471,7 @@ def main():
         stack_bench(torch, sst, args)
         return
 
-    f = synth.config2() if args.workload == "full" else synth.config1()
+    f = synth.full_field() if args.workload == "full" else synth.tiny_field()
     dev = torch.device("cuda:0")
     frames = torch.from_numpy(f.frames).to(dev)
     scale = None
@@ -527,7 +527,7 @@ def main():
         torch.cuda.empty_cache()
         out["storage_16bit_vs_f32"] = ratio
         ps = max(2, args.steps // 5)
-        out["plain_stack_hbm"] = [time_plain_stack(torch, sst, synth.config_diagnostic(), ps, 1),
+        out["plain_stack_hbm"] = [time_plain_stack(torch, sst, synth.diagnostic_field(), ps, 1),
                                   time_plain_stack(torch, sst, f, ps, 1)]
     if args.cpu_velocities > 0:
         out["cpu_baseline"] = cpu_baseline(f, args.cpu_velocities)

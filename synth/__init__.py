@@ -12,10 +12,10 @@ from .fields import (  # noqa: F401
     Field,
     FieldSpec,
     Mover,
-    config1,
-    config2,
-    config3,
-    config_diagnostic,
+    tiny_field,
+    full_field,
+    uneven_batch,
+    diagnostic_field,
     pure_noise,
     render_movers,
     small_case,

@@ -101,7 +101,7 @@ def _frames(rng, t, t_ref, h, w, sky, sigma, movers, noise=True) -> np.ndarray:
     return out
 
 
-def config1(noise: bool = True) -> Field:
+def tiny_field(noise: bool = True) -> Field:
     """Tiny plain case: 32 frames of 128x128, background 0, N(0,1) noise,
     timestamps evenly spaced over 1 h (t_i = i/31), 3 movers of peak 1.5 sigma
     and FWHM 2.5 px at integer velocities within +-10 px/h whose whole track
@@ -123,7 +123,7 @@ def config1(noise: bool = True) -> Field:
                  threshold=5.0, min_coverage=16, k_max=64, movers=movers, sky=0.0, sigma=1.0)
 
 
-def config2_times(rng) -> np.ndarray:
+def full_field_times(rng) -> np.ndarray:
     """71 evenly spaced slots over [0, 4] h with 7 dropped at random (a 10%
     gap fraction), leaving 64 frames."""
     slots = np.arange(71, dtype=np.float64) * (4.0 / 70.0)
@@ -132,13 +132,13 @@ def config2_times(rng) -> np.ndarray:
     return slots[keep]
 
 
-def config2(n_movers: int = 50, h: int = 1024, w: int = 1024) -> Field:
+def full_field(n_movers: int = 50, h: int = 1024, w: int = 1024) -> Field:
     """Full field: 64 frames of 1024x1024 (a 2048^2 CCD binned 2x2), sky 100
     with Gaussian noise sigma=10, 4 h with 10% gaps, 50 movers with
     log-uniform peak 0.2-3 sigma and velocities uniform in +-40 px/h,
     81x81 grid at 1 px/h, S/N threshold 5, top-64 per velocity."""
     rng = np.random.default_rng(SEED_BASE + 2)
-    t = config2_times(rng)
+    t = full_field_times(rng)
     t_ref = float(t[0])
     movers = []
     for _ in range(n_movers):
@@ -182,10 +182,10 @@ class FieldSpec:
                      min_coverage=(self.n + 1) // 2, k_max=64, movers=movers, sky=100.0, sigma=10.0)
 
 
-def config3(n_fields: int = 16) -> List[FieldSpec]:
+def uneven_batch(n_fields: int = 16) -> List[FieldSpec]:
     """Batch of uneven fields: frame counts uniform in 24..160, sides drawn
     from {512, 768, 1024, 2048}, velocity grids n x n with n odd in 41..121
-    (1 px/h), timestamps over 4 h with 10% of the slots dropped, config 2's
+    (1 px/h), timestamps over 4 h with 10% of the slots dropped, the full field's
     noise and movers (50 per 1024^2, scaled by area)."""
     rng = np.random.default_rng(SEED_BASE + 3)
     out = []
@@ -203,10 +203,10 @@ def config3(n_fields: int = 16) -> List[FieldSpec]:
     return out
 
 
-def config_diagnostic(n_frames: int = 32) -> Field:
-    """Diagnostic shape for the stack's HBM roof: config 2's noise and grid
+def diagnostic_field(n_frames: int = 32) -> Field:
+    """Diagnostic shape for the stack's HBM roof: the full field's noise and grid
     with fewer frames (the materialised stack is HBM-bound only for small N)."""
-    f = config2()
+    f = full_field()
     idx = np.linspace(0, f.n - 1, n_frames).round().astype(int)
     idx = np.unique(idx)
     return Field(f"diagnostic {len(idx)}x{f.h}x{f.w} grid81x81", np.ascontiguousarray(f.frames[idx]),

@@ -73,10 +73,10 @@ def test_shift_table_bit_exact_vs_oracle(lib, case):
 
 
 def test_shift_table_bit_exact_on_configs(lib):
-    f1 = synth.config1(noise=False)
+    f1 = synth.tiny_field(noise=False)
     assert np.array_equal(sst.sst_shift_table(f1.t, f1.t_ref, f1.vx), oracle.shift_table(f1.t, f1.t_ref, f1.vx))
     rng = np.random.default_rng(synth.SEED_BASE + 2)
-    t2 = synth.fields.config2_times(rng)
+    t2 = synth.fields.full_field_times(rng)
     v2 = np.arange(-40, 41, dtype=np.float64)
     assert np.array_equal(sst.sst_shift_table(t2, t2[0], v2), oracle.shift_table(t2, t2[0], v2))
 
@@ -180,7 +180,7 @@ def test_workspace_bytes(lib):
     # the full field (candidate slots of every velocity, one launch) takes a
     # few percent of one MI355X's 288 GB
     rng = np.random.default_rng(synth.SEED_BASE + 2)
-    t2 = synth.fields.config2_times(rng)
+    t2 = synth.fields.full_field_times(rng)
     g = np.arange(-40, 41, dtype=np.float64)
     nb = sst.sst_workspace_bytes(sst.SST_OP_DETECT, 64, 1024, 1024, t2, t2[0], g, g, 64)
     assert nb < 10 << 30

@@ -91,7 +91,7 @@ def _check_stack(sst, f, bg=None, mode="sum", velocities=None):
 
 
 def test_stack_tiny_config_sum_and_mean(sst):
-    f = synth.config1()
+    f = synth.tiny_field()
     _say(f"case {f.name} sum")
     w1 = _check_stack(sst, f)
     _say(f"case {f.name} mean")
@@ -191,7 +191,7 @@ def _check_detect(sst, f, thr, cmin, kmax, velocities=None, max_marginal=0):
 
 
 def test_detect_tiny_config(sst):
-    f = synth.config1()
+    f = synth.tiny_field()
     _say(f"case {f.name}")
     got, cnt = _check_detect(sst, f, f.threshold, f.min_coverage, f.k_max)
     # every injected mover is detected at its true velocity bin, within 1 px
@@ -422,7 +422,7 @@ def test_detect_full_field_sampled(sst):
     """The full field (64 x 1024^2, 81^2 velocities) in the benchmark's launch
     configuration; sampled velocities checked against the oracle, including
     the bins nearest the brightest movers."""
-    f = synth.config2()
+    f = synth.full_field()
     _say(f"case {f.name}")
     ks = [0, 80, 3280, 6480, 6560, 41 * 81 + 7]
     movers = sorted(f.movers, key=lambda m: -m.amp)[:6]
@@ -434,6 +434,6 @@ def test_detect_full_field_sampled(sst):
 
 @pytest.mark.slow
 def test_stack_full_field_sampled(sst):
-    f = synth.config2()
+    f = synth.full_field()
     _say(f"case {f.name} stack")
     _check_stack(sst, f, velocities=[0, 3280, 6560, 100])

@@ -216,7 +216,7 @@ def test_precision_full_field(sst, kind, center):
     |dS'| <= 2 u sum_i max|F_i - o_i| plus float32 summation terms."""
     direct = kind == "f16-direct"  # the search on the 16-bit samples themselves
     kind = "f16" if direct else kind
-    f = synth.config2()
+    f = synth.full_field()
     _say(f"case {f.name} {kind} center={center} search on 16-bit samples: {direct}")
     fr = torch.from_numpy(f.frames).to("cuda:0")
     q, s, o = sst.sst_quantize(fr, _tdtype(kind), center=center)

@@ -162,7 +162,7 @@ def test_refine_full_field_candidates(sst):
     to 0.5 px and 0.5 px/h, 33x33 cutouts over 64 frames, 20 ascent steps;
     gradients checked against float32 central differences (h = 1e-3) on the
     GPU and against the float64 oracle gradient."""
-    f = synth.config2()
+    f = synth.full_field()
     fr = torch.from_numpy(f.frames).to("cuda:0")
     cand, count = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max)
     g = sst.candidates_to_numpy(cand)

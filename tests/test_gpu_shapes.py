@@ -38,7 +38,7 @@ CASES = [(50, 10, 70, 130, 7, 5, 3.0), (51, 16, 64, 64, 6, 4, 2.0), (52, 8, 33, 
 
 
 def _fields():
-    out = [synth.config1()]
+    out = [synth.tiny_field()]
     for seed, n, h, w, nvx, nvy, vmax in CASES:
         out.append(synth.small_case(seed, n, h, w, nvx, nvy, vmax=vmax, sky=50.0, sigma=5.0))
     return out
@@ -69,7 +69,7 @@ def test_every_shape_matches_default(sst):
 
 
 def test_tuner_picks_a_shape_and_remembers_it(sst):
-    f = synth.config1()
+    f = synth.tiny_field()
     fr = torch.from_numpy(f.frames).to("cuda:0")
     plan = sst.tune_plan(fr, f.t, f.t_ref, f.vx, f.vy, f.threshold, f.min_coverage, f.k_max)
     sh = sst.tuned_shape(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, f.k_max)

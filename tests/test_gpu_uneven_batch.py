@@ -92,7 +92,7 @@ def _check_lists(f, got, cnt, ks, max_marginal):
 
 @pytest.mark.timeout(600)
 def test_batch_uneven_fields_against_oracle(sst):
-    specs = [synth.config3()[9], synth.config3()[2], _long_spec()]
+    specs = [synth.uneven_batch()[9], synth.uneven_batch()[2], _long_spec()]
     fields, frames, plans = [], [], []
     for sp in specs:
         _say(f"case batch field {sp.name}: generating")

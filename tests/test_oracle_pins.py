@@ -70,7 +70,7 @@ def test_shift_table_matches_exact_rationals_on_config_timestamps():
             assert d1[i, a] == _exact_round(exact)
     # full-field config: slots m*(4/70) with 7 dropped, v in -40..40
     rng = np.random.default_rng(synth.SEED_BASE + 2)
-    t2 = synth.fields.config2_times(rng)
+    t2 = synth.fields.full_field_times(rng)
     slots = np.rint(t2 / (4.0 / 70.0)).astype(int)
     v2 = np.arange(-40, 41, dtype=np.float64)
     d2 = so.shift_table(t2, t2[0], v2)
@@ -342,7 +342,7 @@ def test_tiny_config_movers_recovered():
     +-2 bins and +-3 px clears the 5 sigma threshold.  Over a 1 h baseline
     neighbouring 1 px/h bins differ by under a pixel, so with noise the
     maximum may sit one bin away; exact recovery is pinned noise-free above."""
-    f = synth.config1()
+    f = synth.tiny_field()
     dx = so.shift_table(f.t, f.t_ref, f.vx)
     dy = so.shift_table(f.t, f.t_ref, f.vy)
     b, s2 = so.frame_stats(f.frames)

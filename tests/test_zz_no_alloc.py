@@ -43,7 +43,7 @@ def _run_both(sst, f, thr, kmax):
 
 
 def test_noalloc_matches_detect_twice_then_smaller(sst):
-    big = synth.config1()
+    big = synth.tiny_field()
     _say(f"case no-alloc {big.name}")
     n1 = _run_both(sst, big, big.threshold, big.k_max)
     small = synth.small_case(7, 9, 70, 90, 5, 4, vmax=3.0, sky=20.0, sigma=3.0)
@@ -54,7 +54,7 @@ def test_noalloc_matches_detect_twice_then_smaller(sst):
 
 
 def test_noalloc_rejects_problems_larger_than_the_scratch(sst):
-    f = synth.config2(n_movers=0, h=64, w=64)  # the grid and frames only set the size below
+    f = synth.full_field(n_movers=0, h=64, w=64)  # the grid and frames only set the size below
     n, h, w = 64, 1024, 1024
     need = sst.sst_workspace_bytes(sst.SST_OP_DETECT, n, h, w, f.t, f.t_ref, f.vx, f.vy, 64)
     assert need > sst.sst_noalloc_scratch_bytes()
