@@ -276,6 +276,34 @@ def test_random_cases(sst):
     assert marg <= 0.05 * listed + 20
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_split_items_few_frames(sst, n):
+    """The search of the row-half shape stages frames in pairs and waits at a
+    barrier after every second frame: one to five frames (an odd count ends
+    on an unpaired frame) against the oracle, and against the whole-tile
+    shape bit for bit."""
+    f = synth.small_case(1800 + n, n, 45, 140, 13, 4, vmax=2.0, sky=10.0, sigma=2.0)
+    _say(f"case {f.name}")
+    fr = _dev(f.frames)
+    out = []
+    for shape in (2, 0):
+        plan = sst.sst_plan_detect(n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, 1.0, 0, 8, shape=shape)
+        _say(f"  shape {shape}: {'staged' if plan.staged else 'direct'}")
+        c, k = plan.run(fr)
+        torch.cuda.synchronize()
+        out.append((c.clone(), k.clone()))
+        plan.close()
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    got = sst.candidates_to_numpy(out[0][0])
+    cnt = out[0][1].cpu().numpy()
+    ref = oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, 1.0, 0, 8, keep_maps=True)
+    bmax = float(np.abs(oracle.frame_stats(f.frames)[0]).max())
+    marg = sum(compare_velocity(got[k], int(cnt[k]), ref[k], n, bmax, 1.0, ref["c_min"], 8, f.w)
+               for k in range(len(f.vx) * len(f.vy)))
+    _say(f"  {int(cnt.sum())} candidates, {marg} marginal decisions")
+    assert marg <= 4
+
+
 def test_random_cases_split_items(sst):
     """The shape whose work items are one row half of a tile (12 x 2
     velocities per block; both boundary rows of an item lie outside it):
