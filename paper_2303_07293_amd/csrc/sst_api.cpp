@@ -124,6 +124,7 @@ struct Plan {
     // workspace offsets (bytes)
     size_t o_geom = 0, o_tab = 0, o_part = 0, o_b = 0, o_s2 = 0, o_P = 0, o_Pb = 0, o_b32 = 0, o_sdev = 0;
     size_t o_flag = 0, flag_bytes = 0;  // list of velocities to recompute (detect)
+    size_t o_redo = 0;  // work items left to the second pass (detect, shape 2): counts and marks
     size_t o_ix = 0, o_iy = 0, o_pad = 0, o_tcount = 0, o_ent = 0, o_qpart = 0, o_dt = 0, total = 0;
 };
 
@@ -303,6 +304,11 @@ int make_plan_shape(int op, int n, int h, int w, const double* t, double t_ref, 
         const size_t nk = (size_t)p.rows_per_chunk * p.vby * nvx;
         p.o_tcount = take(cur, nk * p.nslot * sizeof(int32_t));
         p.o_ent = take(cur, nk * p.nslot * p.kt * sizeof(Entry));
+        if (shape_split(shape)) {
+            const size_t items = (size_t)p.tiles_x * p.tiles_y * shape_items_per_tile(shape) * p.nvbx * p.rows_per_chunk;
+            // counts, marks, the list and a count per kCompactChunk marks
+            p.o_redo = take(cur, (kRedoHead + 2 * items + items / kCompactChunk + 1) * sizeof(int32_t));
+        }
     }
     p.total = cur;
     return SST_OK;
@@ -577,6 +583,7 @@ StackArgs detect_args(const Plan& p, void* ws, float threshold, int min_coverage
     a.ent = at<Entry>(ws, p.o_ent);
     a.vby0 = r0;
     a.nvby = rows;
+    a.redo = p.o_redo ? at<int>(ws, p.o_redo) : nullptr;
     return a;
 }
 

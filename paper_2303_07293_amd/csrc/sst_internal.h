@@ -67,10 +67,9 @@ constexpr int kRG = 10;  // row groups (40 rows) of the staged window of a whole
 __host__ __device__ constexpr int shape_rg(int sh) { return shape_split(sh) ? 6 : kRG; }
 __host__ __device__ constexpr int shape_cw_max(int sh) { return sh == 0 ? 89 : (sh == 1 ? 144 : 112); }
 __host__ __device__ constexpr int shape_nbuf(int sh) { return sh == 1 ? 2 : 3; }
-// Staging buffers of a kernel: the search of shape 2 keeps four (and waits
-// at a barrier every second frame); its plain stack keeps three, so that
-// four of its workgroups share a CU's LDS.
-__host__ __device__ constexpr int ring_bufs(int sh, bool detect) { return sh == 2 && detect ? 4 : shape_nbuf(sh); }
+// Staging buffers of a kernel: four for a kernel that waits at a barrier
+// every second frame (pair), else the shape's ring.
+__host__ __device__ constexpr int ring_bufs(int sh, bool pair) { return pair ? 4 : shape_nbuf(sh); }
 // staging instructions (64 chunks each) of the largest window
 __host__ __device__ constexpr int shape_ni_max(int sh) {
     return (shape_rg(sh) * shape_cw_max(sh) + kWave - 1) / kWave;
@@ -182,7 +181,30 @@ struct StackArgs {
     int nslot;   // slots per velocity: one per (tile, row half), 2 * tiles_x * tiles_y
     int32_t* tcount;  // [velocities of this launch][nslot] candidates found (before keeping kt)
     Entry* ent;       // [velocities of this launch][nslot][kt]
+    // (searches of shape 2 in two passes) [kRedoFound]: items the first
+    // pass ran that found a pixel above threshold; [kRedoSkipping]: set once
+    // the first pass lists every further item without running it;
+    // [kRedoTotal]: items listed; [kRedoHead + item]: 1 if the second pass
+    // runs the work item; [kRedoHead + G + i]: the i-th such item in order
+    // (G: work items of the launch); [kRedoHead + 2 G + c]: marks set among
+    // the kCompactChunk items from c kCompactChunk; NULL: one pass
+    int* redo;
 };
+
+// Two-pass search: once more than one in kRedoSkip of the items dealt so
+// far (workgroups are dealt in order) have found a pixel above threshold,
+// from the kRedoWarm-th item on, the first pass lists every further item
+// for the second without running it. The second pass cuts the list into
+// kRedoRuns runs, one per XCD.
+constexpr int kRedoRuns = 8;
+constexpr int kRedoSkip = 8;
+constexpr int kRedoWarm = 2048;
+constexpr int kRedoFound = 0;
+constexpr int kRedoSkipping = 1;
+constexpr int kRedoTotal = 2;
+constexpr int kRedoHead = 32;
+constexpr int kCompactThreads = 1024;  // threads of the workgroups that list the marked items
+constexpr int kCompactChunk = 4 * kCompactThreads;  // marks per such workgroup
 
 // One round of a batch of detect problems, run by one persistent launch:
 // the arguments of each problem's share of the round, the first global work

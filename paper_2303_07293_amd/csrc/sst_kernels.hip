@@ -796,12 +796,12 @@ __device__ __noinline__ void candidates_from_column(KArgs A, LInt* IYr, LFloat* 
 // row of the same velocity (NULL for an item of one row half, whose both
 // boundary rows lie outside it); IYr and RSr start at column row 0 (tile
 // row R0).
-template <bool SPLIT>
+template <bool SPLIT, bool DEFER>
 __device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, const float (&acc)[kRowsW],
                                                 const float (&rsm)[kRowsW], int a, int b, int x, bool xin, int lane,
                                                 int h, int Y0, int tile, float* col, const float* xrow,
                                                 const int* IYr, const float* RSr, const double* P, int xlo, int xhi,
-                                                int vbx, int rec) {
+                                                int vbx, int rec, int* sflag) {
     const long long kc = (long long)(b - A.vby0 * kVYW) * A.nvx + a;
     const long long slot = kc * A.nslot + 2 * tile + h;
     SnCtx c;
@@ -828,11 +828,32 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, co
     if (__ballot(!c.xfull && xin) != 0) {
         // lanes near the frame's x edges: combine both coverage intervals
         if (!c.xfull && xin) {
+            if constexpr (DEFER) {
+                // (few registers: each row's multiplier, as sn_row forms
+                // the S/N, through this wave's column area, then the rows
+                // tested as for inside lanes; NaN where the row cannot hold
+                // a candidate)
+#pragma unroll 1
+                for (int r = 0; r < kRowsW; ++r) {
+                    int lo, hi;
+                    const int cov = coverage(xlo, xhi, IYr[2 * (r + 1)], IYr[2 * (r + 1) + 1], lo, hi);
+                    float m = __builtin_nanf("");
+                    if (cov > 0 && cov >= A.cmin) {
+                        const double V = P[hi + 1] - P[lo];
+                        m = V > 0.0 ? rsqrtf((float)V) : 0.f;
+                    }
+                    col[r * kWave + lane] = m;
+                }
 #pragma unroll
-            for (int r = 0; r < kRowsW; ++r) {
-                int cov;
-                const float s = sn_row(c, acc[r], r + 1, cov);
-                if (cov >= A.cmin && s > A.thr) fl |= 1u << r;
+                for (int r = 0; r < kRowsW; ++r)
+                    if (acc[r] * col[r * kWave + lane] > A.thr) fl |= 1u << r;
+            } else {
+#pragma unroll
+                for (int r = 0; r < kRowsW; ++r) {
+                    int cov;
+                    const float s = sn_row(c, acc[r], r + 1, cov);
+                    if (cov >= A.cmin && s > A.thr) fl |= 1u << r;
+                }
             }
         }
     }
@@ -841,15 +862,21 @@ __device__ __forceinline__ void detect_epilogue(const StackArgs& A, KArgs Ap, co
         if (lane == 0) A.tcount[slot] = 0;
         return;
     }
-    // Rare path (some pixel of this wave's column block clears the
-    // threshold): park the sums in this wave's LDS slot and work from there
-    // with runtime row loops, which keeps this code's register use small.
-    float* own = col + kWave;
+    if constexpr (DEFER) {
+        // the second pass finds this slot's candidates
+        *sflag = 1;
+    } else {
+        // Rare path (some pixel of this wave's column block clears the
+        // threshold): park the sums in this wave's LDS slot and work from
+        // there with runtime row loops, which keeps this code's register use
+        // small.
+        float* own = col + kWave;
 #pragma unroll
-    for (int r = 0; r < kRowsW; ++r) own[r * kWave + lane] = acc[r];
-    if constexpr (!SPLIT) col[(h ? 0 : kColRows - 1) * kWave + lane] = xrow[lane];
-    candidates_from_column<SPLIT>(Ap, (LInt*)IYr, (LFloat*)RSr, P, xlo, xhi, a, b, slot, (LFloat*)col, fl, lane, x,
-                                  Y0 + kRowsW * h - 1, h ? kColRows - 1 : 0, vbx, rec);
+        for (int r = 0; r < kRowsW; ++r) own[r * kWave + lane] = acc[r];
+        if constexpr (!SPLIT) col[(h ? 0 : kColRows - 1) * kWave + lane] = xrow[lane];
+        candidates_from_column<SPLIT>(Ap, (LInt*)IYr, (LFloat*)RSr, P, xlo, xhi, a, b, slot, (LFloat*)col, fl, lane, x,
+                                      Y0 + kRowsW * h - 1, h ? kColRows - 1 : 0, vbx, rec);
+    }
 }
 
 template <int V>
@@ -866,11 +893,11 @@ __device__ __forceinline__ void for_cases(F& f, std::integer_sequence<int, Cs...
 // columns, exchanged boundary rows, coverage, normaliser and background
 // tables, variance prefix), whichever is larger, plus one int for the batch
 // kernel's work counter.
-template <int SH, bool DETECT>
+template <int SH, int NB>
 struct Lds {
     static constexpr int NW = shape_waves(SH);
     static constexpr int buf = shape_ni_max(SH) * kWave * 4;  // floats per staging buffer
-    static constexpr int stage = ring_bufs(SH, DETECT) * buf;
+    static constexpr int stage = NB * buf;
     static constexpr int colf = NW * kColRows * kWave;
     static constexpr int xch = NW * kVPW * kVYW * kWave;
     static constexpr int iy = ((kVYW * kRows + 1) * 2 + 3) / 4 * 4;  // (areas stay 16-byte aligned)
@@ -882,22 +909,38 @@ struct Lds {
     static constexpr int total = (stage > epi ? stage : epi) + 4;
 };
 
+// Staging buffers of the stacking kernels: the one-pass search of shape 2
+// waits at a barrier every second frame (four buffers); its first pass of
+// two (DEFER) and the plain stack keep the shape's ring and run four
+// workgroups per CU.
+__host__ __device__ constexpr bool item_pair(int sh, bool detect, bool defer) { return sh == 2 && detect && !defer; }
+__host__ __device__ constexpr int item_nbuf(int sh, bool detect, bool defer) {
+    return ring_bufs(sh, item_pair(sh, detect, defer));
+}
+__host__ __device__ constexpr int item_waves_per_eu(int sh, bool detect, bool defer) {
+    return sh == 2 && (!detect || defer) ? 4 : 3;
+}
+
 // One work item of the stacking kernels: tile and velocity block number
 // `logical` of the problem A describes (Ap: where a callee reads A); lds is
 // the workgroup's LDS array (Lds<SH, DETECT>::total floats).
-template <bool DETECT, bool STAGED, int SH, bool HALF = false>
+// DEFER (first pass of a two-pass search of shape 2): no candidate search;
+// an item with a pixel above threshold is listed in A.redo for the second
+// pass, which runs it again in full.
+template <bool DETECT, bool STAGED, int SH, bool HALF = false, bool DEFER = false>
 __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int logical, float* lds) {
+    static_assert(!DEFER || (DETECT && STAGED && !HALF && SH == 2), "two passes: the float32 search of shape 2");
     static_assert(!HALF || (DETECT && STAGED), "16-bit samples: the staged search only");
     constexpr int NW = shape_waves(SH), VBX = shape_vbx(SH);
     constexpr int CW = HALF ? shape_cw_half(SH) : shape_cw_max(SH);  // window columns
     constexpr int CB = HALF ? 8 : 16;  // bytes of four rows of one column
-    // the search of shape 2 waits at a barrier every second frame (PAIR)
-    constexpr bool PAIR = SH == 2 && DETECT;
-    constexpr int NBUF = ring_bufs(SH, DETECT), REC = shape_rec_ints(SH);
+    // the one-pass search of shape 2 waits at a barrier every second frame
+    constexpr bool PAIR = item_pair(SH, DETECT, DEFER);
+    constexpr int NBUF = item_nbuf(SH, DETECT, DEFER), REC = shape_rec_ints(SH);
     static_assert(!PAIR || NBUF == 4, "two frames in flight while two are added");
     constexpr int NI = HALF ? shape_ni_half(SH) : shape_ni_max(SH);
     constexpr int BUFF = NI * kWave * 4;      // floats per staging buffer
-    static_assert(BUFF <= Lds<SH, DETECT>::buf, "buffers inside the ring");
+    static_assert(BUFF <= Lds<SH, NBUF>::buf, "buffers inside the ring");
     constexpr int NSTX = (NI + NW - 1) / NW;  // most staging loads per wave and frame
     using T = typename std::conditional<HALF, u2, f4>::type;
     static_assert(NI >= NW && NSTX * (NBUF - 2 > 0 ? NBUF - 2 : 1) < 16, "every wave stages; vmcnt field");
@@ -925,6 +968,28 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     // waves whose velocities all lie past the grid (in a partial last block)
     // only help stage the frames
     const bool busy = aw < A.nvx && b0 < A.nvy;
+    // (DEFER) set by a wave whose rows hold a pixel above threshold; cleared
+    // before the first barrier, set after the frame loop
+    int* const s_redo = reinterpret_cast<int*>(lds + Lds<SH, NBUF>::total - 4);
+    if constexpr (DEFER) {
+        // once more than 1 / kRedoSkip of the items dealt so far have found a
+        // pixel above threshold, list this one at once: where most items
+        // hold such a pixel, the first pass would only add to the second
+        int* const s_skip = s_redo + 1;
+        if (tid == 0) {
+            *s_redo = 0;
+            int skip = 0;
+            if (blockIdx.x >= kRedoWarm) {
+                // set by the item that found the share too large
+                skip = __hip_atomic_load(A.redo + kRedoSkipping, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (skip) A.redo[kRedoHead + logical] = 1;
+            }
+            *s_skip = skip;
+        }
+        __syncthreads();
+        // the same value for every wave: the workgroup leaves as a whole
+        if (*s_skip) return;
+    }
     CInt* blk = (CInt*)(A.ord + (long long)(byi * A.nvbx + bxi) * A.ord_stride);
     CInt* rec = blk + kCountInts;  // record of the block's k-th frame at rec + k * REC
 
@@ -1008,7 +1073,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             }
             if (busy) {
                 const T* base = reinterpret_cast<const T*>(lds + (k % NBUF) * BUFF) + (SPLIT ? 0 : 4 * h * CW) + lane;
-                if constexpr (!DETECT && SH == 2)
+                if constexpr (item_waves_per_eu(SH, DETECT, DEFER) == 4)
                     add_frame1<C, CW>(base, ccol, cgg & 0xFFFF, cgg >> 16, csc, acc);
                 else
                     add_frame<C, CW>(base, ccol, cgg & 0xFFFF, cgg >> 16, csc, acc);
@@ -1107,7 +1172,7 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     // (when it fits) and each lane's x intervals.  (sIY and sRS have one row
     // before tile row 0 of the first velocity row, so that a column starting
     // at tile row -1 has a valid base.)
-    using L = Lds<SH, DETECT>;
+    using L = Lds<SH, NBUF>;
     float* const colarea = lds;
     float* const xch = lds + L::colf;
     int* const sIYa = reinterpret_cast<int*>(xch + L::xch);
@@ -1346,10 +1411,10 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
                     rsm[4 * k + 2] = t.z;
                     rsm[4 * k + 3] = t.w;
                 }
-                detect_epilogue<SPLIT>(A, Ap, acc[q][s], rsm, aw + q, bb, x, xin, lane, h, Y0, tile, col,
+                detect_epilogue<SPLIT, DEFER>(A, Ap, acc[q][s], rsm, aw + q, bb, x, xin, lane, h, Y0, tile, col,
                                 SPLIT ? nullptr : xin_rows + (q * kVYW + s) * kWave, sIY + (s * kRows + R0) * 2,
                                 sRS + s * kRows + R0,
-                                P, xlo[q], xhi[q], VBX, REC);
+                                P, xlo[q], xhi[q], VBX, REC, s_redo);
             }
             __builtin_amdgcn_sched_barrier(0);
         };
@@ -1367,17 +1432,121 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
             epi(sP);
         else
             epi(A.P);
+        if constexpr (DEFER) {
+            // list the item for the second pass if a wave found a pixel above
+            // threshold
+            __syncthreads();
+            if (tid == 0) {
+                const int found = *s_redo;
+                A.redo[kRedoHead + logical] = found;
+                if (found) {
+                    const int seen = atomicAdd(A.redo + kRedoFound, 1) + 1;
+                    if ((int)blockIdx.x >= kRedoWarm && seen * kRedoSkip > (int)blockIdx.x)
+                        __hip_atomic_store(A.redo + kRedoSkipping, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
     }
 }
 
-// (the plain stack of shape 2 fits the registers of four waves per SIMD,
-// which lets four workgroups share a CU)
-template <bool DETECT, bool STAGED, int SH, bool HALF>
-__global__ __launch_bounds__(shape_waves(SH) * kWave) __attribute__((amdgpu_waves_per_eu(!DETECT && SH == 2 ? 4 : 3)))
+// (the plain stack of shape 2 and the first pass of its two-pass search fit
+// the registers of four waves per SIMD, which lets four workgroups share a CU)
+template <bool DETECT, bool STAGED, int SH, bool HALF, bool DEFER = false>
+__global__ __launch_bounds__(shape_waves(SH) * kWave)
+__attribute__((amdgpu_waves_per_eu(item_waves_per_eu(SH, DETECT, DEFER))))
 void k_stack(const StackArgs A) {
-    __shared__ __attribute__((aligned(16))) float lds[Lds<SH, DETECT>::total];
-    stack_item<DETECT, STAGED, SH, HALF>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(),
-                                         xcd_remap(blockIdx.x, gridDim.x), lds);
+    __shared__ __attribute__((aligned(16))) float lds[Lds<SH, item_nbuf(SH, DETECT, DEFER)>::total];
+    stack_item<DETECT, STAGED, SH, HALF, DEFER>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(),
+                                                xcd_remap(blockIdx.x, gridDim.x), lds);
+}
+
+// Between the passes of a two-pass search: the G work items the first pass
+// marked, listed in increasing order. Workgroup c handles the kCompactChunk
+// marks from c kCompactChunk, four consecutive ones per thread: the first
+// kernel counts each chunk's marks, the second adds up the counts of the
+// chunks before its own and lists its items from there.
+__device__ __forceinline__ int compact_marks(const int* __restrict__ redo, int G, int i0, int m[4]) {
+    const int* mark = redo + kRedoHead;
+    if (i0 + 3 < G) {
+        // kRedoHead and i0 are multiples of four: an aligned 16-byte load
+        const int4 v = *reinterpret_cast<const int4*>(mark + i0);
+        m[0] = v.x;
+        m[1] = v.y;
+        m[2] = v.z;
+        m[3] = v.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m[k] = i0 + k < G ? mark[i0 + k] : 0;
+    }
+    return (m[0] != 0) + (m[1] != 0) + (m[2] != 0) + (m[3] != 0);
+}
+
+// inclusive sum over the workgroup's threads up to this one; *all: the sum
+// over all of them
+__device__ __forceinline__ int compact_scan(int c, int* wsum, int* all) {
+    const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+    int x = c;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wsum[wv] = x;
+    __syncthreads();
+    int before = 0, sum = 0;
+#pragma unroll
+    for (int k = 0; k < kCompactThreads / kWave; ++k) {
+        before += k < wv ? wsum[k] : 0;
+        sum += wsum[k];
+    }
+    __syncthreads();
+    *all = sum;
+    return before + x;
+}
+
+__global__ __launch_bounds__(kCompactThreads) void k_redo_count(int* __restrict__ redo, int G) {
+    __shared__ int wsum[kCompactThreads / kWave];
+    int m[4], all;
+    const int c = compact_marks(redo, G, blockIdx.x * kCompactChunk + 4 * threadIdx.x, m);
+    compact_scan(c, wsum, &all);
+    if (threadIdx.x == 0) redo[kRedoHead + 2 * G + blockIdx.x] = all;
+}
+
+__global__ __launch_bounds__(kCompactThreads) void k_redo_list(int* __restrict__ redo, int G) {
+    __shared__ int wsum[kCompactThreads / kWave];
+    const int* counts = redo + kRedoHead + 2 * G;
+    int base = 0, all;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kCompactThreads) base += counts[k];
+    compact_scan(base, wsum, &all);
+    base = all;
+    int m[4];
+    const int i0 = blockIdx.x * kCompactChunk + 4 * threadIdx.x;
+    const int c = compact_marks(redo, G, i0, m);
+    int off = base + compact_scan(c, wsum, &all) - c;
+    int* list = redo + kRedoHead + G;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (m[k]) list[off++] = i0 + k;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) redo[kRedoTotal] = base + all;
+}
+
+// Second pass of a two-pass search: the listed items, run in full
+// (candidates included). The list is cut into kRedoRuns equal runs, and the
+// workgroups dealt to XCD x (blockIdx.x % kRedoRuns) take run x in order, so
+// that items that lie close together run on one XCD, as in the first pass;
+// the grid is the first pass's rounded up to a multiple of kRedoRuns (every
+// run's workgroups exist), and workgroups past the runs exit at once.
+template <int SH>
+__global__ __launch_bounds__(shape_waves(SH) * kWave) __attribute__((amdgpu_waves_per_eu(3)))
+void k_stack_redo(const StackArgs A, int G) {
+    __shared__ __attribute__((aligned(16))) float lds[Lds<SH, item_nbuf(SH, true, false)>::total];
+    const int total = A.redo[kRedoTotal];
+    const int per = (total + kRedoRuns - 1) / kRedoRuns;
+    const int r = blockIdx.x / kRedoRuns;
+    const int j = (blockIdx.x % kRedoRuns) * per + r;
+    if (r >= per || j >= total) return;
+    const int logical = A.redo[kRedoHead + G + j];
+    stack_item<true, true, SH>(A, (KArgs)__builtin_amdgcn_kernarg_segment_ptr(), logical, lds);
 }
 
 // Persistent form for a batch of detect problems (all staged): each
@@ -1390,8 +1559,8 @@ void k_stack_batch(const BatchArgs B) {
     // the table is read-only during the launch: read it through the constant
     // address space, so that the (uniform) loads are scalar
     typedef const __attribute__((address_space(4))) StackArgs CArgs;
-    __shared__ __attribute__((aligned(16))) float lds[Lds<SH, true>::total];
-    int* const s_item = reinterpret_cast<int*>(lds + Lds<SH, true>::total - 4);
+    __shared__ __attribute__((aligned(16))) float lds[Lds<SH, item_nbuf(SH, true, false)>::total];
+    int* const s_item = reinterpret_cast<int*>(lds + Lds<SH, item_nbuf(SH, true, false)>::total - 4);
     const int q0 = blockIdx.x % kBatchQueues;
     // the workgroup's own queue first, then (for the tail of the launch)
     // the other queues in turn; every queue ends, so every workgroup exits
@@ -2007,6 +2176,20 @@ hipError_t launch_cov(const int* D, int ld, int n, int nv, int size, int* I, hip
 template <int SH>
 void launch_stack_shape(const StackArgs& a, bool detect, bool staged, dim3 grid, hipStream_t s) {
     const dim3 block(shape_waves(SH) * kWave);
+    if constexpr (SH == 2) {
+        if (detect && staged && !a.half && a.redo) {
+            // two passes: the search without candidates at four workgroups
+            // per CU, then in full the items it listed
+            hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(kAux), 0, s, a.redo, kRedoHead);
+            hipLaunchKernelGGL((k_stack<true, true, SH, false, true>), grid, block, 0, s, a);
+            const dim3 chunks((grid.x + kCompactChunk - 1) / kCompactChunk);
+            hipLaunchKernelGGL(k_redo_count, chunks, dim3(kCompactThreads), 0, s, a.redo, (int)grid.x);
+            hipLaunchKernelGGL(k_redo_list, chunks, dim3(kCompactThreads), 0, s, a.redo, (int)grid.x);
+            hipLaunchKernelGGL(k_stack_redo<SH>, dim3((grid.x + kRedoRuns - 1) / kRedoRuns * kRedoRuns), block, 0,
+                               s, a, (int)grid.x);
+            return;
+        }
+    }
     if (detect) {
         if (staged && a.half)
             hipLaunchKernelGGL((k_stack<true, true, SH, true>), grid, block, 0, s, a);

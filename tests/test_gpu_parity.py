@@ -304,6 +304,31 @@ def test_split_items_few_frames(sst, n):
     assert marg <= 4
 
 
+@pytest.mark.parametrize("thr", [1.0, 3.5, 6.0])
+def test_split_items_two_passes(sst, thr):
+    """The float32 search of the row-half shape runs in two passes: the
+    first lists the work items that hold a pixel above threshold and, once
+    more than one in eight of an XCD's items have found such a pixel, lists the rest
+    without running them; the second runs the listed items in full. On a
+    field of 5,760 work items (enough for the early listing to start), at a
+    threshold that lists nearly every item, one that lists part of them and
+    one that lists few: the lists and counts of the one-pass whole-tile shape,
+    bit for bit."""
+    f = synth.small_case(1900, 8, 384, 640, 30, 16, vmax=3.0, sky=10.0, sigma=2.0)
+    _say(f"case {f.name} thr {thr}")
+    fr = _dev(f.frames)
+    out = []
+    for shape in (2, 0):
+        plan = sst.sst_plan_detect(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, thr, 0, 16, shape=shape)
+        c, k = plan.run(fr)
+        torch.cuda.synchronize()
+        out.append((c.clone(), k.clone()))
+        plan.close()
+    _say(f"  {int(out[0][1].sum())} candidates")
+    assert torch.equal(out[0][1], out[1][1])
+    assert torch.equal(out[0][0], out[1][0])
+
+
 def test_random_cases_split_items(sst):
     """The shape whose work items are one row half of a tile (12 x 2
     velocities per block; both boundary rows of an item lie outside it):
