@@ -116,8 +116,10 @@ size_t sst_workspace_bytes(int op, int n, int h, int w, const double* t, double 
  * the block; shape 1: the same with a window for spreads up to 80 px (grids
  * whose shifts grow faster per velocity step); shape 2: row halves, 12 x 2
  * velocities, spreads up to 48 px (a lower window shared by more
- * velocities, a barrier every second frame in the search, four workgroups
- * per compute unit in the plain stack, and more border pixels evaluated on
+ * velocities, four workgroups per compute unit in the plain stack, a
+ * float32 search in two passes: every work item stacked at four workgroups
+ * per compute unit without the candidate code, then the items that hold a
+ * pixel above threshold again in full; and more border pixels evaluated on
  * their own).  Every shape gives the same lists and stacks.  The one-shot
  * calls, sst_workspace_bytes and sst_plan_detect take the first of shapes
  * 2, 0, 1 whose window holds the grid's shifts (shape 2, on the direct
