@@ -369,7 +369,7 @@ int sst_bin2x2(const float* frames, int n, int h, int w, float* out, void* strea
  * rules against the oracle on the dequantised frames.  It is off by default
  * because on gfx950 the mixed-precision FMA issues at under half the rate of
  * a float32 add, which costs more than the halved LDS traffic saves on the
- * full-field search (about 21 ms against 18 ms).  Not used by batches. */
+ * full-field search (about 20 ms against 16.4 ms).  Not used by batches. */
 int sst_set_half_search(int on);
 
 /* Work-item shape of sst_stack and its sst_workspace_bytes (process-wide;
@@ -381,6 +381,22 @@ int sst_set_half_search(int on);
  * stacks; the setting exists to test and time each.  Set it before sizing
  * the workspace of the calls it applies to. */
 int sst_set_stack_shape(int shape, int* previous);
+
+/* Two-pass search of shape 2 (process-wide).  A float32 search of shape 2
+ * runs in two passes: the first stacks every work item at four workgroups
+ * per compute unit and only marks the items that hold a pixel above
+ * threshold (once more than one in eight of the items dealt so far are
+ * marked, it marks the rest without running them); the second runs the
+ * marked items in full.  SST_TWO_PASS_AUTO (the default) does so for
+ * launches of at least 4096 work items, SST_TWO_PASS_NEVER never,
+ * SST_TWO_PASS_ALWAYS for every launch.  Writes the previous setting to
+ * *previous (if not NULL) and returns SST_OK, or SST_E_ARG (setting
+ * unchanged) for another mode.  Every mode gives the same lists; the
+ * setting exists to test and time each.  Batches run one pass. */
+#define SST_TWO_PASS_NEVER 0
+#define SST_TWO_PASS_AUTO 1
+#define SST_TWO_PASS_ALWAYS 2
+int sst_set_two_pass(int mode, int* previous);
 
 /* Candidate entries each (tile, row half, velocity) of a detect launch
  * keeps, at most (process-wide, for plans and calls prepared from now on;

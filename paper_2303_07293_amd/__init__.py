@@ -39,6 +39,7 @@ from .binding import (  # noqa: F401
     sst_set_half_search,
     sst_set_slot_keep,
     sst_set_stack_shape,
+    sst_set_two_pass,
     sst_shapes,
     sst_shift_table,
     sst_stack,

@@ -40,7 +40,8 @@ EXPORTS = ("sst_shift_table", "sst_workspace_bytes", "sst_quantize", "sst_median
            "sst_plan_destroy", "sst_batch_workspace_bytes", "sst_batch_create", "sst_batch_run", "sst_batch_destroy",
            "sst_shape_info", "sst_workspace_bytes_shape", "sst_plan_detect_shape", "sst_plan_info",
            "sst_profile_begin", "sst_profile_end", "sst_last_error", "sst_version", "sst_detect_noalloc",
-           "sst_noalloc_scratch_bytes", "sst_set_half_search", "sst_set_slot_keep", "sst_set_stack_shape")
+           "sst_noalloc_scratch_bytes", "sst_set_half_search", "sst_set_slot_keep", "sst_set_stack_shape",
+           "sst_set_two_pass")
 
 
 class SstError(RuntimeError):
@@ -123,6 +124,8 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.sst_set_half_search.restype = _i
     lib.sst_set_stack_shape.argtypes = [_i, _p]
     lib.sst_set_stack_shape.restype = _i
+    lib.sst_set_two_pass.argtypes = [_i, _p]
+    lib.sst_set_two_pass.restype = _i
     lib.sst_profile_end.argtypes = [_p, _p]
     lib.sst_profile_end.restype = _i
     lib.sst_last_error.argtypes = []
@@ -546,6 +549,18 @@ def sst_set_stack_shape(shape: int) -> int:
     setting.  Every shape writes the same stacks."""
     prev = ctypes.c_int(0)
     _check(load().sst_set_stack_shape(int(shape), ctypes.byref(prev)))
+    return prev.value
+
+
+SST_TWO_PASS_NEVER, SST_TWO_PASS_AUTO, SST_TWO_PASS_ALWAYS = 0, 1, 2
+
+
+def sst_set_two_pass(mode: int) -> int:
+    """Two-pass search of shape 2: SST_TWO_PASS_NEVER, _AUTO (the default:
+    launches of at least 4096 work items) or _ALWAYS; returns the previous
+    setting.  Every mode gives the same lists."""
+    prev = ctypes.c_int(0)
+    _check(load().sst_set_two_pass(int(mode), ctypes.byref(prev)))
     return prev.value
 
 

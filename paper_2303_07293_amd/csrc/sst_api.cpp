@@ -316,6 +316,7 @@ int make_plan_shape(int op, int n, int h, int w, const double* t, double t_ref, 
 
 constexpr int kShapeAuto = -1;
 std::atomic<int> g_stack_shape{kShapeAuto};  // sst_set_stack_shape
+std::atomic<int> g_two_pass{SST_TWO_PASS_AUTO};  // sst_set_two_pass
 
 // make_plan_shape with the work-item shape given, or (kShapeAuto) the first
 // shape in order of preference whose window holds the grid's shift spread
@@ -583,7 +584,10 @@ StackArgs detect_args(const Plan& p, void* ws, float threshold, int min_coverage
     a.ent = at<Entry>(ws, p.o_ent);
     a.vby0 = r0;
     a.nvby = rows;
-    a.redo = p.o_redo ? at<int>(ws, p.o_redo) : nullptr;
+    const long long items = (long long)p.tiles_x * p.tiles_y * shape_items_per_tile(p.shape) * p.nvbx * rows;
+    const int mode = g_two_pass.load();
+    const bool two = mode == SST_TWO_PASS_ALWAYS || (mode == SST_TWO_PASS_AUTO && items >= kRedoMinItems);
+    a.redo = p.o_redo && two ? at<int>(ws, p.o_redo) : nullptr;
     return a;
 }
 
@@ -1083,6 +1087,15 @@ int sst_set_stack_shape(int shape, int* previous) {
     if (shape < kShapeAuto || shape >= kNShapes)
         return fail(SST_E_ARG, "work-item shape %d: need -1..%d", shape, kNShapes - 1);
     const int prev = g_stack_shape.exchange(shape);
+    if (previous) *previous = prev;
+    return SST_OK;
+}
+
+int sst_set_two_pass(int mode, int* previous) {
+    g_err.clear();
+    if (mode < SST_TWO_PASS_NEVER || mode > SST_TWO_PASS_ALWAYS)
+        return fail(SST_E_ARG, "two-pass mode %d: need %d..%d", mode, SST_TWO_PASS_NEVER, SST_TWO_PASS_ALWAYS);
+    const int prev = g_two_pass.exchange(mode);
     if (previous) *previous = prev;
     return SST_OK;
 }

@@ -202,6 +202,9 @@ constexpr int kRedoWarm = 2048;
 constexpr int kRedoFound = 0;
 constexpr int kRedoSkipping = 1;
 constexpr int kRedoTotal = 2;
+// Launches of fewer work items search in one pass unless two are forced:
+// the extra launches cost more than the first pass saves on them.
+constexpr int kRedoMinItems = 4096;
 constexpr int kRedoHead = 32;
 constexpr int kCompactThreads = 1024;  // threads of the workgroups that list the marked items
 constexpr int kCompactChunk = 4 * kCompactThreads;  // marks per such workgroup

@@ -307,6 +307,22 @@ def test_stack_shape_switch(lib):
         lib.sst_set_stack_shape(-1, None)
 
 
+def test_two_pass_switch(lib):
+    prev = ctypes.c_int(99)
+    try:
+        assert lib.sst_set_two_pass(B.SST_TWO_PASS_ALWAYS, ctypes.byref(prev)) == B.SST_OK
+        assert prev.value == B.SST_TWO_PASS_AUTO
+        assert lib.sst_set_two_pass(B.SST_TWO_PASS_NEVER, ctypes.byref(prev)) == B.SST_OK
+        assert prev.value == B.SST_TWO_PASS_ALWAYS
+        # other modes leave the setting unchanged
+        assert lib.sst_set_two_pass(3, ctypes.byref(prev)) == B.SST_E_ARG
+        assert lib.sst_set_two_pass(-1, None) == B.SST_E_ARG
+        assert lib.sst_set_two_pass(B.SST_TWO_PASS_AUTO, ctypes.byref(prev)) == B.SST_OK
+        assert prev.value == B.SST_TWO_PASS_NEVER
+    finally:
+        lib.sst_set_two_pass(B.SST_TWO_PASS_AUTO, None)
+
+
 def test_shape_argument_errors(lib):
     vbx, vby = ctypes.c_int(0), ctypes.c_int(0)
     nsh = lib.sst_shape_info(0, ctypes.byref(vbx), ctypes.byref(vby))

@@ -6,6 +6,7 @@ must match exactly except for decisions the derivation marks as marginal;
 the tests also bound how many such decisions may occur.
 """
 
+import contextlib
 import sys
 
 import numpy as np
@@ -15,10 +16,21 @@ import oracle
 from oracle import sst_oracle as so
 import synth
 from parity import compare_velocity
+from paper_2303_07293_amd import binding as B
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+
+@contextlib.contextmanager
+def two_pass(mode):
+    """The two-pass mode of shape 2's search for the runs inside the block."""
+    prev = B.sst_set_two_pass(mode)
+    try:
+        yield
+    finally:
+        B.sst_set_two_pass(prev)
 
 
 def _need_gpu():
@@ -286,14 +298,17 @@ def test_split_items_few_frames(sst, n):
     _say(f"case {f.name}")
     fr = _dev(f.frames)
     out = []
-    for shape in (2, 0):
-        plan = sst.sst_plan_detect(n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, 1.0, 0, 8, shape=shape)
-        _say(f"  shape {shape}: {'staged' if plan.staged else 'direct'}")
-        c, k = plan.run(fr)
-        torch.cuda.synchronize()
+    # shape 2 in one pass and in two (forced: the problem is small), shape 0
+    for shape, mode in ((2, B.SST_TWO_PASS_NEVER), (2, B.SST_TWO_PASS_ALWAYS), (0, B.SST_TWO_PASS_AUTO)):
+        with two_pass(mode):
+            plan = sst.sst_plan_detect(n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, 1.0, 0, 8, shape=shape)
+            _say(f"  shape {shape} two-pass mode {mode}: {'staged' if plan.staged else 'direct'}")
+            c, k = plan.run(fr)
+            torch.cuda.synchronize()
         out.append((c.clone(), k.clone()))
         plan.close()
-    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    for o in out[1:]:
+        assert torch.equal(out[0][0], o[0]) and torch.equal(out[0][1], o[1])
     got = sst.candidates_to_numpy(out[0][0])
     cnt = out[0][1].cpu().numpy()
     ref = oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, 1.0, 0, 8, keep_maps=True)
@@ -318,23 +333,29 @@ def test_split_items_two_passes(sst, thr):
     _say(f"case {f.name} thr {thr}")
     fr = _dev(f.frames)
     out = []
-    for shape in (2, 0):
-        plan = sst.sst_plan_detect(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, thr, 0, 16, shape=shape)
-        c, k = plan.run(fr)
-        torch.cuda.synchronize()
+    # shape 2 (two passes by default at this size, forced, and one pass), shape 0
+    for shape, mode in ((2, B.SST_TWO_PASS_AUTO), (2, B.SST_TWO_PASS_ALWAYS), (2, B.SST_TWO_PASS_NEVER),
+                        (0, B.SST_TWO_PASS_AUTO)):
+        with two_pass(mode):
+            plan = sst.sst_plan_detect(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, thr, 0, 16, shape=shape)
+            c, k = plan.run(fr)
+            torch.cuda.synchronize()
         out.append((c.clone(), k.clone()))
         plan.close()
     _say(f"  {int(out[0][1].sum())} candidates")
-    assert torch.equal(out[0][1], out[1][1])
-    assert torch.equal(out[0][0], out[1][0])
+    for o in out[1:]:
+        assert torch.equal(out[0][1], o[1])
+        assert torch.equal(out[0][0], o[0])
 
 
-def test_random_cases_split_items(sst):
+@pytest.mark.parametrize("mode", [B.SST_TWO_PASS_AUTO, B.SST_TWO_PASS_ALWAYS])
+def test_random_cases_split_items(sst, mode):
     """The shape whose work items are one row half of a tile (12 x 2
     velocities per block; both boundary rows of an item lie outside it):
     seeded random problems against the oracle, with tile rows that end
     inside the frame, exact rounding ties and low thresholds that put
-    candidates on the row-half borders."""
+    candidates on the row-half borders; in the default mode (these problems
+    are small enough for one pass) and with two passes forced."""
     rng = np.random.default_rng(2025)
     marg = listed = 0
     for case in range(14):
@@ -346,11 +367,12 @@ def test_random_cases_split_items(sst):
         thr = float(rng.choice([-50.0, 1.0, 2.5]))
         cmin = int(rng.choice([0, max(1, n // 2)]))
         kmax = int(rng.choice([1, 5, 64]))
-        plan = sst.sst_plan_detect(n, h, w, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax, shape=2)
-        _say(f"case {case}: {f.name} vmax {vmax} thr {thr} cmin {cmin} kmax {kmax} "
+        with two_pass(mode):
+            plan = sst.sst_plan_detect(n, h, w, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax, shape=2)
+            cand, count = plan.run(_dev(f.frames))
+            torch.cuda.synchronize()
+        _say(f"case {case}: {f.name} vmax {vmax} thr {thr} cmin {cmin} kmax {kmax} two-pass mode {mode} "
              f"({'staged' if plan.staged else 'direct'})")
-        cand, count = plan.run(_dev(f.frames))
-        torch.cuda.synchronize()
         got = sst.candidates_to_numpy(cand)
         cnt = count.cpu().numpy()
         ref = oracle.detect(f.frames, f.t, f.t_ref, f.vx, f.vy, thr, cmin, kmax, keep_maps=True)
