@@ -925,7 +925,7 @@ __host__ __device__ constexpr int item_waves_per_eu(int sh, bool detect, bool de
 // `logical` of the problem A describes (Ap: where a callee reads A); lds is
 // the workgroup's LDS array (Lds<SH, DETECT>::total floats).
 // DEFER (first pass of a two-pass search of shape 2): no candidate search;
-// an item with a pixel above threshold is listed in A.redo for the second
+// an item with a pixel above threshold is marked in A.redo for the second
 // pass, which runs it again in full.
 template <bool DETECT, bool STAGED, int SH, bool HALF = false, bool DEFER = false>
 __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int logical, float* lds) {
@@ -973,8 +973,9 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
     int* const s_redo = reinterpret_cast<int*>(lds + Lds<SH, NBUF>::total - 4);
     if constexpr (DEFER) {
         // once more than 1 / kRedoSkip of the items dealt so far have found a
-        // pixel above threshold, list this one at once: where most items
-        // hold such a pixel, the first pass would only add to the second
+        // pixel above threshold, mark this one without running it: where
+        // most items hold such a pixel, the first pass would only add to the
+        // second
         int* const s_skip = s_redo + 1;
         if (tid == 0) {
             *s_redo = 0;
@@ -1433,8 +1434,9 @@ __device__ __forceinline__ void stack_item(const StackArgs& A, KArgs Ap, int log
         else
             epi(A.P);
         if constexpr (DEFER) {
-            // list the item for the second pass if a wave found a pixel above
-            // threshold
+            // mark the item for the second pass if a wave found a pixel above
+            // threshold (0 otherwise: every item of the grid is written);
+            // the count covers the items this pass ran
             __syncthreads();
             if (tid == 0) {
                 const int found = *s_redo;
