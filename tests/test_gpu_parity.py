@@ -322,13 +322,14 @@ def test_split_items_few_frames(sst, n):
 @pytest.mark.parametrize("thr", [1.0, 3.5, 6.0])
 def test_split_items_two_passes(sst, thr):
     """The float32 search of the row-half shape runs in two passes: the
-    first lists the work items that hold a pixel above threshold and, once
-    more than one in eight of an XCD's items have found such a pixel, lists the rest
-    without running them; the second runs the listed items in full. On a
-    field of 5,760 work items (enough for the early listing to start), at a
-    threshold that lists nearly every item, one that lists part of them and
-    one that lists few: the lists and counts of the one-pass whole-tile shape,
-    bit for bit."""
+    first marks the work items that hold a pixel above threshold and, once
+    more than one in eight of the items dealt so far have found such a
+    pixel, marks the rest without running them; the second runs the marked
+    items in full. On a field of 5,760 work items (enough for two passes by
+    default and for the early marking to start), at a threshold that marks
+    nearly every item, one that marks part of them and one that marks few:
+    two passes by default and forced, and one pass, against the one-pass
+    whole-tile shape, lists and counts bit for bit."""
     f = synth.small_case(1900, 8, 384, 640, 30, 16, vmax=3.0, sky=10.0, sigma=2.0)
     _say(f"case {f.name} thr {thr}")
     fr = _dev(f.frames)
