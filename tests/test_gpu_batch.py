@@ -17,6 +17,7 @@ import pytest
 import oracle
 import synth
 from parity import compare_velocity
+from paper_2303_07293_amd import binding as B
 
 pytestmark = pytest.mark.gpu
 
@@ -35,6 +36,13 @@ def sst():
 def _say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _two_pass_default():
+    """Every test leaves the two-pass mode at its default, also on failure."""
+    yield
+    B.sst_set_two_pass(B.SST_TWO_PASS_AUTO)
 
 
 FIELDS = [(50, 10, 70, 130, 7, 5, 3.0), (51, 16, 64, 64, 6, 4, 2.0), (52, 8, 33, 97, 5, 9, 6.0),
@@ -64,10 +72,18 @@ def test_plan_run_matches_detect(sst):
     plan.close()
 
 
+@pytest.mark.parametrize("mode", [B.SST_TWO_PASS_AUTO, B.SST_TWO_PASS_ALWAYS])
 @pytest.mark.parametrize("n_streams", [1, 3])
-def test_graph_capture_of_many_fields(sst, n_streams):
+def test_graph_capture_of_many_fields(sst, n_streams, mode):
+    """Every field's run captured into one graph (on one or three branches),
+    replayed three times with eager work between the replays; each replay
+    against eager one-pass runs. The runs take the two-pass mode in force
+    when they are enqueued: the default (one pass at these sizes) or two
+    passes forced, whose counters the graph clears with a kernel each
+    replay."""
     cases = [_case(s) for s in FIELDS]
-    _say(f"case graph of {len(cases)} fields on {n_streams} branches")
+    _say(f"case graph of {len(cases)} fields on {n_streams} branches, two-pass mode {mode}")
+    prev_mode = B.sst_set_two_pass(mode)
     plans = [sst.sst_plan_detect(f.n, f.h, f.w, f.t, f.t_ref, f.vx, f.vy, 2.5, 0, 8) for f in cases]
     frames = [torch.from_numpy(f.frames).to("cuda:0") for f in cases]
     outs = [(torch.empty((p.nk, 8, 8), dtype=torch.int32, device="cuda:0"),
@@ -104,10 +120,12 @@ def test_graph_capture_of_many_fields(sst, n_streams):
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
+        B.sst_set_two_pass(B.SST_TWO_PASS_NEVER)
         for k, (g, (c, n)) in enumerate(zip(new, outs)):
             ce, ne = sst.sst_detect(frames[k], g.t, g.t_ref, g.vx, g.vy, 2.5, 0, 8)
             torch.cuda.synchronize()
             assert torch.equal(c, ce) and torch.equal(n, ne), (rep, k)
+        B.sst_set_two_pass(mode)
         _say(f"  replay {rep}: {len(new)} fields match eager runs")
     # one field of the last replay against the oracle
     g = new[1]
@@ -119,6 +137,7 @@ def test_graph_capture_of_many_fields(sst, n_streams):
     marg = sum(compare_velocity(got[k], int(cnt[k]), ref[k], g.n, float(np.abs(b).max()), 2.5, ref["c_min"], 8, g.w)
                for k in ks)
     assert marg <= 4
+    B.sst_set_two_pass(prev_mode)
     for p in plans:
         p.close()
 
