@@ -53,6 +53,34 @@ def test_noalloc_matches_detect_twice_then_smaller(sst):
     assert n1 > 0 and n2 > 0
 
 
+def test_noalloc_two_passes_forced(sst):
+    """The same two calls with the two-pass search forced (its counters and
+    marks then live in the scratch too), against sst_detect in one pass."""
+    from paper_2303_07293_amd import binding as B
+
+    prev = B.sst_set_two_pass(B.SST_TWO_PASS_ALWAYS)
+    try:
+        for f, thr, kmax in ((synth.tiny_field(), None, None),
+                             (synth.small_case(7, 9, 70, 90, 5, 4, vmax=3.0, sky=20.0, sigma=3.0), 3.0, 8)):
+            thr = f.threshold if thr is None else thr
+            kmax = f.k_max if kmax is None else kmax
+            _say(f"case no-alloc two passes {f.name}")
+            fr = torch.from_numpy(f.frames).to("cuda:0")
+            nk = len(f.vx) * len(f.vy)
+            cand = torch.full((nk, kmax, 8), -7, dtype=torch.int32, device="cuda:0")
+            count = torch.full((nk,), -7, dtype=torch.int32, device="cuda:0")
+            sst.sst_detect_noalloc(fr, f.t, f.t_ref, f.vx, f.vy, thr, 0, kmax, cand, count)
+            torch.cuda.synchronize()
+            B.sst_set_two_pass(B.SST_TWO_PASS_NEVER)
+            c2, n2 = sst.sst_detect(fr, f.t, f.t_ref, f.vx, f.vy, thr, 0, kmax)
+            torch.cuda.synchronize()
+            B.sst_set_two_pass(B.SST_TWO_PASS_ALWAYS)
+            assert torch.equal(cand, c2) and torch.equal(count, n2)
+            assert int(count.sum().item()) > 0
+    finally:
+        B.sst_set_two_pass(prev)
+
+
 def test_noalloc_rejects_problems_larger_than_the_scratch(sst):
     f = synth.full_field(n_movers=0, h=64, w=64)  # the grid and frames only set the size below
     n, h, w = 64, 1024, 1024
