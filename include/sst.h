@@ -391,8 +391,10 @@ int sst_set_stack_shape(int shape, int* previous);
  * launches of at least 4096 work items, SST_TWO_PASS_NEVER never,
  * SST_TWO_PASS_ALWAYS for every launch.  Writes the previous setting to
  * *previous (if not NULL) and returns SST_OK, or SST_E_ARG (setting
- * unchanged) for another mode.  Every mode gives the same lists; the
- * setting exists to test and time each.  Batches run one pass. */
+ * unchanged) for another mode.  A run takes the mode in force when it is
+ * enqueued (a captured graph keeps the mode of its capture).  Every mode
+ * gives the same lists; the setting exists to test and time each.  The
+ * persistent batch (sst_batch_run) runs one pass. */
 #define SST_TWO_PASS_NEVER 0
 #define SST_TWO_PASS_AUTO 1
 #define SST_TWO_PASS_ALWAYS 2
